@@ -1,0 +1,251 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these retypes the oracle's formulas: each checks a property that a
+dropped term, a wrong sign or index, or a transposed operand would break.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from oracle import ttutv_oracle as O
+import ttgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+COMBOS = [("L2R", "ULV"), ("R2L", "URV"), ("L2R", "URV"), ("R2L", "ULV")]
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _rse(a, cores):
+    return np.linalg.norm(oracle.tt_reconstruct(cores) - a) / np.linalg.norm(a)
+
+
+# ---------------------------------------------------------------- generator
+def test_splitmix64_published_outputs():
+    want = [int(r[0]) for r in _read_golden("splitmix64_seed1234567.txt")]
+    got = [int(x) for x in oracle.splitmix64(1234567, np.arange(1, 6, dtype=np.uint64))]
+    assert got == want
+
+
+def test_sketch_gaussian_distribution_and_ordering():
+    g = oracle.sketch_gaussian(42, 3, 50, 40, 100, True)
+    x = g.ravel()
+    assert abs(x.mean()) < 5 / math.sqrt(x.size)
+    assert abs(x.var() - 1) < 5 * math.sqrt(2 / x.size)
+    assert stats.kstest(x, "norm").pvalue > 1e-4
+    # columns are uncorrelated
+    c = np.corrcoef(g[:, :20].T)
+    assert np.max(np.abs(c - np.eye(20))) < 6 / math.sqrt(g.shape[0])
+    # the (i, beta) -> row map only permutes rows
+    h = oracle.sketch_gaussian(42, 3, 50, 40, 100, False)
+    i, b = 7, 11
+    assert np.array_equal(g[i + 50 * b], h[b + 40 * i])
+    # different modes and seeds give different matrices
+    assert not np.allclose(g, oracle.sketch_gaussian(42, 4, 50, 40, 100, True))
+    assert not np.allclose(g, oracle.sketch_gaussian(43, 3, 50, 40, 100, True))
+    # extending ell keeps the leading columns
+    assert np.array_equal(g[:, :30], oracle.sketch_gaussian(42, 3, 50, 40, 30, True))
+
+
+# ---------------------------------------------------------------- Eq. (TT)
+def test_reconstruct_closed_form_sum():
+    """The rank-2 train [x1 1] [[1 0],[xk 1]] ... [1; xd] represents
+    f(i) = sum_k x_k[i_k] (a textbook TT construction)."""
+    rng = np.random.default_rng(0)
+    dims = [3, 4, 5, 2]
+    xs = [rng.standard_normal(I) for I in dims]
+    d = len(dims)
+    cores = []
+    for k, x in enumerate(xs):
+        if k == 0:
+            g = np.zeros((1, dims[k], 2)); g[0, :, 0] = x; g[0, :, 1] = 1
+        elif k == d - 1:
+            g = np.zeros((2, dims[k], 1)); g[0, :, 0] = 1; g[1, :, 0] = x
+        else:
+            g = np.zeros((2, dims[k], 2)); g[0, :, 0] = 1; g[1, :, 0] = x; g[1, :, 1] = 1
+        cores.append(g)
+    want = np.zeros(dims)
+    for k, x in enumerate(xs):
+        shape = [1] * d; shape[k] = dims[k]
+        want = want + x.reshape(shape)
+    got = oracle.tt_reconstruct(cores)
+    np.testing.assert_allclose(got, want.reshape(-1, order="F"), rtol=0, atol=1e-14)
+    # entry i1 + I1*i2 + ... is (i1, i2, ...): check one off-diagonal entry
+    i = (2, 1, 4, 1)
+    flat = i[0] + dims[0] * (i[1] + dims[1] * (i[2] + dims[2] * i[3]))
+    assert got[flat] == pytest.approx(sum(xs[k][i[k]] for k in range(d)), abs=1e-14)
+
+
+def test_sample_equals_reconstruct_entries():
+    dims = [4, 5, 3, 6]
+    cores = ttgen.gaussian_cores(dims, [1, 3, 2, 4, 1], 1)
+    full = oracle.tt_reconstruct(cores)
+    idx = ttgen.random_indices(dims, 200, 2)
+    flat = idx[:, 0] + dims[0] * (idx[:, 1] + dims[1] * (idx[:, 2] + dims[2] * idx[:, 3]))
+    np.testing.assert_allclose(oracle.tt_sample(cores, idx), full[flat], rtol=1e-13, atol=1e-13)
+
+
+def test_sample_grad_finite_differences():
+    dims = [3, 4, 2, 3]
+    cores = ttgen.gaussian_cores(dims, [1, 2, 3, 2, 1], 5)
+    idx = ttgen.random_indices(dims, 40, 6)
+    w = np.random.default_rng(7).standard_normal(40)
+    grads = oracle.tt_sample_grad(cores, idx, w)
+    h = 1e-6
+    for k, g in enumerate(cores):
+        fd = np.zeros_like(g)
+        for pos in np.ndindex(g.shape):
+            cp = [c.copy() for c in cores]; cp[k][pos] += h
+            cm = [c.copy() for c in cores]; cm[k][pos] -= h
+            fd[pos] = (w @ oracle.tt_sample(cp, idx) - w @ oracle.tt_sample(cm, idx)) / (2 * h)
+        np.testing.assert_allclose(grads[k], fd, rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- sweeps
+@pytest.mark.parametrize("sweep,variant", COMBOS + [("L2R", "SVD"), ("R2L", "SVD")])
+def test_exact_tt_rank_reconstructs(sweep, variant):
+    """Thm. 3.1/3.2 with eps_k = 0: a tensor of exact TT-ranks is recovered."""
+    dims = [5, 6, 7, 5]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 0.0, 11)
+    cores, rep = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep=sweep, variant=variant, q=1, p=4, seed=3)
+    assert _rse(a, cores) < 1e-12
+    assert rep["ranks"] == [1, 3, 4, 3, 1]
+
+
+@pytest.mark.parametrize("sweep,variant", [("L2R", "ULV"), ("R2L", "URV"), ("L2R", "URV")])
+def test_pythagoras_equality(sweep, variant):
+    """With carries equal to the exact projections (U1^T E = 0, resp. E V1 = 0)
+    the proof of Thm. 3.1 holds with equality: ||A - A_TT||^2 = sum delta_k^2."""
+    dims = [6, 7, 5, 6, 4]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 5, 5, 3], 1e-2, 21)
+    cores, rep = oracle.tt_utv(a, dims, ranks=[3, 4, 4, 3], sweep=sweep, variant=variant, q=1, p=3, seed=9)
+    err2 = np.sum((oracle.tt_reconstruct(cores) - a) ** 2)
+    bound2 = np.sum(np.square(rep["delta"]))
+    assert err2 > 0
+    assert abs(err2 - bound2) <= 1e-9 * bound2
+
+
+def test_alg4_sum_bound():
+    """Prop. A.1: the ULV right-to-left sweep obeys ||A - A_TT|| <= sum delta_k."""
+    dims = [6, 7, 5, 6, 4]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 5, 5, 3], 5e-2, 22)
+    for q in (0, 1):
+        cores, rep = oracle.tt_utv(a, dims, ranks=[3, 4, 4, 3], sweep="R2L", variant="ULV", q=q, p=2, seed=4)
+        err = np.linalg.norm(oracle.tt_reconstruct(cores) - a)
+        assert err <= np.sum(rep["delta"]) * (1 + 1e-12)
+        assert rep["err_bound"] == pytest.approx(np.sum(rep["delta"]))
+
+
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_core_orthogonality(sweep, variant):
+    """Def. 2.2: L2R cores 1..d-1 are left-orthogonal, R2L cores 2..d right-orthogonal."""
+    dims = [4, 6, 5, 7]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 1e-3, 31)
+    cores, _ = oracle.tt_utv(a, dims, ranks=[3, 3, 2], sweep=sweep, variant=variant, q=1, p=3, seed=1)
+    if sweep == "L2R":
+        for g in cores[:-1]:
+            G2 = g.reshape(g.shape[0] * g.shape[1], g.shape[2], order="F")
+            assert np.max(np.abs(G2.T @ G2 - np.eye(g.shape[2]))) < 1e-13
+    else:
+        for g in cores[1:]:
+            G1 = g.reshape(g.shape[0], g.shape[1] * g.shape[2], order="F")
+            assert np.max(np.abs(G1 @ G1.T - np.eye(g.shape[0]))) < 1e-13
+
+
+def test_matrix_case_is_eckart_young():
+    """d = 2 with ell >= n: the sweep is one truncated SVD, whose error is
+    sqrt(sum_{i>r} sigma_i^2) (LAPACK singular values as the library reference)."""
+    rng = np.random.default_rng(3)
+    U, _ = np.linalg.qr(rng.standard_normal((40, 30)))
+    V, _ = np.linalg.qr(rng.standard_normal((25, 25)))
+    s = 2.0 ** -np.arange(25)
+    M = (U[:, :25] * s) @ V.T                   # 40 x 25, known spectrum
+    a = M.reshape(-1, order="F")
+    sig = np.linalg.svd(M, compute_uv=False)
+    for sweep, variant in COMBOS + [("L2R", "SVD")]:
+        for r in (1, 4, 9):
+            cores, rep = oracle.tt_utv(a, [40, 25], ranks=[r], sweep=sweep, variant=variant, q=0, p=100, seed=0)
+            err = np.linalg.norm(oracle.tt_reconstruct(cores) - a)
+            assert err == pytest.approx(math.sqrt(np.sum(sig[r:] ** 2)), rel=1e-10)
+    # with ell < n, q power steps still find the optimum on a strongly graded spectrum
+    cores, _ = oracle.tt_utv(a, [40, 25], ranks=[4], sweep="R2L", variant="URV", q=2, p=4, seed=0)
+    err = np.linalg.norm(oracle.tt_reconstruct(cores) - a)
+    assert err == pytest.approx(math.sqrt(np.sum(sig[4:] ** 2)), rel=1e-6)
+
+
+@pytest.mark.parametrize("sweep,variant", [("L2R", "ULV"), ("R2L", "URV"), ("R2L", "ULV")])
+def test_full_sketch_equals_tt_svd(sweep, variant):
+    """ell = n at every step (G = I) makes the UTV step an exact factorisation,
+    so the cores equal TT-SVD's (distinct singular values, canonical signs)."""
+    dims = [5, 6, 4, 5]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 1e-2, 41)
+    c1, r1 = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep=sweep, variant=variant, q=0, p=1000, seed=0)
+    c2, r2 = oracle.tt_svd(a, dims, ranks=[3, 4, 3], sweep=sweep)
+    for g1, g2 in zip(c1, c2):
+        np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-10 * np.max(np.abs(g2)))
+    np.testing.assert_allclose(r1["delta"], r2["delta"], rtol=1e-8)
+
+
+def test_reversed_urv_equals_ulv_left_to_right():
+    """The index-reversal form of TT-URV (remark after Thm. 3.2) sees the same
+    core-side test matrix as TT-ULV, so both give the same left-orthogonal cores."""
+    dims = [6, 5, 7, 4]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 1e-4, 51)
+    c1, _ = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep="L2R", variant="ULV", q=1, p=3, seed=8)
+    c2, _ = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep="L2R", variant="URV", q=1, p=3, seed=8)
+    for g1, g2 in zip(c1, c2):
+        np.testing.assert_allclose(g1, g2, rtol=0, atol=1e-9 * np.max(np.abs(g2)))
+
+
+@pytest.mark.parametrize("sweep,variant", COMBOS + [("L2R", "SVD")])
+def test_prescribed_accuracy_meets_eps(sweep, variant):
+    """Alg. 2 guarantee: RSE <= eps, with ranks found adaptively."""
+    a = ttgen.inverse_sum_tensor(6, 8, dtype=np.float64)
+    dims = [8] * 6
+    for eps in (1e-2, 1e-4, 1e-6):
+        cores, rep = oracle.tt_utv(a, dims, eps=eps, sweep=sweep, variant=variant, q=1, p=4, seed=2)
+        assert rep["rank_rule_met"]
+        assert _rse(a, cores) <= eps * (1 + 1e-9)
+
+
+def test_prescribed_accuracy_recovers_generating_ranks():
+    dims = [6, 7, 6, 5, 6]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 5, 4, 3], 1e-8, 61)
+    for sweep, variant in COMBOS:
+        cores, rep = oracle.tt_utv(a, dims, eps=1e-5, sweep=sweep, variant=variant, q=1, p=4, seed=5)
+        assert rep["ranks"] == [1, 3, 5, 4, 3, 1], (sweep, variant)
+
+
+def test_rank_rule_reads_frobenius_energy():
+    """The rank rule is ||C||^2 - sum_{i<=r} s_i^2 <= eps_k^2, smallest r >= 1."""
+    s = np.array([3.0, 2.0, 1.0, 0.5])
+    n2 = float(np.sum(s * s))
+    assert O._pick_rank(s, n2, math.sqrt(1.25) + 1e-12, None) == (2, True)
+    assert O._pick_rank(s, n2, math.sqrt(1.25) - 1e-9, None) == (3, True)
+    assert O._pick_rank(s, n2, 100.0, None) == (1, True)
+    assert O._pick_rank(s, n2, 0.1, 2) == (2, False)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("TTUTV_SLOW") != "1",
+                    reason="5.2 GB tensor, ~15 min of LAPACK on 8 cores; set TTUTV_SLOW=1")
+def test_table_beps_ttsvd_ranks():
+    """Example 2 (160^4): the TT-SVD ranks printed in Table "Beps"."""
+    a = ttgen.sin_norm_tensor(4, 160)
+    for row in _read_golden("table_beps_ttsvd_ranks.txt"):
+        eps = float(row[0])
+        want = [1] + [int(x) for x in row[1:]] + [1]
+        _, rep = oracle.tt_svd(a, [160] * 4, eps=eps, sweep="L2R")
+        assert rep["ranks"] == want, (eps, rep["ranks"])
