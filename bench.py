@@ -1,0 +1,143 @@
+"""Benchmark of the TT-UTV sweep on one MI355X.
+
+One step = one full TT-URV decomposition (right-to-left sweep, Alg. 3) of the
+resident synthetic tensor: order 5, 32^5 FP64 (33.5M entries, 268 MB),
+contracted from Gaussian TT cores of ranks 16 plus Gaussian noise at 1e-6
+relative Frobenius norm, fixed rank 16, q = 2 power steps, oversampling 8.
+
+Prints one JSON line: GB/s of tensor swept (tensor bytes / step time), the
+roofline of the dominant kernel class (its launches timed with HIP events on
+the launch stream during the timed steps), and the FP64 oracle timed on the
+host cores for one decomposition of the same tensor.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TT-URV GB/s swept + roofline %, mixed vs FP64 GPU at 1e-6 rel. error"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+WORKLOADS = {
+    "order5_32_fp64": dict(
+        dims=[32] * 5, gen_ranks=[16] * 4, noise=1e-6, seed=0, ranks=[16] * 4, q=2, oversample=8,
+        sweep="R2L", variant="URV",
+        desc="order-5 32^5 FP64 (33.5M entries) Gaussian-TT ranks 16 + 1e-6 relative noise; "
+             "TT-URV right-to-left, fixed rank 16, q=2, p=8"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="order5_32_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_07904_amd as T
+    import ttgen
+
+    W = WORKLOADS[args.workload]
+    log(f"bench: generating {W['desc']}")
+    a, _ = ttgen.gaussian_tt_tensor(W["dims"], W["gen_ranks"], W["noise"], W["seed"])
+    A = torch.from_numpy(a).cuda()
+    tensor_bytes = A.numel() * A.element_size()
+    dec = T.Decomposer(W["dims"], A.dtype, ranks=W["ranks"], sweep=W["sweep"], variant=W["variant"], q=W["q"],
+                       oversample=W["oversample"], profile=True)
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        dec(A)
+    torch.cuda.synchronize()
+
+    kstat = {}
+    log(f"bench: timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dec(A)  # fixed ranks: the call synchronises once at the end to fill its report
+        for name, v in dec.report()["kstat"].items():
+            acc = kstat.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0})
+            for key in acc:
+                acc[key] += v[key]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = tensor_bytes / (ms_per_step * 1e-3) / 1e9
+    rep = dec.report()
+    cores = dec.cores()
+    rec = T.tt_reconstruct(cores)
+    rse = float(torch.linalg.norm(rec - A) / torch.linalg.norm(A))
+    log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} GB/s swept, ranks {rep['ranks']}, RSE {rse:.3e}")
+
+    # dominant kernel class: largest summed launch time in the timed steps
+    dom_name, dom = max(kstat.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per = dom["bytes"] / dom["launches"]
+    flops_per = dom["flops"] / dom["launches"]
+    intensity = flops_per / bytes_per if bytes_per else 0.0
+    ridge = FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS   # flop per byte where HBM and FP64 peaks meet
+    if intensity < ridge:
+        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        achieved = flops_per / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof["kernel"] = dom_name
+    roof["launches_per_step"] = dom["launches"] / args.steps
+    roof["avg_launch_ms"] = round(avg_ms, 5)
+    roof["alg_bytes_per_launch"] = bytes_per
+    for name, v in sorted(kstat.items(), key=lambda kv: -kv[1]["ms"]):
+        if v["launches"]:
+            log(f"bench: kernel {name:9s} launches/step {v['launches'] / args.steps:5.1f} "
+                f"ms/step {v['ms'] / args.steps:.4f}  GB/s {v['bytes'] / (v['ms'] * 1e-3) / 1e9:8.1f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores_used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        except Exception:  # threadpoolctl missing: numpy's BLAS default is all cores
+            cores_used = os.cpu_count()
+        log("bench: timing the FP64 oracle on the host (one decomposition of the same tensor)")
+        c0 = time.perf_counter()
+        oracle.tt_utv(a, W["dims"], ranks=W["ranks"], sweep=W["sweep"], variant=W["variant"], q=W["q"],
+                      p=W["oversample"], seed=0)
+        c1 = time.perf_counter()
+        cpu = {"value": round(tensor_bytes / (c1 - c0) / 1e9, 5), "unit": "GB/s", "cores": cores_used,
+               "kind": "oracle", "sample": "one full decomposition of the same 32^5 FP64 tensor "
+                                           f"({c1 - c0:.1f} s)"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["desc"], "ranks": rep["ranks"], "rse": rse},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

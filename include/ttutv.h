@@ -1,0 +1,166 @@
+/*
+ * ttutv.h -- C ABI of the TT-UTV library for AMD Instinct MI355X (gfx950).
+ *
+ * TT-UTV (Wang, Che & Wei, "Effective algorithms for tensor-train
+ * decomposition via the UTV framework") computes a tensor train by a sweep of
+ * truncated rank-revealing UTV factorisations of the unfoldings, in place of
+ * the SVDs of TT-SVD.  The inner factorisation here is a randomized
+ * power-iteration UTV: a Gaussian test matrix on the core side of the
+ * unfolding, q power steps, a Rayleigh-Ritz step on the ell-dimensional
+ * subspace it spans, and truncation at a fixed rank or at the rank rule that
+ * follows Alg. 2.
+ *
+ * Conventions shared by every entry point
+ *  - Tensors are flat in reverse lexicographic order (the paper's `ivec`:
+ *    i1 fastest, Sec. 2.1).  A C-contiguous array of shape (I_d, ..., I_1) has
+ *    this layout.
+ *  - TT core k (1-based) has shape r_{k-1} x I_k x r_k and is stored
+ *    column-major: element (a, i, b) at a + r_{k-1} * (i + I_k * b)
+ *    (the core of Eq. (TT), reshaped as MATLAB's reshape does).
+ *  - ranks arrays hold r_0..r_d (d+1 entries, r_0 = r_d = 1).
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer.  The
+ *    library never allocates or frees device memory; it enqueues work on the
+ *    given HIP stream (NULL = default stream).
+ *  - Every function returns TT_OK (0) or a negative status; on error
+ *    tt_last_error() returns a message (thread-local, valid until the next
+ *    call from the same thread).  Argument errors are detected on the host
+ *    before any work is enqueued.
+ */
+#ifndef TTUTV_H
+#define TTUTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_OK 0
+#define TT_EINVAL (-1)        /* bad argument: dims, ranks, enum value, null pointer */
+#define TT_ENOSPC (-2)        /* workspace smaller than tt_utv_workspace reported */
+#define TT_ERANK (-3)         /* eps not reachable within max_rank; cores and report still written */
+#define TT_ENONFINITE (-4)    /* input holds NaN or Inf (detected from ||A||_F) */
+#define TT_EHIP (-5)          /* a HIP runtime call failed */
+#define TT_EUNSUPPORTED (-6)  /* valid request outside this build's limits (e.g. ell > 64) */
+
+#define TT_MAX_D 32           /* largest tensor order */
+#define TT_MAX_ELL 64         /* largest sketch width ell (and therefore rank) */
+
+typedef enum { TT_L2R = 0, TT_R2L = 1 } tt_sweep;
+/* TT_ULV + TT_L2R: Alg. 1 (fixed ranks) / Alg. 2 (prescribed accuracy).
+ * TT_URV + TT_R2L: Alg. 3 and its prescribed-accuracy form (Sec. 3.2).
+ * TT_URV + TT_L2R: the index-reversal form (remark after Thm. 3.2).
+ * TT_ULV + TT_R2L: Alg. 4 (appendix), carry U^ L11 without the U2 L21 term.
+ * TT_SVD: exact truncated SVD of every unfolding (TT-SVD), the ell = n case. */
+typedef enum { TT_ULV = 0, TT_URV = 1, TT_SVD = 2 } tt_variant;
+typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
+
+typedef struct {
+  int32_t q;                /* power steps (>= 0) */
+  int32_t oversample;       /* p: ell = min(r + p, n, m) */
+  uint64_t seed;            /* seed of the Gaussian test matrices */
+  int32_t max_rank;         /* eps mode: rank cap per step (0 = TT_MAX_ELL) */
+  int32_t exact_delta;      /* 1: measure every step error ||C - C_r||_F by an extra
+                               pass over C; 0: from ||C||^2 - ||carry||^2 */
+  const double* weights;    /* host, d-1 entries with sum w_k^2 = 1, or NULL for the
+                               default (1/sqrt(d-1); 1/(d-1) for Alg. 4) */
+  int32_t profile;          /* 1: time every kernel launch with HIP events on the
+                               caller's stream and fill tt_report.kstat */
+} tt_opts;
+
+/* Kernel classes of the profile (tt_kernel_class_name gives their names). */
+#define TT_NKCLASS 7
+typedef struct {
+  int64_t launches;
+  double ms;        /* summed launch durations (HIP events around each launch) */
+  double bytes;     /* algorithmic bytes: operands read once + results written */
+  double flops;     /* algorithmic floating-point operations */
+} tt_kstat;
+
+typedef struct {
+  int64_t ranks[TT_MAX_D + 1];  /* r_0..r_d actually used */
+  int64_t ell[TT_MAX_D];        /* sketch width of unfolding k (index k-1) */
+  double delta[TT_MAX_D];       /* step error of unfolding k: ||C - truncated||_F */
+  double normC[TT_MAX_D];       /* ||C||_F of the matrix factorised for unfolding k */
+  double norm_A;                /* ||A||_F */
+  double err_bound;             /* sqrt(sum delta^2) (Cor. 3.1 / Thm. 3.2), or
+                                   sum delta for Alg. 4 (Prop. A.1) */
+  int32_t rank_rule_met;        /* eps mode: 1 if every step met its tolerance */
+  int32_t d;
+  tt_kstat kstat[TT_NKCLASS];   /* filled when opts.profile = 1 */
+} tt_report;
+
+/* Name of kernel class c (0 <= c < TT_NKCLASS), or NULL. */
+const char* tt_kernel_class_name(int c);
+
+/* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
+ * exact_delta = 0, weights = NULL, profile = 0. */
+void tt_default_opts(tt_opts* opts);
+
+/* Device bytes of workspace tt_utv_decompose needs for this problem.
+ * ranks (host, d+1) for fixed ranks, or NULL with eps >= 0 for prescribed
+ * accuracy (then the bound assumes every rank reaches its cap). */
+int tt_utv_workspace(int d, const int64_t* dims, const int64_t* ranks, double eps,
+                     tt_sweep sweep, tt_variant variant, tt_dtype dtype,
+                     const tt_opts* opts, size_t* bytes);
+
+/* Largest number of doubles core k (0-based) can need: max r_{k-1} * I_k * r_k
+ * over the ranks this problem may produce (exact for fixed ranks). */
+int tt_utv_core_capacity(int d, const int64_t* dims, const int64_t* ranks, double eps,
+                         const tt_opts* opts, int64_t* capacity /* host, d entries */);
+
+/* TT-UTV decomposition (Alg. 1-4 and the prescribed-accuracy forms).
+ *  A          device, prod(dims) elements of `dtype`, ivec order; not modified.
+ *  dims       host, d extents (each >= 1), 2 <= d <= TT_MAX_D.
+ *  ranks      host, r_0..r_d for fixed ranks (clamped to what each unfolding
+ *             allows, as the theorems allow ranks "not higher than" r_k), or
+ *             NULL for prescribed accuracy eps (relative: ||A - A_TT||_F <=
+ *             eps ||A||_F, eps_k = w_k eps ||A||_F per step).
+ *  work       device workspace of at least tt_utv_workspace bytes.
+ *  cores      host array of d device pointers; core k receives r_{k-1} I_k r_k
+ *             doubles (see tt_utv_core_capacity), layout above.
+ *  rep        host, filled on TT_OK and TT_ERANK (may be NULL).
+ *  stream     hipStream_t or NULL.
+ * With fixed ranks the call only enqueues work and synchronises the stream
+ * once at the end to fill the report; with eps it synchronises after every
+ * step to size the next one. */
+int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
+                     const int64_t* ranks, double eps, tt_sweep sweep, tt_variant variant,
+                     const tt_opts* opts, void* work, size_t work_bytes,
+                     double* const* cores, tt_report* rep, void* stream);
+
+/* Device bytes of workspace tt_reconstruct needs for this train. */
+int tt_reconstruct_workspace(int d, const int64_t* dims, const int64_t* ranks, size_t* bytes);
+
+/* Full tensor from TT cores, Eq. (TT).  cores: host array of d device
+ * pointers (FP64, layout above); ranks r_0..r_d with every r_k <= 64; out:
+ * device, prod(dims) elements of `dtype` in ivec order; work: device
+ * workspace of tt_reconstruct_workspace bytes (the two partial products of
+ * the train, split near the middle so that out = L R is one GEMM).
+ * Enqueues only. */
+int tt_reconstruct(int d, const int64_t* dims, const int64_t* ranks,
+                   const double* const* cores, void* out, tt_dtype dtype,
+                   void* work, size_t work_bytes, void* stream);
+
+/* Entries of the train at N multi-indices, Eq. (TT).  idx: device, N x d
+ * int64 row-major, 0-based, each i_k < I_k (not checked on the device: the
+ * caller guarantees it); out: device, N doubles.  Enqueues only. */
+int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+              const int64_t* idx, int64_t N, double* out, void* stream);
+
+/* Gradient of L = sum_s gout[s] * A_TT[idx_s] with respect to every core:
+ * gcores[k] (device, same layout and size as core k) is overwritten with
+ * dL/dG_k.  The left and right interface products of each sample are
+ * recomputed, not stored.  Enqueues only. */
+int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks,
+                       const double* const* cores, const int64_t* idx, int64_t N,
+                       const double* gout, double* const* gcores, void* stream);
+
+const char* tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTUTV_H */

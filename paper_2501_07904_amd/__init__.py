@@ -1,0 +1,330 @@
+"""TT-UTV on AMD MI355X: thin Python binding of libttutv.so.
+
+Only argument marshalling happens here: every step of the decomposition,
+reconstruction, sampling and sampled-entry backward runs in the HIP kernels
+of libttutv.so.  PyTorch provides device memory and the current stream.  The
+library must be built first (python -m paper_2501_07904_amd.build); importing
+the binding without it raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libttutv.so")
+
+TT_OK, TT_EINVAL, TT_ENOSPC, TT_ERANK, TT_ENONFINITE, TT_EHIP, TT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+TT_MAX_D = 32
+TT_MAX_ELL = 64
+SWEEPS = {"L2R": 0, "R2L": 1}
+VARIANTS = {"ULV": 0, "URV": 1, "SVD": 2}
+DTYPES = {torch.float64: 0, torch.float32: 1}
+EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose",
+           "tt_reconstruct_workspace", "tt_reconstruct", "tt_sample", "tt_sample_backward",
+           "tt_last_error", "tt_kernel_class_name"]
+
+
+class TTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libttutv error {code}: {msg}")
+        self.code = code
+
+
+class tt_opts(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("max_rank", ctypes.c_int32), ("exact_delta", ctypes.c_int32),
+                ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32)]
+
+
+TT_NKCLASS = 7
+
+
+class tt_kstat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+class tt_report(ctypes.Structure):
+    _fields_ = [("ranks", ctypes.c_int64 * (TT_MAX_D + 1)), ("ell", ctypes.c_int64 * TT_MAX_D),
+                ("delta", ctypes.c_double * TT_MAX_D), ("normC", ctypes.c_double * TT_MAX_D),
+                ("norm_A", ctypes.c_double), ("err_bound", ctypes.c_double),
+                ("rank_rule_met", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("kstat", tt_kstat * TT_NKCLASS)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libttutv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2501_07904_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    lib.tt_default_opts.argtypes = [ctypes.POINTER(tt_opts)]
+    lib.tt_default_opts.restype = None
+    lib.tt_last_error.restype = ctypes.c_char_p
+    lib.tt_kernel_class_name.argtypes = [ctypes.c_int]
+    lib.tt_kernel_class_name.restype = ctypes.c_char_p
+    lib.tt_utv_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.POINTER(tt_opts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.tt_utv_core_capacity.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_double, ctypes.POINTER(tt_opts), i64p]
+    lib.tt_utv_decompose.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64p, i64p, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.POINTER(tt_opts), vp, ctypes.c_size_t,
+                                     ctypes.POINTER(vp), ctypes.POINTER(tt_report), vp]
+    lib.tt_reconstruct_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(ctypes.c_size_t)]
+    lib.tt_reconstruct.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int, vp,
+                                   ctypes.c_size_t, vp]
+    lib.tt_sample.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp, vp]
+    lib.tt_sample_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp,
+                                       ctypes.POINTER(vp), vp]
+    for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_reconstruct_workspace",
+                 "tt_reconstruct", "tt_sample", "tt_sample_backward"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow=()):
+    if rc != TT_OK and rc not in allow:
+        raise TTError(rc, load_library().tt_last_error().decode())
+    return rc
+
+
+def _i64(vals):
+    arr = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _ptrs(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _full_ranks(ranks, d):
+    r = [int(x) for x in ranks]
+    if len(r) == d - 1:
+        r = [1] + r + [1]
+    if len(r) != d + 1:
+        raise ValueError("ranks must be r_0..r_d or r_1..r_{d-1}")
+    return r
+
+
+def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False):
+    o = tt_opts()
+    load_library().tt_default_opts(ctypes.byref(o))
+    o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
+    o.profile = int(bool(profile))
+    keep = None
+    if weights is not None:
+        keep = (ctypes.c_double * len(weights))(*[float(w) for w in weights])
+        o.weights = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    return o, keep
+
+
+def _core_view(flat, r0, I, r1):
+    """Logical (r_{k-1}, I_k, r_k) view of a column-major core buffer."""
+    return flat[: r0 * I * r1].view(r1, I, r0).permute(2, 1, 0)
+
+
+def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dtype=torch.float64, **kw):
+    lib = load_library()
+    d = len(dims)
+    o, _keep = make_opts(**kw)
+    nbytes = ctypes.c_size_t(0)
+    rk = None if ranks is None else _i64(_full_ranks(ranks, d))
+    _check(lib.tt_utv_workspace(d, _i64(dims), rk, -1.0 if eps is None else float(eps), SWEEPS[sweep],
+                                VARIANTS[variant], DTYPES[dtype], ctypes.byref(o), ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
+                     max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
+                     profile=False):
+    """TT-UTV of the device tensor A (float64/float32, flat in ivec order, i1
+    fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
+    float64 view of a column-major device buffer."""
+    lib = load_library()
+    if not (A.is_cuda and A.is_contiguous()):
+        raise ValueError("A must be a contiguous device tensor")
+    if A.dtype not in DTYPES:
+        raise ValueError("A must be float64 or float32")
+    dims = [int(x) for x in dims]
+    d = len(dims)
+    if (ranks is None) == (eps is None):
+        raise ValueError("give exactly one of ranks and eps")
+    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile)
+    rk = None if ranks is None else _i64(_full_ranks(ranks, d))
+    epsv = -1.0 if eps is None else float(eps)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.tt_utv_workspace(d, _i64(dims), rk, epsv, SWEEPS[sweep], VARIANTS[variant], DTYPES[A.dtype],
+                                ctypes.byref(o), ctypes.byref(nbytes)))
+    if work is None or work.numel() < nbytes.value:
+        work = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=A.device)
+    cap = (ctypes.c_int64 * d)()
+    _check(lib.tt_utv_core_capacity(d, _i64(dims), rk, epsv, ctypes.byref(o), cap))
+    flats = [torch.empty(max(int(c), 1), dtype=torch.float64, device=A.device) for c in cap]
+    rep = tt_report()
+    rc = lib.tt_utv_decompose(ctypes.c_void_p(A.data_ptr()), DTYPES[A.dtype], d, _i64(dims), rk, epsv,
+                              SWEEPS[sweep], VARIANTS[variant], ctypes.byref(o), ctypes.c_void_p(work.data_ptr()),
+                              nbytes.value, _ptrs(flats), ctypes.byref(rep), _stream(stream))
+    _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
+    r = [int(rep.ranks[k]) for k in range(d + 1)]
+    cores = [_core_view(flats[k], r[k], dims[k], r[k + 1]) for k in range(d)]
+    report = {
+        "ranks": r, "ell": [int(rep.ell[k]) for k in range(d - 1)],
+        "delta": [float(rep.delta[k]) for k in range(d - 1)],
+        "normC": [float(rep.normC[k]) for k in range(d - 1)],
+        "norm_A": float(rep.norm_A), "err_bound": float(rep.err_bound),
+        "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
+    }
+    if profile:
+        report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
+            "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),
+            "bytes": float(rep.kstat[c].bytes), "flops": float(rep.kstat[c].flops)} for c in range(TT_NKCLASS)}
+    return cores, report
+
+
+def _core_buffers(cores):
+    """Column-major flat buffers of logical (r0, I, r1) cores."""
+    out = []
+    for g in cores:
+        flat = g.permute(2, 1, 0).contiguous().reshape(-1)
+        out.append(flat if flat.dtype == torch.float64 else flat.double())
+    return out
+
+
+def _train_shape(cores):
+    dims = [int(g.shape[1]) for g in cores]
+    ranks = [int(cores[0].shape[0])] + [int(g.shape[2]) for g in cores]
+    return dims, ranks
+
+
+def tt_reconstruct(cores, dtype=torch.float64, stream=None):
+    """Dense tensor (flat, ivec order) of a train of (r0, I, r1) device cores."""
+    lib = load_library()
+    dims, ranks = _train_shape(cores)
+    d = len(dims)
+    bufs = _core_buffers(cores)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.tt_reconstruct_workspace(d, _i64(dims), _i64(ranks), ctypes.byref(nbytes)))
+    dev = cores[0].device
+    work = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+    total = 1
+    for I in dims:
+        total *= I
+    out = torch.empty(total, dtype=dtype, device=dev)
+    _check(lib.tt_reconstruct(d, _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(out.data_ptr()),
+                              DTYPES[dtype], ctypes.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+    return out
+
+
+def tt_sample(cores, idx, stream=None):
+    """Train entries at the rows of idx (N x d int64, 0-based, on the device)."""
+    lib = load_library()
+    dims, ranks = _train_shape(cores)
+    idx = idx.contiguous().to(torch.int64)
+    N = idx.shape[0]
+    bufs = _core_buffers(cores)
+    out = torch.empty(N, dtype=torch.float64, device=cores[0].device)
+    _check(lib.tt_sample(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()), N,
+                         ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def tt_sample_backward(cores, idx, gout, stream=None):
+    """Core gradients of sum_s gout[s] * A_TT[idx_s]; list of (r0, I, r1) tensors."""
+    lib = load_library()
+    dims, ranks = _train_shape(cores)
+    idx = idx.contiguous().to(torch.int64)
+    gout = gout.contiguous().to(torch.float64)
+    N = idx.shape[0]
+    bufs = _core_buffers(cores)
+    gflat = [torch.empty_like(b) for b in bufs]
+    _check(lib.tt_sample_backward(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()),
+                                  N, ctypes.c_void_p(gout.data_ptr()), _ptrs(gflat), _stream(stream)))
+    return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
+
+
+class TTSample(torch.autograd.Function):
+    """Sampled entries of a train as a differentiable function of its cores;
+    the backward is the hand-written tt_sample_backward kernel."""
+
+    @staticmethod
+    def forward(ctx, idx, *cores):
+        ctx.save_for_backward(idx, *cores)
+        return tt_sample(list(cores), idx)
+
+    @staticmethod
+    def backward(ctx, gout):
+        idx, *cores = ctx.saved_tensors
+        grads = tt_sample_backward(list(cores), idx, gout)
+        return (None, *[g.to(c.dtype) for g, c in zip(grads, cores)])
+
+
+class Decomposer:
+    """A planned TT-UTV decomposition for a fixed problem shape: workspace,
+    core buffers and argument structs are allocated once; each call only runs
+    tt_utv_decompose on the given device tensor (same shape and dtype)."""
+
+    def __init__(self, dims, dtype=torch.float64, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
+                 oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
+                 device="cuda"):
+        lib = load_library()
+        self.lib = lib
+        self.dims = [int(x) for x in dims]
+        self.d = d = len(self.dims)
+        if (ranks is None) == (eps is None):
+            raise ValueError("give exactly one of ranks and eps")
+        self.dtype = dtype
+        self.profile = profile
+        self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile)
+        self._dims = _i64(self.dims)
+        self._ranks = None if ranks is None else _i64(_full_ranks(ranks, d))
+        self.eps = -1.0 if eps is None else float(eps)
+        self.sweep, self.variant = SWEEPS[sweep], VARIANTS[variant]
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.tt_utv_workspace(d, self._dims, self._ranks, self.eps, self.sweep, self.variant, DTYPES[dtype],
+                                    ctypes.byref(self.opts), ctypes.byref(nbytes)))
+        self.work_bytes = nbytes.value
+        self.work = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=device)
+        cap = (ctypes.c_int64 * d)()
+        _check(lib.tt_utv_core_capacity(d, self._dims, self._ranks, self.eps, ctypes.byref(self.opts), cap))
+        self.flats = [torch.empty(max(int(c), 1), dtype=torch.float64, device=device) for c in cap]
+        self._cores = _ptrs(self.flats)
+        self.rep = tt_report()
+
+    def __call__(self, A, stream=None, allow_rank_miss=False):
+        if A.dtype != self.dtype or not A.is_contiguous():
+            raise ValueError("A must be contiguous with the planned dtype")
+        rc = self.lib.tt_utv_decompose(ctypes.c_void_p(A.data_ptr()), DTYPES[self.dtype], self.d, self._dims,
+                                       self._ranks, self.eps, self.sweep, self.variant, ctypes.byref(self.opts),
+                                       ctypes.c_void_p(self.work.data_ptr()), self.work_bytes, self._cores,
+                                       ctypes.byref(self.rep), _stream(stream))
+        _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
+        return rc
+
+    def cores(self):
+        r = [int(self.rep.ranks[k]) for k in range(self.d + 1)]
+        return [_core_view(self.flats[k], r[k], self.dims[k], r[k + 1]) for k in range(self.d)]
+
+    def report(self):
+        rep, d = self.rep, self.d
+        out = {"ranks": [int(rep.ranks[k]) for k in range(d + 1)], "ell": [int(rep.ell[k]) for k in range(d - 1)],
+               "delta": [float(rep.delta[k]) for k in range(d - 1)],
+               "normC": [float(rep.normC[k]) for k in range(d - 1)], "norm_A": float(rep.norm_A),
+               "err_bound": float(rep.err_bound), "rank_rule_met": bool(rep.rank_rule_met)}
+        if self.profile:
+            out["kstat"] = {self.lib.tt_kernel_class_name(c).decode(): {
+                "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),
+                "bytes": float(rep.kstat[c].bytes), "flops": float(rep.kstat[c].flops)} for c in range(TT_NKCLASS)}
+        return out

@@ -1,0 +1,692 @@
+// Host side of libttutv: argument checks, the per-step plan of the sweep,
+// the kernel sequence of every truncated UTV step, and the C ABI.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/ttutv.h"
+#include "tt_internal.h"
+
+using namespace ttutv;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_OK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(TT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+// ---- optional per-launch timing with HIP events on the caller's stream ----
+enum KClass { KC_ATB = 0, KC_AX = 1, KC_GRAM_Y = 2, KC_CARRY = 3, KC_RESID = 4, KC_REDUCE = 5, KC_SMALL = 6 };
+const char* const kClassNames[TT_NKCLASS] = {"tall_atb", "tall_ax", "gram_y", "carry", "resid", "reduce", "small"};
+
+thread_local std::vector<hipEvent_t> g_events;
+
+struct Prof {
+  bool on = false;
+  hipStream_t st = nullptr;
+  size_t next = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Rec> recs;
+  hipError_t event(hipEvent_t* e) {
+    if (next == g_events.size()) {
+      hipEvent_t x;
+      hipError_t rc = hipEventCreate(&x);
+      if (rc != hipSuccess) return rc;
+      g_events.push_back(x);
+    }
+    *e = g_events[next++];
+    return hipSuccess;
+  }
+};
+
+#define LAUNCH(P, cls, nbytes, nflops, expr)                                        \
+  do {                                                                             \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                       \
+    if ((P).on) {                                                                  \
+      HIP_OK((P).event(&ea_));                                                     \
+      HIP_OK(hipEventRecord(ea_, (P).st));                                         \
+    }                                                                              \
+    HIP_OK(expr);                                                                  \
+    if ((P).on) {                                                                  \
+      HIP_OK((P).event(&eb_));                                                     \
+      HIP_OK(hipEventRecord(eb_, (P).st));                                         \
+      (P).recs.push_back({(cls), ea_, eb_, (double)(nbytes), (double)(nflops)});  \
+    }                                                                              \
+  } while (0)
+
+// One truncated UTV step of the sweep, in the tall frame: the m x n matrix A
+// whose n columns are the core side.
+struct Step {
+  int core;        // 1-based index of the core this step produces
+  int unfolding;   // 1-based index k of the unfolding A_k it factorises
+  int64_t m;       // long side
+  int n;           // core side: r_{k-1} I_k (L2R) or I_k r_k (R2L)
+  int layout;      // ROW (L2R) or COL (R2L)
+  int n_mode, n_rank, mode_fastest;
+  int r;           // fixed rank (clamped) or the cap in eps mode
+  int ell;
+  bool gram;       // n <= kGramMax: A^T A formed in one pass
+};
+
+struct Problem {
+  int d;
+  int64_t dims[TT_MAX_D];
+  bool fixed;
+  int64_t ranks[TT_MAX_D + 1];  // fixed: given ranks; eps: caps
+  double eps;
+  tt_sweep sweep;
+  tt_variant variant;
+  tt_dtype dtype;
+  tt_opts o;
+  double w[TT_MAX_D];
+  bool alg4;
+};
+
+int64_t prod(const int64_t* v, int a, int b) {  // v[a] * ... * v[b-1]
+  int64_t p = 1;
+  for (int i = a; i < b; ++i) p *= v[i];
+  return p;
+}
+
+int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_sweep sweep,
+               tt_variant variant, tt_dtype dtype, const tt_opts* opts, Problem& P) {
+  if (d < 2 || d > TT_MAX_D) return fail(TT_EINVAL, "d = %d outside [2, %d]", d, TT_MAX_D);
+  if (!dims) return fail(TT_EINVAL, "dims is NULL");
+  if (sweep != TT_L2R && sweep != TT_R2L) return fail(TT_EINVAL, "bad sweep %d", (int)sweep);
+  if (variant != TT_ULV && variant != TT_URV && variant != TT_SVD)
+    return fail(TT_EINVAL, "bad variant %d", (int)variant);
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "bad dtype %d", (int)dtype);
+  P.d = d;
+  for (int k = 0; k < d; ++k) {
+    if (dims[k] < 1 || dims[k] >= (1 << 16))
+      return fail(TT_EINVAL, "dims[%d] = %lld outside [1, 65535]", k, (long long)dims[k]);
+    P.dims[k] = dims[k];
+  }
+  if (opts) P.o = *opts; else tt_default_opts(&P.o);
+  if (P.o.q < 0 || P.o.q > 64) return fail(TT_EINVAL, "q = %d outside [0, 64]", P.o.q);
+  if (P.o.oversample < 0 || P.o.oversample > TT_MAX_ELL)
+    return fail(TT_EINVAL, "oversample = %d outside [0, %d]", P.o.oversample, TT_MAX_ELL);
+  if (P.o.max_rank < 0) return fail(TT_EINVAL, "max_rank < 0");
+  P.sweep = sweep;
+  P.variant = variant;
+  P.dtype = dtype;
+  P.alg4 = (sweep == TT_R2L && variant == TT_ULV);
+  P.fixed = ranks != nullptr;
+  if (P.fixed) {
+    if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "ranks must have r_0 = r_d = 1");
+    for (int k = 0; k <= d; ++k) {
+      if (ranks[k] < 1) return fail(TT_EINVAL, "ranks[%d] = %lld < 1", k, (long long)ranks[k]);
+      P.ranks[k] = ranks[k];
+    }
+    P.eps = 0.0;
+  } else {
+    if (!(eps >= 0.0) || !isfinite(eps)) return fail(TT_EINVAL, "eps must be finite and >= 0");
+    P.eps = eps;
+    const int cap = P.o.max_rank > 0 ? std::min(P.o.max_rank, TT_MAX_ELL) : TT_MAX_ELL;
+    for (int k = 0; k <= d; ++k) P.ranks[k] = (k == 0 || k == d) ? 1 : cap;
+    double sw = 0.0;
+    for (int k = 0; k < d - 1; ++k) {
+      double wk;
+      if (P.o.weights) {
+        wk = P.o.weights[k];
+        if (!(wk >= 0.0) || !isfinite(wk)) return fail(TT_EINVAL, "weights[%d] invalid", k);
+      } else {
+        wk = P.alg4 ? 1.0 / (d - 1) : 1.0 / sqrt((double)(d - 1));
+      }
+      P.w[k] = wk;
+      sw += wk * wk;
+    }
+    if (P.o.weights && fabs(sw - 1.0) > 1e-9) return fail(TT_EINVAL, "sum of squared weights is %g, not 1", sw);
+  }
+  return TT_OK;
+}
+
+// Shapes of every step.  For eps mode the ranks are the caps, so the shapes
+// are upper bounds used to size buffers; run-time shapes are re-derived.
+int plan_steps(const Problem& P, const int64_t* rk /* r_0..r_d to assume */, std::vector<Step>& S,
+               int64_t* used_ranks) {
+  const int d = P.d;
+  S.clear();
+  int64_t r[TT_MAX_D + 1];
+  for (int k = 0; k <= d; ++k) r[k] = rk[k];
+  if (P.sweep == TT_L2R) {
+    r[0] = 1;
+    for (int k = 1; k <= d - 1; ++k) {
+      Step s{};
+      s.core = k;
+      s.unfolding = k;
+      const int64_t n = r[k - 1] * P.dims[k - 1];
+      const int64_t m = prod(P.dims, k, d);
+      s.m = m;
+      s.n = (int)n;
+      s.layout = ROW;
+      s.n_mode = (int)P.dims[k - 1];
+      s.n_rank = (int)r[k - 1];
+      s.mode_fastest = 0;
+      int64_t rr = std::min<int64_t>(r[k], std::min<int64_t>(n, m));
+      s.r = (int)rr;
+      r[k] = rr;
+      S.push_back(s);
+    }
+  } else {
+    r[d] = 1;
+    for (int k = d; k >= 2; --k) {
+      Step s{};
+      s.core = k;
+      s.unfolding = k - 1;
+      const int64_t n = P.dims[k - 1] * r[k];
+      const int64_t m = prod(P.dims, 0, k - 1);
+      s.m = m;
+      s.n = (int)n;
+      s.layout = COL;
+      s.n_mode = (int)P.dims[k - 1];
+      s.n_rank = (int)r[k];
+      s.mode_fastest = 1;
+      int64_t rr = std::min<int64_t>(r[k - 1], std::min<int64_t>(n, m));
+      s.r = (int)rr;
+      r[k - 1] = rr;
+      S.push_back(s);
+    }
+  }
+  if (used_ranks)
+    for (int k = 0; k <= d; ++k) used_ranks[k] = r[k];
+  return TT_OK;
+}
+
+int step_ell(const Problem& P, const Step& s, int ell_hint) {
+  const int64_t lim = std::min<int64_t>(s.n, s.m);
+  int64_t ell;
+  if (P.variant == TT_SVD) ell = lim;
+  else if (P.fixed) ell = std::min<int64_t>((int64_t)s.r + P.o.oversample, lim);
+  else ell = std::min<int64_t>(ell_hint, lim);
+  return (int)ell;
+}
+
+bool step_gram(const Problem& P, const Step& s) { return !P.alg4 && s.n <= kGramMax; }
+
+// ---- workspace layout ------------------------------------------------------
+struct Work {
+  double* carry[2];
+  double* Y;
+  double* X;
+  double* M;
+  double* part;
+  double* H;
+  double* K;
+  double* V1;
+  double* W;
+  double* normA2;
+  StepRec* recs;
+  size_t bytes;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Sizes {
+  int64_t carry, Y, X, part, V1;
+};
+
+// Upper bounds over every step (and every ell a prescribed-accuracy step may grow to).
+Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
+  Sizes z{1, 1, 1, 1, 1};
+  for (size_t i = 0; i < S.size(); ++i) {
+    const Step& s = S[i];
+    const int64_t lim = std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
+    const int ellmax = P.fixed ? step_ell(P, s, 0) : (int)lim;
+    if (i + 1 < S.size()) z.carry = std::max(z.carry, s.m * (int64_t)s.r);
+    z.V1 = std::max(z.V1, (int64_t)s.n * s.r);
+    const int c = std::max(1, std::min(ellmax, (int)kCMax));
+    if (step_gram(P, s)) {
+      z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, s.n) * s.n * s.n);
+    } else {
+      z.Y = std::max(z.Y, s.m * (int64_t)c);
+      z.X = std::max(z.X, (int64_t)s.n * c);
+      z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, c) * s.n * c);
+      z.part = std::max(z.part, (int64_t)atb_chunks(s.m, c, c) * c * c);
+    }
+    // with eps the run-time n may fall to <= kGramMax and take the Gram path
+    // (atb_chunks(m, n, c) * n <= 1024 * 64 for every n, so 65536 * kCMax covers any
+    // shape a prescribed-accuracy step can take)
+    if (!P.fixed) z.part = std::max<int64_t>(z.part, (int64_t)65536 * kCMax);
+    z.part = std::max<int64_t>(z.part, 2048);
+  }
+  return z;
+}
+
+size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
+  size_t off = 0;
+  auto take = [&](size_t nbytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(nbytes);
+    return p;
+  };
+  Work tmp;
+  Work& W = w ? *w : tmp;
+  W.carry[0] = (double*)take(z.carry * 8);
+  W.carry[1] = (double*)take(z.carry * 8);
+  W.Y = (double*)take(z.Y * 8);
+  W.X = (double*)take(z.X * 8);
+  W.M = (double*)take(z.X * 8);
+  W.part = (double*)take(z.part * 8);
+  W.H = (double*)take((size_t)kCMax * kCMax * 8);
+  W.K = (double*)take((size_t)kCMax * kCMax * 8);
+  W.V1 = (double*)take(z.V1 * 8);
+  W.W = (double*)take((size_t)kCMax * kCMax * 8);
+  W.normA2 = (double*)take(64);
+  W.recs = (StepRec*)take(sizeof(StepRec) * (size_t)d);
+  W.bytes = off;
+  return off;
+}
+
+int check_limits(const Problem& P, const std::vector<Step>& S) {
+  for (const Step& s : S) {
+    const int ell = P.fixed ? step_ell(P, s, 0) : std::min<int64_t>(TT_MAX_ELL, std::min<int64_t>(s.n, s.m));
+    if (P.fixed && ell > TT_MAX_ELL)
+      return fail(TT_EUNSUPPORTED, "step for core %d needs ell = %d > %d (n = %d, m = %lld)", s.core,
+                  ell, TT_MAX_ELL, s.n, (long long)s.m);
+    if (s.n > (1 << 20)) return fail(TT_EUNSUPPORTED, "core side n = %d too large", s.n);
+  }
+  return TT_OK;
+}
+
+// ---- one step --------------------------------------------------------------
+struct StepIO {
+  const void* A;
+  int a_f32;
+  double* out;       // carry (next A) or the last core
+  double* core;      // core buffer of this step
+};
+
+int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
+             const StepRec* prev, const Work& W, hipStream_t st, Prof& PF) {
+  SolveArgs a{};
+  a.n = s.n;
+  a.ell = ell;
+  a.q = P.o.q;
+  a.seed = P.o.seed;
+  a.label = s.core;
+  a.n_mode = s.n_mode;
+  a.n_rank = s.n_rank;
+  a.mode_fastest = s.mode_fastest;
+  a.r_fixed = P.fixed ? s.r : 0;
+  const double wk = P.fixed ? 0.0 : P.w[s.unfolding - 1];
+  a.eps_factor2 = wk * P.eps * wk * P.eps;
+  a.max_rank = P.fixed ? 0 : (int)std::min<int64_t>(s.r, TT_MAX_ELL);
+  a.core_layout = (P.sweep == TT_L2R) ? 0 : 1;
+  a.core = io.core;
+  a.V1 = W.V1;
+  a.W = W.W;
+  a.rec = W.recs + si;
+  a.normA2 = W.normA2;
+  a.first = first ? 1 : 0;
+  a.normC2_src = first ? nullptr : &prev->carry2;
+  const int64_t m = s.m;
+  const int n = s.n;
+  StepRec* rec = W.recs + si;
+
+  const double sa = io.a_f32 ? 4.0 : 8.0;
+  const double mn = (double)m * n;
+  if (step_gram(P, s)) {
+    // H = A^T A in one pass, then everything else on n x n
+    const int nch = atb_chunks(m, n, n);
+    LAUNCH(PF, KC_ATB, mn * sa + (double)n * n * 8, 2.0 * mn * n,
+           launch_atb(io.A, io.a_f32, io.A, io.a_f32, m, n, n, s.layout, W.part, nch, st));
+    LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * n * 8, (double)nch * n * n,
+           launch_reduce(W.part, nch, (int64_t)n * n, W.H, nullptr, st));
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_gram_solve(W.H, a, st));
+  } else if (!P.alg4) {
+    // sketch and q+1 power steps: X <- orth(A^T (A X)), starting from X = G
+    const int c = ell;
+    const int ach = ax_chunks(m, c);
+    const double mc = (double)m * c;
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
+    for (int it = 0; it <= P.o.q; ++it) {
+      LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+             launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
+                       (first && it == 0) ? W.part : nullptr, nullptr, st));
+      if (first && it == 0)
+        LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
+      const int nch = atb_chunks(m, n, c);
+      LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+             launch_atb(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, W.part, nch, st));
+      LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+             launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
+    }
+    // Rayleigh-Ritz: Y = A X, K = Y^T Y
+    LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, st));
+    const int kch = atb_chunks(m, c, c);
+    LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
+           launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, W.part, kch, st));
+    LAUNCH(PF, KC_REDUCE, (double)(kch + 1) * c * c * 8, (double)kch * c * c,
+           launch_reduce(W.part, kch, (int64_t)c * c, W.K, nullptr, st));
+    if (first) a.normC2_src = W.normA2;
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_rr_solve(W.K, W.X, a, st));
+  } else {
+    return fail(TT_EUNSUPPORTED, "ULV right-to-left sweep (Alg. 4) is not built yet");
+  }
+  return TT_OK;
+}
+
+int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io, const Work& W,
+               StepRec* rec, hipStream_t st, Prof& PF) {
+  const int64_t m = s.m;
+  const int ach = ax_chunks(m, r);
+  const double sa = io.a_f32 ? 4.0 : 8.0;
+  const double mr = (double)m * r;
+  if (step_gram(P, s)) {
+    const double mn = (double)m * s.n;
+    LAUNCH(PF, KC_CARRY, mn * sa + mr * 8 + (double)s.n * r * 8, 2.0 * mn * r,
+           launch_ax(io.A, io.a_f32, W.V1, io.out, 0, m, s.n, r, s.layout, ach, nullptr, W.part, st));
+  } else {
+    const double ml = (double)m * ell;
+    LAUNCH(PF, KC_CARRY, ml * 8 + mr * 8 + (double)ell * r * 8, 2.0 * ml * r,
+           launch_ax(W.Y, 0, W.W, io.out, 0, m, ell, r, s.layout, ach, nullptr, W.part, st));
+  }
+  LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, &rec->carry2, nullptr, st));
+  if (P.o.exact_delta) {
+    const int rch = resid_chunks(m);
+    const double mn = (double)m * s.n;
+    LAUNCH(PF, KC_RESID, mn * sa + mr * 8, 2.0 * mn * r + 2.0 * mn,
+           launch_resid(io.A, io.a_f32, io.out, W.V1, m, s.n, r, s.layout, rch, W.part, st));
+    LAUNCH(PF, KC_REDUCE, (double)rch * 8, rch, launch_reduce(W.part, rch, 1, &rec->resid2, nullptr, st));
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void tt_default_opts(tt_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->q = 1;
+  o->oversample = 8;
+}
+
+const char* tt_last_error(void) { return g_err; }
+
+const char* tt_kernel_class_name(int c) { return (c >= 0 && c < TT_NKCLASS) ? kClassNames[c] : nullptr; }
+
+int tt_utv_workspace(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_sweep sweep,
+                     tt_variant variant, tt_dtype dtype, const tt_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(TT_EINVAL, "bytes is NULL");
+  Problem P;
+  int rc = check_args(d, dims, ranks, eps, sweep, variant, dtype, opts, P);
+  if (rc) return rc;
+  std::vector<Step> S;
+  plan_steps(P, P.ranks, S, nullptr);
+  rc = check_limits(P, S);
+  if (rc) return rc;
+  *bytes = layout_work(size_bounds(P, S), d, nullptr, nullptr);
+  return TT_OK;
+}
+
+int tt_utv_core_capacity(int d, const int64_t* dims, const int64_t* ranks, double eps,
+                         const tt_opts* opts, int64_t* capacity) {
+  if (!capacity) return fail(TT_EINVAL, "capacity is NULL");
+  Problem P;
+  int rc = check_args(d, dims, ranks, eps, TT_L2R, TT_ULV, TT_F64, opts, P);
+  if (rc) return rc;
+  // the largest rank each bond can take in either sweep direction
+  int64_t r[TT_MAX_D + 1];
+  for (int k = 0; k <= d; ++k) {
+    const int64_t left = prod(P.dims, 0, k), right = prod(P.dims, k, d);
+    int64_t b = std::min(left, right);
+    if (k > 0 && k < d) b = std::min(b, P.ranks[k]);
+    r[k] = (k == 0 || k == d) ? 1 : b;
+  }
+  for (int k = 0; k < d; ++k) capacity[k] = r[k] * P.dims[k] * r[k + 1];
+  return TT_OK;
+}
+
+int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, const int64_t* ranks,
+                     double eps, tt_sweep sweep, tt_variant variant, const tt_opts* opts,
+                     void* work, size_t work_bytes, double* const* cores, tt_report* rep,
+                     void* stream) {
+  Problem P;
+  int rc = check_args(d, dims, ranks, eps, sweep, variant, dtype, opts, P);
+  if (rc) return rc;
+  if (!A) return fail(TT_EINVAL, "A is NULL");
+  if (!cores) return fail(TT_EINVAL, "cores is NULL");
+  for (int k = 0; k < d; ++k)
+    if (!cores[k]) return fail(TT_EINVAL, "cores[%d] is NULL", k);
+  std::vector<Step> S;
+  plan_steps(P, P.ranks, S, nullptr);
+  rc = check_limits(P, S);
+  if (rc) return rc;
+  Work W;
+  const size_t need = layout_work(size_bounds(P, S), d, (char*)work, &W);
+  if (!work || work_bytes < need)
+    return fail(TT_ENOSPC, "workspace %zu bytes < %zu needed", work_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Prof PF;
+  PF.on = P.o.profile != 0;
+  PF.st = st;
+
+  const int nsteps = d - 1;
+  int64_t r_run[TT_MAX_D + 1];
+  for (int k = 0; k <= d; ++k) r_run[k] = P.ranks[k];
+  std::vector<int> ells(nsteps, 0), rs(nsteps, 0);
+  const void* curA = A;
+  int a_f32 = (dtype == TT_F32);
+  int prev_r = 0;
+  bool all_sat = true;
+  std::vector<StepRec> host(nsteps);
+  for (int si = 0; si < nsteps; ++si) {
+    // shape of this step from the ranks decided so far
+    std::vector<Step> S2;
+    plan_steps(P, r_run, S2, nullptr);
+    Step s = S2[si];
+    const bool first = (si == 0);
+    const bool last = (si == nsteps - 1);
+    StepIO io;
+    io.A = curA;
+    io.a_f32 = a_f32;
+    io.core = cores[s.core - 1];
+    const int final_core = (P.sweep == TT_L2R) ? d - 1 : 0;
+    io.out = last ? cores[final_core] : W.carry[si & 1];
+    int ell = step_ell(P, s, first ? 2 * P.o.oversample : prev_r + P.o.oversample);
+    if (ell < 1) ell = 1;
+    if (ell > TT_MAX_ELL) ell = TT_MAX_ELL;
+    int r;
+    while (true) {
+      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, W, st, PF);
+      if (rc) return rc;
+      if (P.fixed) { r = std::min(s.r, ell); break; }
+      HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      r = host[si].r;
+      const int lim = (int)std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
+      if (host[si].sat || ell >= lim || (s.r > 0 && r >= s.r)) {
+        if (!host[si].sat) all_sat = false;
+        break;
+      }
+      ell = std::min(2 * ell, lim);
+    }
+    rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF);
+    if (rc) return rc;
+    ells[si] = ell;
+    rs[si] = r;
+    // rank of the bond this step decided
+    if (P.sweep == TT_L2R) r_run[s.core] = r; else r_run[s.core - 1] = r;
+    prev_r = r;
+    curA = io.out;
+    a_f32 = 0;
+  }
+  HIP_OK(hipMemcpyAsync(host.data(), W.recs, sizeof(StepRec) * nsteps, hipMemcpyDeviceToHost, st));
+  double nA2 = 0.0;
+  HIP_OK(hipMemcpyAsync(&nA2, W.normA2, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    rep->d = d;
+    for (int k = 0; k <= d; ++k) rep->ranks[k] = r_run[k];
+    rep->ranks[0] = rep->ranks[d] = 1;
+    double sum2 = 0.0, sum1 = 0.0;
+    std::vector<Step> S2;
+    plan_steps(P, r_run, S2, nullptr);
+    for (int si = 0; si < nsteps; ++si) {
+      const int u = S2[si].unfolding - 1;
+      const StepRec& h = host[si];
+      double dl2 = (h.resid2 >= 0.0) ? h.resid2 : h.normC2 - h.carry2;
+      if (dl2 < 0.0) dl2 = 0.0;
+      rep->delta[u] = sqrt(dl2);
+      rep->normC[u] = sqrt(std::max(h.normC2, 0.0));
+      rep->ell[u] = ells[si];
+      sum2 += dl2;
+      sum1 += sqrt(dl2);
+      if (!P.fixed && !h.sat) all_sat = false;
+    }
+    rep->norm_A = sqrt(std::max(nA2, 0.0));
+    for (const Prof::Rec& pr : PF.recs) {
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, pr.a, pr.b));
+      tt_kstat& k = rep->kstat[pr.cls];
+      k.launches += 1;
+      k.ms += ms;
+      k.bytes += pr.bytes;
+      k.flops += pr.flops;
+    }
+    rep->err_bound = P.alg4 ? sum1 : sqrt(sum2);
+    rep->rank_rule_met = P.fixed ? 1 : (all_sat ? 1 : 0);
+  }
+  if (!isfinite(nA2)) return fail(TT_ENONFINITE, "input holds non-finite values (||A||^2 = %g)", nA2);
+  if (!P.fixed && !all_sat)
+    return fail(TT_ERANK, "eps = %g not reached within the rank cap", P.eps);
+  return TT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reconstruction plan: split the train after core h so that the two partial
+// products L (P_left x r_h) and R (r_h x P_right) are about equally long; the
+// dense tensor is then one small-K GEMM L R (column-major = ivec order).
+struct RecPlan {
+  int h;
+  int64_t left_max, right_max;
+};
+
+int rec_plan(int d, const int64_t* dims, const int64_t* ranks, RecPlan& rp) {
+  if (d < 2 || d > TT_MAX_D || !dims || !ranks) return fail(TT_EINVAL, "bad train description");
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+  for (int k = 0; k < d; ++k)
+    if (dims[k] < 1) return fail(TT_EINVAL, "dims[%d] < 1", k);
+  for (int k = 0; k <= d; ++k)
+    if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
+  double best = 1e300;
+  rp.h = 1;
+  for (int h = 1; h < d; ++h) {
+    const double l = log((double)prod(dims, 0, h)), r = log((double)prod(dims, h, d));
+    if (fabs(l - r) < best) { best = fabs(l - r); rp.h = h; }
+  }
+  rp.left_max = 1;
+  for (int k = 2; k <= rp.h; ++k) rp.left_max = std::max(rp.left_max, prod(dims, 0, k) * ranks[k]);
+  rp.right_max = 1;
+  for (int k = d - 1; k >= rp.h + 1; --k) rp.right_max = std::max(rp.right_max, ranks[k - 1] * prod(dims, k - 1, d));
+  return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tt_reconstruct_workspace(int d, const int64_t* dims, const int64_t* ranks, size_t* bytes) {
+  if (!bytes) return fail(TT_EINVAL, "bytes is NULL");
+  RecPlan rp;
+  int rc = rec_plan(d, dims, ranks, rp);
+  if (rc) return rc;
+  *bytes = 2 * align_up(rp.left_max * 8) + 2 * align_up(rp.right_max * 8);
+  return TT_OK;
+}
+
+int tt_reconstruct(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                   void* out, tt_dtype dtype, void* work, size_t work_bytes, void* stream) {
+  RecPlan rp;
+  int rc = rec_plan(d, dims, ranks, rp);
+  if (rc) return rc;
+  if (!cores || !out) return fail(TT_EINVAL, "cores/out is NULL");
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "bad dtype");
+  for (int k = 0; k < d; ++k)
+    if (!cores[k]) return fail(TT_EINVAL, "cores[%d] is NULL", k);
+  const size_t need = 2 * align_up(rp.left_max * 8) + 2 * align_up(rp.right_max * 8);
+  if (work_bytes < need || (need > 0 && !work)) return fail(TT_ENOSPC, "workspace %zu < %zu", work_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)work;
+  double* Lb[2] = {(double*)base, (double*)(base + align_up(rp.left_max * 8))};
+  double* Rb[2] = {(double*)(base + 2 * align_up(rp.left_max * 8)),
+                   (double*)(base + 2 * align_up(rp.left_max * 8) + align_up(rp.right_max * 8))};
+  const int h = rp.h;
+  // L_1 = G_1 (I_1 x r_1); L_k = L_{k-1} (P_{k-1} x r_{k-1}) G_k (r_{k-1} x I_k r_k)
+  const double* L = cores[0];
+  for (int k = 2; k <= h; ++k) {
+    double* dst = Lb[k & 1];
+    HIP_OK(launch_gemm_smallk(L, cores[k - 1], dst, 0, prod(dims, 0, k - 1), dims[k - 1] * ranks[k],
+                              (int)ranks[k - 1], st));
+    L = dst;
+  }
+  // R_d = G_d (r_{d-1} x I_d); R_k = G_k (r_{k-1} I_k x r_k) R_{k+1} (r_k x Q_{k+1})
+  const double* R = cores[d - 1];
+  for (int k = d - 1; k >= h + 1; --k) {
+    double* dst = Rb[k & 1];
+    HIP_OK(launch_gemm_smallk(cores[k - 1], R, dst, 0, ranks[k - 1] * dims[k - 1], prod(dims, k, d),
+                              (int)ranks[k], st));
+    R = dst;
+  }
+  HIP_OK(launch_gemm_smallk(L, R, out, dtype == TT_F32, prod(dims, 0, h), prod(dims, h, d),
+                            (int)ranks[h], st));
+  return TT_OK;
+}
+
+int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+              const int64_t* idx, int64_t N, double* out, void* stream) {
+  if (d < 2 || d > TT_MAX_D || !dims || !ranks || !cores) return fail(TT_EINVAL, "bad train description");
+  for (int k = 0; k <= d; ++k)
+    if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+  if (N < 0) return fail(TT_EINVAL, "N < 0");
+  if (N > 0 && (!idx || !out)) return fail(TT_EINVAL, "idx/out is NULL");
+  HIP_OK(launch_sample(d, dims, ranks, cores, idx, N, out, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                       const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
+                       void* stream) {
+  if (d < 2 || d > TT_MAX_D || !dims || !ranks || !cores || !gcores) return fail(TT_EINVAL, "bad train description");
+  for (int k = 0; k <= d; ++k)
+    if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+  if (N < 0) return fail(TT_EINVAL, "N < 0");
+  if (N > 0 && (!idx || !gout)) return fail(TT_EINVAL, "idx/gout is NULL");
+  HIP_OK(launch_sample_bwd(d, dims, ranks, cores, idx, N, gout, gcores, (hipStream_t)stream));
+  return TT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the HIP translation units of libttutv.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ttutv {
+
+// Storage of a tall m x n matrix (m >= 1 rows on the long side, n columns on
+// the core side).  ROW: element (i, j) at i*n + j (left-to-right sweep, where
+// the tall matrix is the transpose of a column-major unfolding).  COL: at
+// i + j*m (right-to-left sweep, the unfolding itself).
+enum Layout : int { ROW = 0, COL = 1 };
+
+constexpr int kCMax = 64;      // widest small side handled by the tall kernels
+constexpr int kGramMax = 64;   // n up to which a step forms A^T A in one pass
+
+// One record per step of the sweep, written on the device, read back once.
+struct StepRec {
+  double normC2;    // ||C||_F^2 of the factorised matrix
+  double kept2;     // sum_{i<=r} s_i^2 (energy of the rank-r part)
+  double carry2;    // ||carry||_F^2 as measured on the written carry
+  double resid2;    // ||C - C_r||_F^2 measured directly (exact_delta), else -1
+  double lam[kCMax];// squared singular values of the ell x ell triangle, descending
+  int32_t r;        // rank chosen
+  int32_t sat;      // eps rule met (1) / not met (0); 1 for fixed ranks
+  int32_t ell;
+  int32_t pad;
+};
+
+// ---- tall streaming kernels (tt_tall.hip) --------------------------------
+// Number of row chunks the A^T Y kernel uses for an m x n by m x c product.
+int atb_chunks(int64_t m, int n, int c);
+// partials[ch][j + n*cc] = sum over the rows of chunk ch of A(i,j) Y(i,cc).
+hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n,
+                      int c, int layout, double* partials, int nchunks, hipStream_t st);
+// Rows of A handled per chunk by the A*W kernel, and the chunk count.
+int ax_chunks(int64_t m, int c);
+// Y(i, cc) = sum_j A(i,j) W(j,cc), W column-major n x c (FP64); Y in `layout`.
+// If sumsqA != NULL, sumsqA[ch] = sum of squares of the A entries read by chunk ch.
+// If sumsqY != NULL, sumsqY[ch] = sum of squares of the Y entries written.
+hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m,
+                     int n, int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
+                     hipStream_t st);
+// resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r col-major.
+int resid_chunks(int64_t m);
+hipError_t launch_resid(const void* A, int a_f32, const double* Cr, const double* V1, int64_t m,
+                        int n, int r, int layout, int nchunks, double* resid, hipStream_t st);
+// out[e] (+ out2[e] if out2) = sum_ch partials[ch*size + e], fixed order.
+hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,
+                         double* out2, hipStream_t st);
+
+// ---- single-workgroup factorisations (tt_small.hip) -----------------------
+struct SolveArgs {
+  int n, ell, q;
+  uint64_t seed;
+  int label, n_mode, n_rank, mode_fastest;
+  int r_fixed;            // > 0: fixed rank; <= 0: eps rule
+  double eps_factor2;     // (w_k * eps)^2: eps_k^2 = eps_factor2 * ||A||^2
+  int max_rank;
+  int core_layout;        // 0: core = V1 column-major (L2R); 1: core = V1 row-major (R2L)
+  double* core;           // core buffer (or NULL)
+  double* V1;             // n x r column-major
+  double* W;              // carry weights (non-Gram: ell x r, column-major)
+  StepRec* rec;
+  const double* normC2_src;  // NULL: take trace(H) (Gram mode, first step)
+  double* normA2;            // ||A||^2 (written on the first step, read for eps_k)
+  int first;
+};
+// Gram mode (n <= kGramMax): H = A^T A (n x n column-major).
+hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st);
+// Gaussian test matrix G (n x ell column-major) of the step.
+hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st);
+// X = orth(M): explicit orthonormal factor of the Householder QR of M (n x c).
+hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st);
+// Rayleigh-Ritz on span(X): K = (A X)^T (A X) (ell x ell) -> rank, V1 = X Z_r, W = Z_r.
+hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st);
+
+// ---- train contractions (tt_train.hip) ------------------------------------
+// C (M x N) = A (M x K) B (K x N), all column-major, K <= kCMax; C is double or float.
+hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f32, int64_t M,
+                              int64_t N, int K, hipStream_t st);
+hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
+                         const double* const* cores, const int64_t* idx, int64_t N, double* out,
+                         hipStream_t st);
+hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
+                             const double* const* cores, const int64_t* idx, int64_t N,
+                             const double* gout, double* const* gcores, hipStream_t st);
+
+}  // namespace ttutv

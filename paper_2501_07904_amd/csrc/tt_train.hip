@@ -1,0 +1,226 @@
+// Contractions of a tensor train (Eq. (TT)): dense reconstruction as a chain
+// of small-K GEMMs, entries at given multi-indices, and the gradient of a
+// weighted sum of sampled entries with respect to every core.
+#include "tt_internal.h"
+
+namespace ttutv {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int TT_MAX_D_INTERNAL = 32;
+
+// C (M x N) = A (M x K) B (K x N), column-major, K <= 64.  64 x 64 output
+// tile per workgroup, 4 x 4 per thread; consecutive threads own consecutive
+// row quads so that the column-major writes coalesce.
+template <typename TC>
+__global__ __launch_bounds__(kThreads) void k_gemm_smallk(const double* __restrict__ A,
+                                                          const double* __restrict__ B,
+                                                          TC* __restrict__ C, int64_t M, int64_t N,
+                                                          int K) {
+  __shared__ double sA[kCMax][64 + 1];
+  __shared__ double sB[kCMax][64 + 1];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t j0 = (int64_t)blockIdx.y * 64;
+  const int mi = (int)min((int64_t)64, M - i0);
+  const int nj = (int)min((int64_t)64, N - j0);
+  for (int e = t; e < 64 * K; e += kThreads) {
+    const int i = e % 64, k = e / 64;
+    sA[k][i] = (i < mi) ? A[(i0 + i) + M * k] : 0.0;
+  }
+  for (int e = t; e < 64 * K; e += kThreads) {
+    const int k = e % K, j = e / K;
+    sB[k][j] = (j < nj) ? B[k + (int64_t)K * (j0 + j)] : 0.0;
+  }
+  __syncthreads();
+  const int ti = (t % 16) * 4, tj = (t / 16) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = sA[k][ti + u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = sB[k][tj + v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    if (tj + v >= nj) break;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ti + u < mi) C[(i0 + ti + u) + M * (j0 + tj + v)] = (TC)acc[u][v];
+  }
+}
+
+struct TrainDesc {
+  int d;
+  int64_t dims[TT_MAX_D_INTERNAL];
+  int64_t ranks[TT_MAX_D_INTERNAL + 1];
+  const double* cores[TT_MAX_D_INTERNAL];
+};
+
+struct GradDesc {
+  double* cores[TT_MAX_D_INTERNAL];
+};
+
+__device__ __forceinline__ double core_at(const TrainDesc& D, int c, int64_t a, int64_t i, int64_t b) {
+  return D.cores[c][a + D.ranks[c] * (i + D.dims[c] * b)];
+}
+
+// One wave per sample: lane b holds entry b of the running row vector
+// G_1[i_1] ... G_k[i_k] (length r_k <= 64).
+__global__ __launch_bounds__(kThreads) void k_sample(TrainDesc D, const int64_t* __restrict__ idx,
+                                                     int64_t N, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kThreads) >> 6;
+  for (int64_t s = wave; s < N; s += nwaves) {
+    const int64_t* ix = idx + s * D.d;
+    double v = (lane < D.ranks[1]) ? core_at(D, 0, 0, ix[0], lane) : 0.0;
+    for (int c = 1; c < D.d; ++c) {
+      const int ra = (int)D.ranks[c], rb = (int)D.ranks[c + 1];
+      const int64_t i = ix[c];
+      double nv = 0.0;
+      for (int a = 0; a < ra; ++a) {
+        const double va = __shfl(v, a, 64);
+        if (lane < rb) nv = fma(va, core_at(D, c, a, i, lane), nv);
+      }
+      v = nv;
+    }
+    if (lane == 0) out[s] = v;
+  }
+}
+
+// One wave per sample: the right interface products rho_c (c = d-1..0) are
+// recomputed into LDS, then a left-to-right pass forms lambda_c and scatters
+// gout_s * lambda_c[a] * rho_c[b] into dG_c[a, i_c, b].
+__global__ __launch_bounds__(kThreads) void k_sample_bwd(TrainDesc D, const int64_t* __restrict__ idx,
+                                                         int64_t N, const double* __restrict__ gout,
+                                                         GradDesc G) {
+  __shared__ double rho[kThreads / 64][TT_MAX_D_INTERNAL][64];
+  const int lane = threadIdx.x & 63;
+  const int wl = threadIdx.x >> 6;
+  const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kThreads) >> 6;
+  const int d = D.d;
+  for (int64_t s = wave; s < N; s += nwaves) {
+    const int64_t* ix = idx + s * d;
+    const double w = gout[s];
+    // rho_{d-1} = [1]; rho_c[a] = sum_b G_{c+1}[a, i_{c+1}, b] rho_{c+1}[b]
+    double r = (lane == 0) ? 1.0 : 0.0;
+    rho[wl][d - 1][lane] = r;
+    for (int c = d - 2; c >= 0; --c) {
+      const int ra = (int)D.ranks[c + 1], rb = (int)D.ranks[c + 2];
+      const int64_t i = ix[c + 1];
+      double nr = 0.0;
+      for (int b = 0; b < rb; ++b) {
+        const double rbv = __shfl(r, b, 64);
+        if (lane < ra) nr = fma(core_at(D, c + 1, lane, i, b), rbv, nr);
+      }
+      r = nr;
+      rho[wl][c][lane] = r;
+    }
+    // left pass
+    double l = (lane == 0) ? 1.0 : 0.0;
+    for (int c = 0; c < d; ++c) {
+      const int ra = (int)D.ranks[c], rb = (int)D.ranks[c + 1];
+      const int64_t i = ix[c];
+      const int tot = ra * rb;
+      // lambda_c[a] lives in lane a; gather it by shuffle for every (a, b) entry
+      for (int e0 = 0; e0 < tot; e0 += 64) {
+        const int e = e0 + lane;
+        const int a = (e < tot) ? e % ra : 0;
+        const int b = (e < tot) ? e / ra : 0;
+        const double la = __shfl(l, a, 64);
+        if (e < tot) {
+          const double g = w * la * rho[wl][c][b];
+          atomicAdd(&G.cores[c][a + (int64_t)ra * (i + D.dims[c] * b)], g);
+        }
+      }
+      if (c + 1 < d) {
+        double nl = 0.0;
+        for (int a = 0; a < ra; ++a) {
+          const double la = __shfl(l, a, 64);
+          if (lane < rb) nl = fma(la, core_at(D, c, a, i, lane), nl);
+        }
+        l = nl;
+      }
+    }
+  }
+}
+
+__global__ void k_fill_zero(double* p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+
+bool fill_desc(TrainDesc& D, int d, const int64_t* dims, const int64_t* ranks,
+               const double* const* cores) {
+  if (d < 2 || d > TT_MAX_D_INTERNAL) return false;
+  D.d = d;
+  for (int k = 0; k < d; ++k) {
+    D.dims[k] = dims[k];
+    D.cores[k] = cores[k];
+  }
+  for (int k = 0; k <= d; ++k) D.ranks[k] = ranks[k];
+  return true;
+}
+
+}  // namespace
+
+hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f32, int64_t M,
+                              int64_t N, int K, hipStream_t st) {
+  if (M < 1 || N < 1 || K < 1 || K > kCMax) return hipErrorInvalidValue;
+  const int64_t gx = (M + 63) / 64, gy = (N + 63) / 64;
+  if (gy > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, (unsigned)gy);
+  if (c_f32)
+    hipLaunchKernelGGL((k_gemm_smallk<float>), grid, dim3(kThreads), 0, st, A, B, (float*)C, M, N, K);
+  else
+    hipLaunchKernelGGL((k_gemm_smallk<double>), grid, dim3(kThreads), 0, st, A, B, (double*)C, M, N, K);
+  return hipGetLastError();
+}
+
+static unsigned sample_blocks(int64_t N) {
+  int64_t waves = N;
+  int64_t blocks = (waves + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
+                         const double* const* cores, const int64_t* idx, int64_t N, double* out,
+                         hipStream_t st) {
+  TrainDesc D;
+  if (!fill_desc(D, d, dims, ranks, cores) || N < 0) return hipErrorInvalidValue;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
+                             const double* const* cores, const int64_t* idx, int64_t N,
+                             const double* gout, double* const* gcores, hipStream_t st) {
+  TrainDesc D;
+  GradDesc G;
+  if (!fill_desc(D, d, dims, ranks, cores)) return hipErrorInvalidValue;
+  for (int k = 0; k < d; ++k) G.cores[k] = gcores[k];
+  for (int k = 0; k < d; ++k) {
+    const int64_t sz = ranks[k] * dims[k] * ranks[k + 1];
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((sz + 255) / 256)), dim3(256), 0, st, gcores[k], sz);
+  }
+  if (N > 0)
+    hipLaunchKernelGGL(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, gout, G);
+  return hipGetLastError();
+}
+
+}  // namespace ttutv

