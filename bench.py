@@ -86,7 +86,8 @@ def main():
     cores = dec.cores()
     rec = T.tt_reconstruct(cores)
     rse = float(torch.linalg.norm(rec - A) / torch.linalg.norm(A))
-    log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} GB/s swept, ranks {rep['ranks']}, RSE {rse:.3e}")
+    log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} GB/s swept, ranks {rep['ranks']}, RSE {rse:.3e}, "
+        f"Jacobi sweeps {rep['sweeps']}")
 
     # dominant kernel class: largest summed launch time in the timed steps
     dom_name, dom = max(kstat.items(), key=lambda kv: kv[1]["ms"])

@@ -90,6 +90,7 @@ typedef struct {
   int32_t rank_rule_met;        /* eps mode: 1 if every step met its tolerance */
   int32_t d;
   tt_kstat kstat[TT_NKCLASS];   /* filled when opts.profile = 1 */
+  int32_t sweeps[TT_MAX_D];     /* Jacobi sweeps of the Rayleigh-Ritz step of unfolding k */
 } tt_report;
 
 /* Name of kernel class c (0 <= c < TT_NKCLASS), or NULL. */

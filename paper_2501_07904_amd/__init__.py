@@ -50,7 +50,7 @@ class tt_report(ctypes.Structure):
                 ("delta", ctypes.c_double * TT_MAX_D), ("normC", ctypes.c_double * TT_MAX_D),
                 ("norm_A", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("rank_rule_met", ctypes.c_int32), ("d", ctypes.c_int32),
-                ("kstat", tt_kstat * TT_NKCLASS)]
+                ("kstat", tt_kstat * TT_NKCLASS), ("sweeps", ctypes.c_int32 * TT_MAX_D)]
 
 
 _lib = None
@@ -186,6 +186,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
         "normC": [float(rep.normC[k]) for k in range(d - 1)],
         "norm_A": float(rep.norm_A), "err_bound": float(rep.err_bound),
         "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
+        "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
     }
     if profile:
         report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
@@ -322,7 +323,8 @@ class Decomposer:
         out = {"ranks": [int(rep.ranks[k]) for k in range(d + 1)], "ell": [int(rep.ell[k]) for k in range(d - 1)],
                "delta": [float(rep.delta[k]) for k in range(d - 1)],
                "normC": [float(rep.normC[k]) for k in range(d - 1)], "norm_A": float(rep.norm_A),
-               "err_bound": float(rep.err_bound), "rank_rule_met": bool(rep.rank_rule_met)}
+               "err_bound": float(rep.err_bound), "rank_rule_met": bool(rep.rank_rule_met),
+               "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)]}
         if self.profile:
             out["kstat"] = {self.lib.tt_kernel_class_name(c).decode(): {
                 "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),

@@ -269,7 +269,7 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
     // (atb_chunks(m, n, c) * n <= 1024 * 64 for every n, so 65536 * kCMax covers any
     // shape a prescribed-accuracy step can take)
     if (!P.fixed) z.part = std::max<int64_t>(z.part, (int64_t)65536 * kCMax);
-    z.part = std::max<int64_t>(z.part, 2048);
+    z.part = std::max<int64_t>(z.part, 8192);   // per-workgroup sums of k_ax (<= 8192 groups)
   }
   return z;
 }
@@ -358,7 +358,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   } else if (!P.alg4) {
     // sketch and q+1 power steps: X <- orth(A^T (A X)), starting from X = G
     const int c = ell;
-    const int ach = ax_chunks(m, c);
+    const int ach = ax_chunks(m, n, c);
     const double mc = (double)m * c;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
     for (int it = 0; it <= P.o.q; ++it) {
@@ -393,7 +393,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
 int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io, const Work& W,
                StepRec* rec, hipStream_t st, Prof& PF) {
   const int64_t m = s.m;
-  const int ach = ax_chunks(m, r);
+  const int ach = step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r);
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double mr = (double)m * r;
   if (step_gram(P, s)) {
@@ -558,6 +558,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       rep->delta[u] = sqrt(dl2);
       rep->normC[u] = sqrt(std::max(h.normC2, 0.0));
       rep->ell[u] = ells[si];
+      rep->sweeps[u] = h.sweeps;
       sum2 += dl2;
       sum1 += sqrt(dl2);
       if (!P.fixed && !h.sat) all_sat = false;

@@ -25,7 +25,7 @@ struct StepRec {
   int32_t r;        // rank chosen
   int32_t sat;      // eps rule met (1) / not met (0); 1 for fixed ranks
   int32_t ell;
-  int32_t pad;
+  int32_t sweeps;   // Jacobi sweeps used by the Rayleigh-Ritz eigen-decomposition
 };
 
 // ---- tall streaming kernels (tt_tall.hip) --------------------------------
@@ -34,15 +34,15 @@ int atb_chunks(int64_t m, int n, int c);
 // partials[ch][j + n*cc] = sum over the rows of chunk ch of A(i,j) Y(i,cc).
 hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n,
                       int c, int layout, double* partials, int nchunks, hipStream_t st);
-// Rows of A handled per chunk by the A*W kernel, and the chunk count.
-int ax_chunks(int64_t m, int c);
-// Y(i, cc) = sum_j A(i,j) W(j,cc), W column-major n x c (FP64); Y in `layout`.
+// Number of workgroups (and of sum-of-squares partials) the A*W kernel uses.
+int ax_chunks(int64_t m, int n, int c);
+// Y(i, cc) = sum_j A(i,j) W(j,cc), W k-major n x c (W(j,cc) at j*c + cc, FP64); Y in `layout`.
 // If sumsqA != NULL, sumsqA[ch] = sum of squares of the A entries read by chunk ch.
 // If sumsqY != NULL, sumsqY[ch] = sum of squares of the Y entries written.
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m,
                      int n, int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
                      hipStream_t st);
-// resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r col-major.
+// resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r k-major.
 int resid_chunks(int64_t m);
 hipError_t launch_resid(const void* A, int a_f32, const double* Cr, const double* V1, int64_t m,
                         int n, int r, int layout, int nchunks, double* resid, hipStream_t st);
@@ -60,8 +60,8 @@ struct SolveArgs {
   int max_rank;
   int core_layout;        // 0: core = V1 column-major (L2R); 1: core = V1 row-major (R2L)
   double* core;           // core buffer (or NULL)
-  double* V1;             // n x r column-major
-  double* W;              // carry weights (non-Gram: ell x r, column-major)
+  double* V1;             // n x r, k-major (V1(i,c) at i*r + c)
+  double* W;              // carry weights (non-Gram: ell x r, k-major)
   StepRec* rec;
   const double* normC2_src;  // NULL: take trace(H) (Gram mode, first step)
   double* normA2;            // ||A||^2 (written on the first step, read for eps_k)
@@ -69,11 +69,13 @@ struct SolveArgs {
 };
 // Gram mode (n <= kGramMax): H = A^T A (n x n column-major).
 hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st);
-// Gaussian test matrix G (n x ell column-major) of the step.
+// Gaussian test matrix G (n x ell, k-major: G(i,j) at i*ell + j) of the step.
 hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st);
-// X = orth(M): explicit orthonormal factor of the Householder QR of M (n x c).
+// X = orth(M): explicit orthonormal factor of the Householder QR of M (n x c,
+// column-major); X is written k-major.
 hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st);
-// Rayleigh-Ritz on span(X): K = (A X)^T (A X) (ell x ell) -> rank, V1 = X Z_r, W = Z_r.
+// Rayleigh-Ritz on span(X) (X k-major): K = (A X)^T (A X) (ell x ell) -> rank,
+// V1 = X Z_r, W = Z_r.
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st);
 
 // ---- train contractions (tt_train.hip) ------------------------------------

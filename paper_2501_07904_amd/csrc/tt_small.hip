@@ -8,7 +8,7 @@ namespace ttutv {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;   // single-workgroup solvers: 16 waves
 constexpr int kLd = kCMax + 1;   // padded leading dimension of LDS matrices
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -54,131 +54,144 @@ __device__ __forceinline__ double sketch_row_entry(const SolveArgs& a, int row, 
 __global__ void k_gen_sketch(double* G, SolveArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)a.n * a.ell) return;
-  G[e] = sketch_row_entry(a, (int)(e % a.n), (int)(e / a.n));
+  const int row = (int)(e / a.ell), j = (int)(e % a.ell);
+  G[e] = sketch_row_entry(a, row, j);   // k-major: G[row * ell + j]
 }
 
 // --------------------------------------------------------------------------
-// Householder QR of X (n x c, column-major, leading dim ldx), c <= 64: X is
-// overwritten by the reflectors and Q (n x c) receives the explicit
-// orthonormal factor H_0 H_1 ... H_{c-1} [I; 0].  A zero column gives an
-// identity reflector, so Q stays orthonormal for rank-deficient X.
-__device__ void householder_q(double* X, int64_t ldx, double* Q, int64_t ldq, int n, int c,
-                              double* tau, double* sh) {
+// Householder QR of X (n x c, column-major, leading dim ld), c <= 64, in
+// place: on return X holds the explicit orthonormal factor H_0 ... H_{c-1}
+// [I; 0].  A zero column gives an identity reflector, so the result stays
+// orthonormal for rank-deficient X.  Factorisation: per column one pass in
+// which a group of tpj threads per trailing column computes both the norm of
+// the pivot column and its own dot product, then updates its column (one
+// barrier per column).  The reflector v_k = [1; scal_k X[k+1:, k]] is kept
+// unscaled below the diagonal.  Q is then formed in place backwards, as
+// LAPACK's dorg2r does.
+__device__ __forceinline__ int group_width(int ncol) {
+  int tpj = 64;
+  while (tpj * ncol > kThreads && tpj > 1) tpj >>= 1;
+  return tpj;
+}
+
+__device__ void householder_inplace(double* X, int64_t ld, int n, int c, double* tau, double* scal) {
   const int t = threadIdx.x;
   for (int k = 0; k < c; ++k) {
-    double part = 0.0;
-    for (int i = k + 1 + t; i < n; i += kThreads) {
-      const double x = X[i + k * ldx];
-      part = fma(x, x, part);
+    const int ncol = c - k;
+    const int tpj = group_width(ncol);
+    const int g = t / tpj, lane = t % tpj;
+    const bool on = g < ncol;
+    const int j = k + g;
+    double sig = 0.0, gj = 0.0;
+    if (on) {
+#pragma unroll 4
+      for (int i = k + 1 + lane; i < n; i += tpj) {
+        const double xk = X[i + k * ld];
+        sig = fma(xk, xk, sig);
+        gj = fma(xk, X[i + j * ld], gj);
+      }
     }
-    const double sig = block_sum(part, sh);
-    if (t == 0) {
-      const double alpha = X[k + k * ldx];
-      double tk = 0.0, scale = 0.0;
+    for (int o = tpj >> 1; o > 0; o >>= 1) {
+      sig += __shfl_xor(sig, o, 64);
+      gj += __shfl_xor(gj, o, 64);
+    }
+    if (on) {
+      const double alpha = X[k + k * ld];
+      double tk = 0.0, sc = 0.0;
       if (sig > 0.0) {
         const double mu = sqrt(fma(alpha, alpha, sig));
         const double beta = alpha <= 0.0 ? mu : -mu;
         tk = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-        X[k + k * ldx] = beta;
+        sc = 1.0 / (alpha - beta);
       }
-      tau[k] = tk;
-      sh[8] = scale;
-    }
-    __syncthreads();
-    const double tk = tau[k];
-    const double scale = sh[8];
-    if (tk != 0.0) {
-      for (int i = k + 1 + t; i < n; i += kThreads) X[i + k * ldx] *= scale;
-    }
-    __syncthreads();
-    const int ncol = c - k - 1;
-    if (ncol > 0 && tk != 0.0) {
-      int tpj = 64;
-      while (tpj * ncol > kThreads && tpj > 1) tpj >>= 1;
-      const int col = t / tpj, lane = t % tpj;
-      const bool on = col < ncol;
-      const int j = k + 1 + col;
-      double dot = 0.0;
-      if (on) {
-        if (lane == 0) dot = X[k + j * ldx];
-        for (int i = k + 1 + lane; i < n; i += tpj) dot = fma(X[i + k * ldx], X[i + j * ldx], dot);
-      }
-      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-      if (on) {
-        const double f = tk * dot;
-        if (lane == 0) X[k + j * ldx] -= f;
-        for (int i = k + 1 + lane; i < n; i += tpj) X[i + j * ldx] = fma(-f, X[i + k * ldx], X[i + j * ldx]);
+      if (g == 0) {
+        if (lane == 0) { tau[k] = tk; scal[k] = sc; }
+      } else if (tk != 0.0) {
+        const double xkj = X[k + j * ld];
+        const double f = tk * fma(sc, gj, xkj);  // tau * v^T x_j
+        if (lane == 0) X[k + j * ld] = xkj - f;
+        const double fs = f * sc;
+        for (int i = k + 1 + lane; i < n; i += tpj) X[i + j * ld] = fma(-fs, X[i + k * ld], X[i + j * ld]);
       }
     }
     __syncthreads();
   }
-  for (int64_t e = t; e < (int64_t)n * c; e += kThreads) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    Q[i + j * ldq] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
   for (int k = c - 1; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    const int ncol = c - k;
-    int tpj = 64;
-    while (tpj * ncol > kThreads && tpj > 1) tpj >>= 1;
-    const int col = t / tpj, lane = t % tpj;
-    const bool on = col < ncol;
-    const int j = k + col;
-    double dot = 0.0;
-    if (on) {
-      if (lane == 0) dot = Q[k + j * ldq];
-      for (int i = k + 1 + lane; i < n; i += tpj) dot = fma(X[i + k * ldx], Q[i + j * ldq], dot);
+    const double tk = tau[k], sc = scal[k];
+    const int ncol = c - k - 1;
+    if (ncol > 0) {
+      const int tpj = group_width(ncol);
+      const int g = t / tpj, lane = t % tpj;
+      const bool on = g < ncol;
+      const int j = k + 1 + g;
+      double dsum = 0.0;
+      if (on && tk != 0.0)
+        for (int i = k + 1 + lane; i < n; i += tpj) dsum = fma(X[i + k * ld], X[i + j * ld], dsum);
+      for (int o = tpj >> 1; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+      if (on) {
+        // row k of column j is zero before H_k (it held an entry of R)
+        const double f = tk * sc * dsum;
+        if (lane == 0) X[k + j * ld] = -f;
+        if (tk != 0.0) {
+          const double fs = f * sc;
+          for (int i = k + 1 + lane; i < n; i += tpj) X[i + j * ld] = fma(-fs, X[i + k * ld], X[i + j * ld]);
+        }
+      }
     }
-    for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-    if (on) {
-      const double f = tk * dot;
-      if (lane == 0) Q[k + j * ldq] -= f;
-      for (int i = k + 1 + lane; i < n; i += tpj) Q[i + j * ldq] = fma(-f, X[i + k * ldx], Q[i + j * ldq]);
-    }
+    __syncthreads();
+    for (int i = t; i < n; i += kThreads)
+      X[i + k * ld] = (i < k) ? 0.0 : (i == k ? 1.0 - tk : -tk * sc * X[i + k * ld]);
     __syncthreads();
   }
 }
 
 // --------------------------------------------------------------------------
 // Symmetric eigen-decomposition of K (L x L in LDS, ld kLd) by cyclic Jacobi
-// with the round-robin parallel ordering (L/2 disjoint rotations per round).
-// On return lam[0..L) holds the eigenvalues in descending order and perm[a]
-// the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
-__device__ void jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, double* rot,
-                           int* rp, double* sh, int* flag) {
+// with the round-robin parallel ordering: each round rotates L/2 disjoint
+// pairs, and K <- J^T K J is applied as independent 2 x 2 block updates
+// (two barriers per round).  Pairs whose off-diagonal entry is below the
+// rounding floor are skipped; the iteration stops after a sweep without a
+// rotation.  On return lam[0..L) holds the eigenvalues in descending order
+// and perm[a] the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
+__device__ __forceinline__ void rr_pair(int p, int round, int Le, int* a, int* b) {
+  int x, y;
+  if (p == 0) { x = 0; y = 1 + (round % (Le - 1)); }
+  else { x = 1 + ((p + round) % (Le - 1)); y = 1 + ((Le - 1 - p + round) % (Le - 1)); }
+  *a = min(x, y);
+  *b = max(x, y);
+}
+
+__device__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, double* rot, double* sh,
+                          int* flag) {
   const int t = threadIdx.x;
   const int Le = L + (L & 1);
+  const int h = Le / 2;
   for (int e = t; e < L * L; e += kThreads) {
     const int i = e % L, j = e / L;
     Z[i + j * kLd] = (i == j) ? 1.0 : 0.0;
   }
-  double dmax_part = 0.0;
-  for (int i = t; i < L; i += kThreads) dmax_part = fmax(dmax_part, fabs(K[i + i * kLd]));
-  // block max via shuffles + LDS
-  for (int o = 32; o > 0; o >>= 1) dmax_part = fmax(dmax_part, __shfl_xor(dmax_part, o, 64));
-  if ((t & 63) == 0) sh[t >> 6] = dmax_part;
+  double dpart = 0.0;
+  for (int i = t; i < L; i += kThreads) dpart = fmax(dpart, fabs(K[i + i * kLd]));
+  for (int o = 32; o > 0; o >>= 1) dpart = fmax(dpart, __shfl_xor(dpart, o, 64));
+  if ((t & 63) == 0) sh[t >> 6] = dpart;
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < kThreads / 64; ++i) dmax = fmax(dmax, sh[i]);
+  const double abs_floor = 1e-300 + 1e-15 * dmax;
   __syncthreads();
-  const double abs_floor = 1e-300 + 1e-18 * dmax;
-  for (int sweep = 0; sweep < 40 && Le >= 2; ++sweep) {
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
+    sweeps = sweep + 1;
     if (t == 0) *flag = 0;
     __syncthreads();
     for (int round = 0; round < Le - 1; ++round) {
-      if (t < Le / 2) {
-        const int p = t;
+      if (t < h) {
         int a, b;
-        if (p == 0) { a = 0; b = 1 + (round % (Le - 1)); }
-        else { a = 1 + ((p + round) % (Le - 1)); b = 1 + ((Le - 1 - p + round) % (Le - 1)); }
-        if (a > b) { const int s = a; a = b; b = s; }
+        rr_pair(t, round, Le, &a, &b);
         double cs = 1.0, sn = 0.0;
         if (b < L) {
           const double app = K[a + a * kLd], aqq = K[b + b * kLd], apq = K[a + b * kLd];
-          if (fabs(apq) > abs_floor && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > abs_floor && fabs(apq) > 1e-15 * sqrt(fabs(app)) * sqrt(fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             cs = 1.0 / sqrt(1.0 + tt * tt);
@@ -186,35 +199,43 @@ __device__ void jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, 
             *flag = 1;
           }
         }
-        rot[p] = cs;
-        rot[32 + p] = sn;
-        rp[p] = a;
-        rp[32 + p] = b;
+        rot[2 * t] = cs;
+        rot[2 * t + 1] = sn;
       }
       __syncthreads();
-      // K <- J^T K: rows a, b
-      for (int e = t; e < (Le / 2) * L; e += kThreads) {
-        const int p = e / L, j = e % L;
-        const double cs = rot[p], sn = rot[32 + p];
-        if (sn == 0.0) continue;
-        const int a = rp[p], b = rp[32 + p];
-        const double ka = K[a + j * kLd], kb = K[b + j * kLd];
-        K[a + j * kLd] = cs * ka - sn * kb;
-        K[b + j * kLd] = sn * ka + cs * kb;
-      }
-      __syncthreads();
-      // K <- K J and Z <- Z J: columns a, b
-      for (int e = t; e < (Le / 2) * L; e += kThreads) {
-        const int p = e / L, i = e % L;
-        const double cs = rot[p], sn = rot[32 + p];
-        if (sn == 0.0) continue;
-        const int a = rp[p], b = rp[32 + p];
-        const double ka = K[i + a * kLd], kb = K[i + b * kLd];
-        K[i + a * kLd] = cs * ka - sn * kb;
-        K[i + b * kLd] = sn * ka + cs * kb;
-        const double za = Z[i + a * kLd], zb = Z[i + b * kLd];
-        Z[i + a * kLd] = cs * za - sn * zb;
-        Z[i + b * kLd] = sn * za + cs * zb;
+      // K <- J^T K J on the 2 x 2 blocks (P, Q); Z <- Z J on the 1 x 2 blocks (i, Q)
+      for (int e = t; e < h * h + L * h; e += kThreads) {
+        if (e < h * h) {
+          const int P = e % h, Q = e / h;
+          const double cP = rot[2 * P], sP = rot[2 * P + 1], cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
+          if (sP == 0.0 && sQ == 0.0) continue;
+          int aP, bP, aQ, bQ;
+          rr_pair(P, round, Le, &aP, &bP);
+          rr_pair(Q, round, Le, &aQ, &bQ);
+          const bool vb = bP < L, wb = bQ < L;
+          const double kaa = K[aP + aQ * kLd];
+          const double kab = wb ? K[aP + bQ * kLd] : 0.0;
+          const double kba = vb ? K[bP + aQ * kLd] : 0.0;
+          const double kbb = (vb && wb) ? K[bP + bQ * kLd] : 0.0;
+          // right: columns (aQ, bQ) times J_Q
+          const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
+          const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
+          // left: rows (aP, bP) times J_P^T
+          K[aP + aQ * kLd] = cP * raa - sP * rba;
+          if (wb) K[aP + bQ * kLd] = cP * rab - sP * rbb;
+          if (vb) K[bP + aQ * kLd] = sP * raa + cP * rba;
+          if (vb && wb) K[bP + bQ * kLd] = sP * rab + cP * rbb;
+        } else {
+          const int f = e - h * h;
+          const int i = f % L, Q = f / L;
+          const double cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
+          if (sQ == 0.0) continue;
+          int aQ, bQ;
+          rr_pair(Q, round, Le, &aQ, &bQ);
+          const double za = Z[i + aQ * kLd], zb = Z[i + bQ * kLd];
+          Z[i + aQ * kLd] = cQ * za - sQ * zb;
+          Z[i + bQ * kLd] = sQ * za + cQ * zb;
+        }
       }
       __syncthreads();
     }
@@ -235,6 +256,7 @@ __device__ void jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, 
   __syncthreads();
   if (t < L) lam[t] = K[perm[t] + perm[t] * kLd];
   __syncthreads();
+  return sweeps;
 }
 
 // Rank decision (fixed r, or the smallest r with ||C||^2 - sum_{i<=r} s_i^2 <= eps_k^2).
@@ -266,13 +288,13 @@ __device__ void decide_rank(const SolveArgs& a, const double* lam, int ell, doub
 
 // Column signs: largest-magnitude entry of every column of V (n x r) positive,
 // lowest row on ties; one wave per column.
-__device__ void canonical_signs(const double* V, int64_t ldv, int n, int r, double* sg) {
+__device__ void canonical_signs(const double* V, int64_t si, int64_t sa, int n, int r, double* sg) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (int a = w; a < r; a += kThreads / 64) {
     double best = -1.0, val = 0.0;
     int bi = 0x7fffffff;
     for (int i = lane; i < n; i += 64) {
-      const double x = V[i + a * ldv];
+      const double x = V[i * si + a * sa];
       const double ax = fabs(x);
       if (ax > best) { best = ax; bi = i; val = x; }
     }
@@ -293,16 +315,23 @@ __device__ void canonical_signs(const double* V, int64_t ldv, int n, int r, doub
 // factorisation; the core side V1 = X Z_r goes to the core and to V1.
 __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restrict__ H, SolveArgs a) {
   __shared__ double sH[kCMax * kLd];
-  __shared__ double sX[kCMax * kLd];
-  __shared__ double sQ[kCMax * kLd];
+  __shared__ double sB0[kCMax * kLd];
+  __shared__ double sB1[kCMax * kLd];
   __shared__ double sK[kCMax * kLd];
-  __shared__ double lam[kCMax], tau[kCMax], rot[64], sg[kCMax], sh[16];
-  __shared__ int perm[kCMax], rp[64], flag, sr, ssat;
+  __shared__ double lam[kCMax], tau[kCMax], scal[kCMax], rot[64], sg[kCMax], sh[32];
+  __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
   const int n = a.n;
-  const int ell = min(a.ell, n);
+  const int L = min(a.ell, n);
   for (int e = t; e < n * n; e += kThreads) sH[(e % n) + (e / n) * kLd] = H[e];
+  double* X = sB0;   // current basis (n x L)
+  double* T = sB1;   // H X
+  if (L >= n) {
+    for (int e = t; e < n * n; e += kThreads) X[(e % n) + (e / n) * kLd] = ((e % n) == (e / n)) ? 1.0 : 0.0;
+  } else {
+    for (int e = t; e < n * L; e += kThreads) X[(e % n) + (e / n) * kLd] = sketch_row_entry(a, e % n, e / n);
+  }
   __syncthreads();
   if (t == 0) {
     double tr = 0.0;
@@ -311,52 +340,43 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     snormC2 = nc2;
     if (a.first) *a.normA2 = nc2;
   }
-  if (ell >= n) {
-    for (int e = t; e < n * n; e += kThreads) sX[(e % n) + (e / n) * kLd] = ((e % n) == (e / n)) ? 1.0 : 0.0;
-  } else {
-    for (int e = t; e < n * ell; e += kThreads) sX[(e % n) + (e / n) * kLd] = sketch_row_entry(a, e % n, e / n);
-  }
-  __syncthreads();
-  const int L = ell >= n ? n : ell;
-  if (ell < n) {
+  if (L < n) {
+    // X spans H^(q+1) G: multiply, orthonormalise in place, swap
     for (int it = 0; it <= a.q; ++it) {
       for (int e = t; e < n * L; e += kThreads) {
         const int i = e % n, j = e / n;
         double s = 0.0;
-        for (int k = 0; k < n; ++k) s = fma(sH[i + k * kLd], sX[k + j * kLd], s);
-        sQ[i + j * kLd] = s;
+        for (int k = 0; k < n; ++k) s = fma(sH[i + k * kLd], X[k + j * kLd], s);
+        T[i + j * kLd] = s;
       }
       __syncthreads();
-      householder_q(sQ, kLd, sX, kLd, n, L, tau, sh);
+      householder_inplace(T, kLd, n, L, tau, scal);
+      double* tmp = X; X = T; T = tmp;
     }
   }
   // K = X^T H X
   for (int e = t; e < n * L; e += kThreads) {
     const int i = e % n, j = e / n;
     double s = 0.0;
-    for (int k = 0; k < n; ++k) s = fma(sH[i + k * kLd], sX[k + j * kLd], s);
-    sQ[i + j * kLd] = s;
+    for (int k = 0; k < n; ++k) s = fma(sH[i + k * kLd], X[k + j * kLd], s);
+    T[i + j * kLd] = s;
   }
   __syncthreads();
   for (int e = t; e < L * L; e += kThreads) {
     const int i = e % L, j = e / L;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s = fma(sX[k + i * kLd], sQ[k + j * kLd], s);
-    sK[i + j * kLd] = s;
-  }
-  __syncthreads();
-  // symmetrise against rounding
-  for (int e = t; e < L * L; e += kThreads) {
-    const int i = e % L, j = e / L;
-    if (i < j) {
-      const double v = 0.5 * (sK[i + j * kLd] + sK[j + i * kLd]);
-      sK[i + j * kLd] = v;
-      sK[j + i * kLd] = v;
+    if (i > j) continue;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      s1 = fma(X[k + i * kLd], T[k + j * kLd], s1);
+      s2 = fma(X[k + j * kLd], T[k + i * kLd], s2);
     }
+    const double v = 0.5 * (s1 + s2);
+    sK[i + j * kLd] = v;
+    sK[j + i * kLd] = v;
   }
   __syncthreads();
   double* sZ = sH;  // H is no longer needed
-  jacobi_eig(sK, sZ, L, lam, perm, rot, rp, sh, &flag);
+  const int sweeps = jacobi_eig(sK, sZ, L, lam, perm, rot, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -365,20 +385,20 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
   }
   __syncthreads();
   const int r = sr;
-  // V1 = X Z_r (into sQ)
+  // V1 = X Z_r (into T)
   for (int e = t; e < n * r; e += kThreads) {
     const int i = e % n, c = e / n;
     const int pc = perm[c];
     double s = 0.0;
-    for (int k = 0; k < L; ++k) s = fma(sX[i + k * kLd], sZ[k + pc * kLd], s);
-    sQ[i + c * kLd] = s;
+    for (int k = 0; k < L; ++k) s = fma(X[i + k * kLd], sZ[k + pc * kLd], s);
+    T[i + c * kLd] = s;
   }
   __syncthreads();
-  canonical_signs(sQ, kLd, n, r, sg);
+  canonical_signs(T, 1, kLd, n, r, sg);
   for (int e = t; e < n * r; e += kThreads) {
     const int i = e % n, c = e / n;
-    const double v = sQ[i + c * kLd] * sg[c];
-    a.V1[i + (int64_t)n * c] = v;
+    const double v = T[i + c * kLd] * sg[c];
+    a.V1[(int64_t)i * r + c] = v;
     if (a.core) {
       if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
       else a.core[c + (int64_t)r * i] = v;
@@ -392,6 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     rec->sat = ssat;
     rec->ell = L;
     rec->resid2 = -1.0;
+    rec->sweeps = sweeps;
   }
   for (int i = t; i < kCMax; i += kThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
 }
@@ -399,21 +420,21 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
 // --------------------------------------------------------------------------
 // X = orth(M) for n x c blocks; LDS-resident when it fits, else in place in
 // global memory (M is overwritten by the reflectors).
-constexpr int kOrthLdsDoubles = 8192;
+constexpr int kOrthLdsDoubles = 19456;   // 152 KB: n x c blocks up to this size stay in LDS
 
 __global__ __launch_bounds__(kThreads) void k_orth(double* M, double* X, int n, int c) {
-  __shared__ double buf[2 * kOrthLdsDoubles];
-  __shared__ double tau[kCMax], sh[16];
+  __shared__ double buf[kOrthLdsDoubles];
+  __shared__ double tau[kCMax], scal[kCMax];
   const int t = threadIdx.x;
   if ((int64_t)n * c <= kOrthLdsDoubles) {
-    double* sM = buf;
-    double* sX = buf + kOrthLdsDoubles;
-    for (int e = t; e < n * c; e += kThreads) sM[e] = M[e];
+    for (int e = t; e < n * c; e += kThreads) buf[e] = M[e];
     __syncthreads();
-    householder_q(sM, n, sX, n, n, c, tau, sh);
-    for (int e = t; e < n * c; e += kThreads) X[e] = sX[e];
+    householder_inplace(buf, n, n, c, tau, scal);
+    for (int e = t; e < n * c; e += kThreads) X[e] = buf[(e / c) + (int64_t)n * (e % c)];
   } else {
-    householder_q(M, n, X, n, n, c, tau, sh);
+    // large blocks: factor in place in M (global), then write X k-major
+    householder_inplace(M, n, n, c, tau, scal);
+    for (int64_t e = t; e < (int64_t)n * c; e += kThreads) X[e] = M[(e / c) + (int64_t)n * (e % c)];
   }
 }
 
@@ -425,8 +446,8 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
                                                        const double* __restrict__ X, SolveArgs a) {
   __shared__ double sK[kCMax * kLd];
   __shared__ double sZ[kCMax * kLd];
-  __shared__ double lam[kCMax], rot[64], sg[kCMax], sh[16];
-  __shared__ int perm[kCMax], rp[64], flag, sr, ssat;
+  __shared__ double lam[kCMax], rot[64], sg[kCMax], sh[32];
+  __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
   const int n = a.n;
@@ -437,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
   }
   if (t == 0) snormC2 = *a.normC2_src;
   __syncthreads();
-  jacobi_eig(sK, sZ, L, lam, perm, rot, rp, sh, &flag);
+  const int sweeps = jacobi_eig(sK, sZ, L, lam, perm, rot, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -447,17 +468,17 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
   __syncthreads();
   const int r = sr;
   for (int64_t e = t; e < (int64_t)n * r; e += kThreads) {
-    const int i = (int)(e % n), c = (int)(e / n);
+    const int i = (int)(e / r), c = (int)(e % r);
     const int pc = perm[c];
     double s = 0.0;
-    for (int k = 0; k < L; ++k) s = fma(X[i + (int64_t)n * k], sZ[k + pc * kLd], s);
-    a.V1[e] = s;
+    for (int k = 0; k < L; ++k) s = fma(X[(int64_t)i * L + k], sZ[k + pc * kLd], s);
+    a.V1[e] = s;   // k-major: V1[i * r + c]
   }
   __threadfence_block();
   __syncthreads();
-  canonical_signs(a.V1, n, n, r, sg);
+  canonical_signs(a.V1, r, 1, n, r, sg);
   for (int64_t e = t; e < (int64_t)n * r; e += kThreads) {
-    const int i = (int)(e % n), c = (int)(e / n);
+    const int i = (int)(e / r), c = (int)(e % r);
     const double v = a.V1[e] * sg[c];
     a.V1[e] = v;
     if (a.core) {
@@ -466,8 +487,8 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
     }
   }
   for (int e = t; e < L * r; e += kThreads) {
-    const int k = e % L, c = e / L;
-    a.W[k + (int64_t)L * c] = sZ[k + perm[c] * kLd] * sg[c];
+    const int k = e / r, c = e % r;
+    a.W[(int64_t)k * r + c] = sZ[k + perm[c] * kLd] * sg[c];   // k-major
   }
   if (t == 0) {
     StepRec* rec = a.rec;
@@ -477,6 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
     rec->sat = ssat;
     rec->ell = L;
     rec->resid2 = -1.0;
+    rec->sweeps = sweeps;
   }
   for (int i = t; i < kCMax; i += kThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
 }

@@ -39,9 +39,12 @@ __global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, cons
                                                   int64_t m, int n, int c, int layout,
                                                   int64_t rows_per_chunk,
                                                   double* __restrict__ partials) {
-  __shared__ double sA[kAtbTR][kAtbJT + 1];
-  __shared__ double sY[kAtbTR][kCMax + 1];
-  __shared__ double red[kThreads * 16];
+  // tiles and the final reduction scratch share the same LDS
+  __shared__ double lds[2 * kAtbTR * (kAtbJT + 1) > kThreads * 16 ? 2 * kAtbTR * (kAtbJT + 1) : kThreads * 16];
+  double (*sA)[kAtbJT + 1] = reinterpret_cast<double (*)[kAtbJT + 1]>(lds);
+  double (*sY)[kCMax + 1] = reinterpret_cast<double (*)[kCMax + 1]>(lds + kAtbTR * (kAtbJT + 1));
+  double* red = lds;
+  const bool gram = ((const void*)A == (const void*)Y);   // Y = A: the tile of A serves both sides
   const int t = threadIdx.x;
   const int64_t chunk = blockIdx.x;
   const int j0 = blockIdx.y * kAtbJT;
@@ -67,10 +70,12 @@ __global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, cons
       if (layout == ROW) { i = e / kAtbJT; j = e % kAtbJT; } else { i = e % kAtbTR; j = e / kAtbTR; }
       sA[i][j] = (i < tr && j < jt) ? ldv(A, at(layout, rb + i, j0 + j, m, n)) : 0.0;
     }
-    for (int e = t; e < kAtbTR * kCMax; e += kThreads) {
-      int i, j;
-      if (layout == ROW) { i = e / kCMax; j = e % kCMax; } else { i = e % kAtbTR; j = e / kAtbTR; }
-      sY[i][j] = (i < tr && j < c) ? ldv(Y, at(layout, rb + i, j, m, c)) : 0.0;
+    if (!gram) {
+      for (int e = t; e < kAtbTR * kCMax; e += kThreads) {
+        int i, j;
+        if (layout == ROW) { i = e / kCMax; j = e % kCMax; } else { i = e % kAtbTR; j = e / kAtbTR; }
+        sY[i][j] = (i < tr && j < c) ? ldv(Y, at(layout, rb + i, j, m, c)) : 0.0;
+      }
     }
     __syncthreads();
     if (active) {
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, cons
 #pragma unroll
         for (int u = 0; u < 4; ++u) a[u] = sA[i][bj + u];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) y[v] = sY[i][bc + v];
+        for (int v = 0; v < 4; ++v) y[v] = gram ? sA[i][bc + v] : sY[i][bc + v];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -107,102 +112,130 @@ __global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, cons
 }
 
 // ---------------------------------------------------------------------------
-// Y = A W.  Each thread owns a 4-row x 4-column block of the output tile of
-// TR = 4 * (256 / ceil(c/4)) rows; A is staged 32 columns at a time in LDS.
-constexpr int kAxKT = 32;
-
-// Row blocks of 4 per tile: as many as the 256 threads allow, at most 64 so
-// that a tile never exceeds the 256 rows staged in LDS.
-__host__ __device__ __forceinline__ int ax_row_blocks(int nbc) {
-  const int rb = kThreads / nbc;
-  return rb < 64 ? rb : 64;
-}
-
-template <typename TA, typename TY>
+// Y = A W with W (n x c) stored k-major (row k = the c contiguous doubles
+// W[k*c .. k*c+c)).  One thread per row of A: it streams the row once and
+// keeps the c outputs in registers; W is read with wave-uniform addresses, so
+// it comes through the scalar cache and never occupies LDS.
+template <typename TA, typename TY, int CB>
 __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
                                                  TY* __restrict__ Y, int64_t m, int n, int c,
-                                                 int layout, int64_t rows_per_chunk,
-                                                 double* __restrict__ sumsqA,
+                                                 int layout, double* __restrict__ sumsqA,
                                                  double* __restrict__ sumsqY) {
-  __shared__ double sA[kThreads][kAxKT + 1];
-  __shared__ double sW[kAxKT][kCMax];
   __shared__ double sh[8];
-  const int t = threadIdx.x;
-  const int nbc = (c + 3) >> 2;
-  const int RB = ax_row_blocks(nbc);
-  const int TR = 4 * RB;  // <= kThreads rows, the height of sA
-  const bool active = t < RB * nbc;
-  const int bc = (t % nbc) * 4, br = (t / nbc) * 4;
-  const int64_t chunk = blockIdx.x;
-  const int64_t r0 = chunk * rows_per_chunk;
-  const int64_t r1 = min(m, r0 + rows_per_chunk);
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
   double ssa = 0.0, ssy = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += TR) {
-    const int tr = (int)min((int64_t)TR, r1 - rb);
-    double acc[4][4];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+    double acc[CB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < CB; ++u) acc[u] = 0.0;
+    const TA* a = (layout == COL) ? A + i : A + i * n;
+    const int64_t ks = (layout == COL) ? m : 1;
+#pragma unroll 8
+    for (int k = 0; k < n; ++k) {
+      const double x = (double)a[(int64_t)k * ks];
+      ssa = fma(x, x, ssa);
+      const double* w = W + (int64_t)k * c;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int k0 = 0; k0 < n; k0 += kAxKT) {
-      const int kt = min(kAxKT, n - k0);
-      const int cnt = tr * kt;
-      for (int e = t; e < cnt; e += kThreads) {
-        int i, k;
-        if (layout == ROW) { i = e / kt; k = e % kt; } else { i = e % tr; k = e / tr; }
-        const double x = ldv(A, at(layout, rb + i, k0 + k, m, n));
-        ssa = fma(x, x, ssa);
-        sA[i][k] = x;
-      }
-      for (int e = t; e < kAxKT * kCMax; e += kThreads) {
-        const int k = e % kAxKT, cc = e / kAxKT;
-        sW[k][cc] = (k < kt && cc < c) ? W[(k0 + k) + (int64_t)n * cc] : 0.0;
-      }
-      __syncthreads();
-      if (active && br < tr) {
-        for (int k = 0; k < kt; ++k) {
-          double a[4], w[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = sA[min(br + u, TR - 1)][k];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) w[v] = sW[k][bc + v];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], w[v], acc[u][v]);
-        }
-      }
-      __syncthreads();
+      for (int u = 0; u < CB; ++u)
+        if (u < c) acc[u] = fma(x, w[u], acc[u]);
     }
-    if (active) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (br + u >= tr) break;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (bc + v < c) {
-            const TY y = (TY)acc[u][v];
-            const double yd = (double)y;
-            ssy = fma(yd, yd, ssy);
-            Y[at(layout, rb + br + u, bc + v, m, c)] = y;
-          }
-        }
+    for (int u = 0; u < CB; ++u) {
+      if (u < c) {
+        const TY y = (TY)acc[u];
+        const double yd = (double)y;
+        ssy = fma(yd, yd, ssy);
+        Y[at(layout, i, u, m, c)] = y;
       }
     }
   }
   if (sumsqA) {
     const double s = block_sum(ssa, sh);
-    if (t == 0) sumsqA[chunk] = s;
+    if (threadIdx.x == 0) sumsqA[blockIdx.x] = s;
   }
   if (sumsqY) {
     const double s = block_sum(ssy, sh);
-    if (t == 0) sumsqY[chunk] = s;
+    if (threadIdx.x == 0) sumsqY[blockIdx.x] = s;
   }
 }
 
+// Same product when there are too few rows to fill the chip: a workgroup
+// owns 64 rows (one per lane) and splits the n columns of A over its KS
+// waves; the KS partial rows are summed in LDS in a fixed order, 8 output
+// columns at a time.
+template <typename TA, typename TY, int CB, int KS>
+__global__ __launch_bounds__(64 * KS) void k_ax_split(const TA* __restrict__ A, const double* __restrict__ W,
+                                                     TY* __restrict__ Y, int64_t m, int n, int c,
+                                                     int layout, double* __restrict__ sumsqA,
+                                                     double* __restrict__ sumsqY) {
+  __shared__ double red[KS][64][9];
+  __shared__ double sh[KS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool row_ok = i < m;
+  const int kper = (n + KS - 1) / KS;
+  const int k0 = w * kper, k1 = min(n, k0 + kper);
+  double acc[CB];
+#pragma unroll
+  for (int u = 0; u < CB; ++u) acc[u] = 0.0;
+  double ssa = 0.0, ssy = 0.0;
+  if (row_ok) {
+    const TA* a = (layout == COL) ? A + i : A + i * n;
+    const int64_t ks = (layout == COL) ? m : 1;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) {
+      const double x = (double)a[(int64_t)k * ks];
+      ssa = fma(x, x, ssa);
+      const double* wr = W + (int64_t)k * c;
+#pragma unroll
+      for (int u = 0; u < CB; ++u)
+        if (u < c) acc[u] = fma(x, wr[u], acc[u]);
+    }
+  }
+#pragma unroll
+  for (int u0 = 0; u0 < CB; u0 += 8) {
+    if (u0 >= c) break;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) red[w][lane][u] = acc[u0 + u < CB ? u0 + u : 0];
+    __syncthreads();
+    if (w == 0 && row_ok) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (u0 + u < c) {
+          double s = 0.0;
+          for (int q = 0; q < KS; ++q) s += red[q][lane][u];
+          const TY y = (TY)s;
+          const double yd = (double)y;
+          ssy = fma(yd, yd, ssy);
+          Y[at(layout, i, u0 + u, m, c)] = y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // fixed-order block sums of the squares
+  for (int o = 32; o > 0; o >>= 1) {
+    ssa += __shfl_xor(ssa, o, 64);
+    ssy += __shfl_xor(ssy, o, 64);
+  }
+  if (sumsqA) {
+    if (lane == 0) sh[w] = ssa;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int q = 0; q < KS; ++q) s += sh[q];
+      sumsqA[blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+  if (sumsqY && threadIdx.x == 0) sumsqY[blockIdx.x] = ssy;
+}
+
 // ---------------------------------------------------------------------------
-// resid[chunk] = sum over rows of ||A(i,:) - Cr(i,:) V1^T||^2 (direct step error).
+// resid[chunk] = sum over rows of ||A(i,:) - Cr(i,:) V1^T||^2 (direct step
+// error); V1 (n x r) is stored k-major like the right operand of k_ax.
 constexpr int kResTR = 64;
+constexpr int kAxKT = 32;
 
 template <typename TA>
 __global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, const double* __restrict__ Cr,
@@ -229,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, co
       __syncthreads();
       for (int e = t; e < kt * r; e += kThreads) {
         const int k = e % kt, a = e / kt;
-        sV[k][a] = V1[(k0 + k) + (int64_t)n * a];
+        sV[k][a] = V1[(int64_t)(k0 + k) * r + a];
       }
       __syncthreads();
       for (int e = t; e < tr * kt; e += kThreads) {
@@ -250,12 +283,21 @@ __global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, co
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int nchunks,
                                                      int64_t size, double* __restrict__ out,
                                                      double* __restrict__ out2) {
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= size) return;
+  // 16 consecutive entries x 16 chunk slices; slices are summed in a fixed order
+  __shared__ double red[16][17];
+  const int el = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + el;
   double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) s += partials[(int64_t)ch * size + e];
-  out[e] = s;
-  if (out2) out2[e] = s;
+  if (e < size)
+    for (int ch = sl; ch < nchunks; ch += 16) s += partials[(int64_t)ch * size + e];
+  red[sl][el] = s;
+  __syncthreads();
+  if (sl == 0 && e < size) {
+    double tot = 0.0;
+    for (int k = 0; k < 16; ++k) tot += red[k][el];
+    out[e] = tot;
+    if (out2) out2[e] = tot;
+  }
 }
 
 }  // namespace
@@ -290,31 +332,62 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
   return hipGetLastError();
 }
 
-int ax_chunks(int64_t m, int c) {
-  const int nbc = (c + 3) / 4;
-  const int TR = 4 * ax_row_blocks(nbc);
-  const int64_t tiles = (m + TR - 1) / TR;
-  return (int)(tiles < 2048 ? tiles : 2048);
+// Split factor over the columns of A: 1 (one thread per row) when the rows
+// alone give enough waves, else 4, 8 or 16 waves per 64 rows.
+static int ax_split(int64_t m, int n) {
+  const int64_t row_waves = (m + 63) / 64;
+  if (row_waves >= 8192 || n < 64) return 1;
+  int ks = 4;
+  while (ks < 16 && row_waves * ks < 8192 && n / (2 * ks) >= 16) ks *= 2;
+  return ks;
+}
+
+int ax_chunks(int64_t m, int n, int c) {
+  (void)c;
+  if (ax_split(m, n) > 1) return (int)((m + 63) / 64);
+  const int64_t blocks = (m + kThreads - 1) / kThreads;
+  return (int)(blocks < 2048 ? blocks : 2048);
+}
+
+template <typename TA, typename TY, int CB>
+static void ax_dispatch_cb(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
+                           int nchunks, double* sumsqA, double* sumsqY, hipStream_t st) {
+  const int ks = ax_split(m, n);
+  if (ks == 1)
+    hipLaunchKernelGGL((k_ax<TA, TY, CB>), dim3(nchunks), dim3(kThreads), 0, st, A, W, Y, m, n, c, layout,
+                       sumsqA, sumsqY);
+  else if (ks == 4)
+    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 4>), dim3(nchunks), dim3(256), 0, st, A, W, Y, m, n, c,
+                       layout, sumsqA, sumsqY);
+  else if (ks == 8)
+    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 8>), dim3(nchunks), dim3(512), 0, st, A, W, Y, m, n, c,
+                       layout, sumsqA, sumsqY);
+  else
+    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 16>), dim3(nchunks), dim3(1024), 0, st, A, W, Y, m, n, c,
+                       layout, sumsqA, sumsqY);
+}
+
+template <typename TA, typename TY>
+static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
+                        int nchunks, double* sumsqA, double* sumsqY, hipStream_t st) {
+  if (c <= 8) ax_dispatch_cb<TA, TY, 8>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+  else if (c <= 16) ax_dispatch_cb<TA, TY, 16>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+  else if (c <= 32) ax_dispatch_cb<TA, TY, 32>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+  else ax_dispatch_cb<TA, TY, 64>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
 }
 
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m, int n,
                      int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
                      hipStream_t st) {
-  if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
-  const int64_t rpc = (m + nchunks - 1) / nchunks;
-  dim3 grid(nchunks);
+  if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks != ax_chunks(m, n, c)) return hipErrorInvalidValue;
   if (!a_f32 && !y_f32)
-    hipLaunchKernelGGL((k_ax<double, double>), grid, dim3(kThreads), 0, st, (const double*)A, W,
-                       (double*)Y, m, n, c, layout, rpc, sumsqA, sumsqY);
+    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
   else if (a_f32 && !y_f32)
-    hipLaunchKernelGGL((k_ax<float, double>), grid, dim3(kThreads), 0, st, (const float*)A, W,
-                       (double*)Y, m, n, c, layout, rpc, sumsqA, sumsqY);
+    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
   else if (a_f32 && y_f32)
-    hipLaunchKernelGGL((k_ax<float, float>), grid, dim3(kThreads), 0, st, (const float*)A, W,
-                       (float*)Y, m, n, c, layout, rpc, sumsqA, sumsqY);
+    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
   else
-    hipLaunchKernelGGL((k_ax<double, float>), grid, dim3(kThreads), 0, st, (const double*)A, W,
-                       (float*)Y, m, n, c, layout, rpc, sumsqA, sumsqY);
+    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
   return hipGetLastError();
 }
 
@@ -339,7 +412,7 @@ hipError_t launch_resid(const void* A, int a_f32, const double* Cr, const double
 hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,
                          double* out2, hipStream_t st) {
   if (size < 1 || nchunks < 1) return hipErrorInvalidValue;
-  const int64_t blocks = (size + kThreads - 1) / kThreads;
+  const int64_t blocks = (size + 15) / 16;
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
                      size, out, out2);
   return hipGetLastError();
