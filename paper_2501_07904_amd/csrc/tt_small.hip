@@ -74,7 +74,7 @@ __device__ __forceinline__ int group_width(int ncol) {
   return tpj;
 }
 
-__device__ void householder_inplace(double* X, int64_t ld, int n, int c, double* tau, double* scal) {
+__device__ __forceinline__ void householder_inplace(double* X, int64_t ld, int n, int c, double* tau, double* scal) {
   const int t = threadIdx.x;
   for (int k = 0; k < c; ++k) {
     const int ncol = c - k;
@@ -146,6 +146,251 @@ __device__ void householder_inplace(double* X, int64_t ld, int n, int c, double*
 }
 
 // --------------------------------------------------------------------------
+// Register-resident Householder QR with the same result as householder_inplace
+// (explicit Q of X, n x c), for n <= R * tpj.  Thread group g (tpj threads,
+// tpj = kThreads / c rounded up to a power of two) owns column g and keeps its
+// rows i = lane + tpj*r (r < R) in registers.  Column k's Householder vector
+// is published by its group through a double-buffered LDS vector, so both the
+// factorisation and the backward formation of Q take one barrier per column.
+// Input X(i, j) at X[i*xi + j*xj]; output Q(i, j) at Q[i*qi + j*qj] (may alias X).
+__host__ __device__ __forceinline__ int reg_group_width(int c) {
+  int cp = 1;
+  while (cp < c) cp <<= 1;
+  const int tpj = kThreads / cp;
+  return tpj < 64 ? tpj : 64;
+}
+
+template <int R, int TPJ>
+__device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int64_t xj, double* Q, int64_t qi,
+                                                int64_t qj, int n, int c, double* vbuf) {
+  // rows are padded to NP = R * TPJ with zeros, so the loops below need no row
+  // guards; TPJ (= reg_group_width(c)) is a compile-time constant so that the
+  // LDS offsets of a thread's rows are immediates
+  const int t = threadIdx.x;
+  constexpr int tpj = TPJ;
+  constexpr int NP = R * TPJ;
+  const int g = t / tpj, lane = t % tpj;
+  const bool own = g < c;
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + tpj * r;
+    x[r] = 0.0;
+    if (own && i < n) x[r] = X[i * xi + g * xj];
+  }
+  double* taus = vbuf + 2 * NP;
+  double my_tau = 0.0;
+  // ---- factorisation
+  for (int k = 0; k < c; ++k) {
+    double* v = vbuf + (k & 1) * NP;
+    if (g == k) {
+      double sig = 0.0, alpha = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        sig = fma(i > k ? x[r] : 0.0, x[r], sig);
+        alpha += (i == k) ? x[r] : 0.0;
+      }
+      for (int o = tpj >> 1; o > 0; o >>= 1) {
+        sig += __shfl_xor(sig, o, 64);
+        alpha += __shfl_xor(alpha, o, 64);
+      }
+      double tk = 0.0, sc = 0.0;
+      if (sig > 0.0) {
+        const double mu = sqrt(fma(alpha, alpha, sig));
+        const double beta = alpha <= 0.0 ? mu : -mu;
+        tk = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      my_tau = tk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        const double vi = (i < k) ? 0.0 : (i == k ? 1.0 : sc * x[r]);
+        v[i] = vi;
+        x[r] = (i > k) ? vi : x[r];   // keep the scaled reflector below the diagonal
+      }
+      if (lane == 0) taus[k] = tk;
+    }
+    __syncthreads();
+    if (own && g > k) {
+      const double tk = taus[k];
+      double dot = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dot = fma(v[lane + tpj * r], x[r], dot);
+      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      const double f = tk * dot;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = fma(-f, v[lane + tpj * r], x[r]);
+    }
+  }
+  __syncthreads();
+  // ---- Q = H_0 ... H_{c-1} [I; 0], backwards, in registers
+  for (int k = c - 1; k >= 0; --k) {
+    double* v = vbuf + (k & 1) * NP;
+    if (g == k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        v[i] = (i < k) ? 0.0 : (i == k ? 1.0 : x[r]);
+      }
+      if (lane == 0) taus[k] = my_tau;
+    }
+    __syncthreads();
+    if (own && g > k) {
+      const double tk = taus[k];
+      double dot = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dot = fma(v[lane + tpj * r], x[r], dot);
+      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      const double f = tk * dot;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = fma(-f, v[lane + tpj * r], x[r]);
+    } else if (g == k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        x[r] = (i < k) ? 0.0 : (i == k ? 1.0 - my_tau : -my_tau * x[r]);
+      }
+    }
+  }
+  __syncthreads();   // every read of X (and of vbuf) is done before Q may overwrite them
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + tpj * r;
+      if (i < n) Q[i * qi + g * qj] = x[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Same algorithm and thread mapping with the columns kept in LDS (W, column g
+// at W + g*NP) instead of registers: each thread touches only its own rows of
+// its own column, so the accesses are conflict-free and independent; used
+// when R rows per thread would not fit the register budget of 1024 threads.
+template <int R, int TPJ>
+__device__ __forceinline__ void householder_lds(const double* X, int64_t xi, int64_t xj, double* Q, int64_t qi,
+                                                int64_t qj, int n, int c, double* W, double* vbuf) {
+  const int t = threadIdx.x;
+  constexpr int tpj = TPJ;
+  constexpr int NP = R * TPJ;
+  const int g = t / tpj, lane = t % tpj;
+  const bool own = g < c;
+  double* x = W + (int64_t)g * NP + lane;   // row lane + tpj*r at x[tpj*r]
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + tpj * r;
+      x[tpj * r] = (i < n) ? X[i * xi + g * xj] : 0.0;
+    }
+  }
+  double* taus = vbuf + 2 * NP;
+  double my_tau = 0.0;
+  for (int k = 0; k < c; ++k) {
+    double* v = vbuf + (k & 1) * NP + lane;
+    if (g == k) {
+      double sig = 0.0, alpha = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        const double xr = x[tpj * r];
+        sig = fma(i > k ? xr : 0.0, xr, sig);
+        alpha += (i == k) ? xr : 0.0;
+      }
+      for (int o = tpj >> 1; o > 0; o >>= 1) {
+        sig += __shfl_xor(sig, o, 64);
+        alpha += __shfl_xor(alpha, o, 64);
+      }
+      double tk = 0.0, sc = 0.0;
+      if (sig > 0.0) {
+        const double mu = sqrt(fma(alpha, alpha, sig));
+        const double beta = alpha <= 0.0 ? mu : -mu;
+        tk = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      my_tau = tk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        const double xr = x[tpj * r];
+        const double vi = (i < k) ? 0.0 : (i == k ? 1.0 : sc * xr);
+        v[tpj * r] = vi;
+        x[tpj * r] = (i > k) ? vi : xr;
+      }
+      if (lane == 0) taus[k] = tk;
+    }
+    __syncthreads();
+    if (own && g > k) {
+      const double tk = taus[k];
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        d0 = fma(v[tpj * r], x[tpj * r], d0);
+        if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
+      }
+      double dot = d0 + d1;
+      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      const double f = tk * dot;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
+    }
+  }
+  __syncthreads();
+  for (int k = c - 1; k >= 0; --k) {
+    double* v = vbuf + (k & 1) * NP + lane;
+    if (g == k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        v[tpj * r] = (i < k) ? 0.0 : (i == k ? 1.0 : x[tpj * r]);
+      }
+      if (lane == 0) taus[k] = my_tau;
+    }
+    __syncthreads();
+    if (own && g > k) {
+      const double tk = taus[k];
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        d0 = fma(v[tpj * r], x[tpj * r], d0);
+        if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
+      }
+      double dot = d0 + d1;
+      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      const double f = tk * dot;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
+    } else if (g == k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + tpj * r;
+        x[tpj * r] = (i < k) ? 0.0 : (i == k ? 1.0 - my_tau : -my_tau * x[tpj * r]);
+      }
+    }
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + tpj * r;
+      if (i < n) Q[i * qi + g * qj] = x[tpj * r];
+    }
+  }
+  __syncthreads();
+}
+
+// Rows per thread the register path needs for an n x c block (0: too large).
+__device__ __host__ __forceinline__ int reg_rows(int n, int c) {
+  int cp = 1;
+  while (cp < c) cp <<= 1;
+  int tpj = kThreads / cp;
+  if (tpj > 64) tpj = 64;
+  const int R = (n + tpj - 1) / tpj;
+  return R <= 4 ? 4 : R <= 8 ? 8 : R <= 16 ? 16 : 0;   // R <= 16 keeps 1024 threads within 128 VGPRs
+}
+
+// --------------------------------------------------------------------------
 // Symmetric eigen-decomposition of K (L x L in LDS, ld kLd) by cyclic Jacobi
 // with the round-robin parallel ordering: each round rotates L/2 disjoint
 // pairs, and K <- J^T K J is applied as independent 2 x 2 block updates
@@ -154,31 +399,47 @@ __device__ void householder_inplace(double* X, int64_t ld, int n, int c, double*
 // rotation.  On return lam[0..L) holds the eigenvalues in descending order
 // and perm[a] the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
 __device__ __forceinline__ void rr_pair(int p, int round, int Le, int* a, int* b) {
+  // round < Le-1 and p < Le/2, so each sum is below 2(Le-1): one conditional subtraction
+  const int m = Le - 1;
   int x, y;
-  if (p == 0) { x = 0; y = 1 + (round % (Le - 1)); }
-  else { x = 1 + ((p + round) % (Le - 1)); y = 1 + ((Le - 1 - p + round) % (Le - 1)); }
+  if (p == 0) {
+    x = 0;
+    y = 1 + round;
+  } else {
+    int u = p + round;
+    if (u >= m) u -= m;
+    int v = m - p + round;
+    if (v >= m) v -= m;
+    x = 1 + u;
+    y = 1 + v;
+  }
   *a = min(x, y);
   *b = max(x, y);
 }
 
-__device__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, double* rot, double* sh,
-                          int* flag) {
+template <int NT>
+__device__ __forceinline__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, double* rot,
+                                          double* sh, int* flag) {
+  // K and Z are padded to Le = L rounded up to even with a zero row and column;
+  // the pair holding the padding index then always gets the identity rotation
   const int t = threadIdx.x;
   const int Le = L + (L & 1);
   const int h = Le / 2;
-  for (int e = t; e < L * L; e += kThreads) {
-    const int i = e % L, j = e / L;
-    Z[i + j * kLd] = (i == j) ? 1.0 : 0.0;
+  for (int e = t; e < Le * Le; e += NT) {
+    const int i = e % Le, j = e / Le;
+    Z[i + j * kLd] = (i == j && i < L) ? 1.0 : 0.0;
+    if (i >= L || j >= L) K[i + j * kLd] = 0.0;
   }
   double dpart = 0.0;
-  for (int i = t; i < L; i += kThreads) dpart = fmax(dpart, fabs(K[i + i * kLd]));
+  for (int i = t; i < L; i += NT) dpart = fmax(dpart, fabs(K[i + i * kLd]));
   for (int o = 32; o > 0; o >>= 1) dpart = fmax(dpart, __shfl_xor(dpart, o, 64));
   if ((t & 63) == 0) sh[t >> 6] = dpart;
   __syncthreads();
   double dmax = 0.0;
-  for (int i = 0; i < kThreads / 64; ++i) dmax = fmax(dmax, sh[i]);
+  for (int i = 0; i < NT / 64; ++i) dmax = fmax(dmax, sh[i]);
   const double abs_floor = 1e-300 + 1e-15 * dmax;
   __syncthreads();
+  int* pr = (int*)(rot + 64);   // pair indices of the round: pr[2p], pr[2p+1]
   int sweeps = 0;
   for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
     sweeps = sweep + 1;
@@ -188,50 +449,43 @@ __device__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, d
       if (t < h) {
         int a, b;
         rr_pair(t, round, Le, &a, &b);
+        const double app = K[a + a * kLd], aqq = K[b + b * kLd], apq = K[a + b * kLd];
         double cs = 1.0, sn = 0.0;
-        if (b < L) {
-          const double app = K[a + a * kLd], aqq = K[b + b * kLd], apq = K[a + b * kLd];
-          if (fabs(apq) > abs_floor && fabs(apq) > 1e-15 * sqrt(fabs(app)) * sqrt(fabs(aqq))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            cs = 1.0 / sqrt(1.0 + tt * tt);
-            sn = tt * cs;
-            *flag = 1;
-          }
+        if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(app * aqq)) {
+          // t = tan(theta) of the rotation zeroing apq, |t| <= 1:
+          // t = 2 apq / (d + sign(d) sqrt(d^2 + 4 apq^2)), d = aqq - app
+          const double dd = aqq - app, tw = 2.0 * apq;
+          const double rr = sqrt(fma(dd, dd, tw * tw));
+          const double tt = tw / (dd >= 0.0 ? dd + rr : dd - rr);
+          cs = rsqrt(fma(tt, tt, 1.0));
+          sn = tt * cs;
+          *flag = 1;
         }
         rot[2 * t] = cs;
         rot[2 * t + 1] = sn;
+        pr[2 * t] = a;
+        pr[2 * t + 1] = b;
       }
       __syncthreads();
       // K <- J^T K J on the 2 x 2 blocks (P, Q); Z <- Z J on the 1 x 2 blocks (i, Q)
-      for (int e = t; e < h * h + L * h; e += kThreads) {
+      for (int e = t; e < h * h + Le * h; e += NT) {
         if (e < h * h) {
           const int P = e % h, Q = e / h;
           const double cP = rot[2 * P], sP = rot[2 * P + 1], cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
-          if (sP == 0.0 && sQ == 0.0) continue;
-          int aP, bP, aQ, bQ;
-          rr_pair(P, round, Le, &aP, &bP);
-          rr_pair(Q, round, Le, &aQ, &bQ);
-          const bool vb = bP < L, wb = bQ < L;
-          const double kaa = K[aP + aQ * kLd];
-          const double kab = wb ? K[aP + bQ * kLd] : 0.0;
-          const double kba = vb ? K[bP + aQ * kLd] : 0.0;
-          const double kbb = (vb && wb) ? K[bP + bQ * kLd] : 0.0;
-          // right: columns (aQ, bQ) times J_Q
+          const int aP = pr[2 * P], bP = pr[2 * P + 1], aQ = pr[2 * Q], bQ = pr[2 * Q + 1];
+          const double kaa = K[aP + aQ * kLd], kab = K[aP + bQ * kLd];
+          const double kba = K[bP + aQ * kLd], kbb = K[bP + bQ * kLd];
           const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
           const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
-          // left: rows (aP, bP) times J_P^T
           K[aP + aQ * kLd] = cP * raa - sP * rba;
-          if (wb) K[aP + bQ * kLd] = cP * rab - sP * rbb;
-          if (vb) K[bP + aQ * kLd] = sP * raa + cP * rba;
-          if (vb && wb) K[bP + bQ * kLd] = sP * rab + cP * rbb;
+          K[aP + bQ * kLd] = cP * rab - sP * rbb;
+          K[bP + aQ * kLd] = sP * raa + cP * rba;
+          K[bP + bQ * kLd] = sP * rab + cP * rbb;
         } else {
           const int f = e - h * h;
-          const int i = f % L, Q = f / L;
+          const int i = f % Le, Q = f / Le;
           const double cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
-          if (sQ == 0.0) continue;
-          int aQ, bQ;
-          rr_pair(Q, round, Le, &aQ, &bQ);
+          const int aQ = pr[2 * Q], bQ = pr[2 * Q + 1];
           const double za = Z[i + aQ * kLd], zb = Z[i + bQ * kLd];
           Z[i + aQ * kLd] = cQ * za - sQ * zb;
           Z[i + bQ * kLd] = sQ * za + cQ * zb;
@@ -260,7 +514,7 @@ __device__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, d
 }
 
 // Rank decision (fixed r, or the smallest r with ||C||^2 - sum_{i<=r} s_i^2 <= eps_k^2).
-__device__ void decide_rank(const SolveArgs& a, const double* lam, int ell, double normC2,
+__device__ __forceinline__ void decide_rank(const SolveArgs& a, const double* lam, int ell, double normC2,
                             double normA2, int* out_r, int* out_sat, double* out_kept) {
   int r, sat;
   if (a.r_fixed > 0) {
@@ -288,9 +542,10 @@ __device__ void decide_rank(const SolveArgs& a, const double* lam, int ell, doub
 
 // Column signs: largest-magnitude entry of every column of V (n x r) positive,
 // lowest row on ties; one wave per column.
-__device__ void canonical_signs(const double* V, int64_t si, int64_t sa, int n, int r, double* sg) {
+template <int NT>
+__device__ __forceinline__ void canonical_signs(const double* V, int64_t si, int64_t sa, int n, int r, double* sg) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int a = w; a < r; a += kThreads / 64) {
+  for (int a = w; a < r; a += NT / 64) {
     double best = -1.0, val = 0.0;
     int bi = 0x7fffffff;
     for (int i = lane; i < n; i += 64) {
@@ -318,7 +573,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
   __shared__ double sB0[kCMax * kLd];
   __shared__ double sB1[kCMax * kLd];
   __shared__ double sK[kCMax * kLd];
-  __shared__ double lam[kCMax], tau[kCMax], scal[kCMax], rot[64], sg[kCMax], sh[32];
+  __shared__ double lam[kCMax], tau[kCMax], scal[kCMax], rot[96], sg[kCMax], sh[32];
+  __shared__ double vbuf[2 * 64 * 4 + kCMax];   // register Householder with R = 4, tpj <= 64
   __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
@@ -350,7 +606,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
         T[i + j * kLd] = s;
       }
       __syncthreads();
-      householder_inplace(T, kLd, n, L, tau, scal);
+      // n <= 64: at most 4 rows per thread
+      switch (reg_group_width(L)) {
+        case 16: householder_reg<4, 16>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
+        case 32: householder_reg<4, 32>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
+        default: householder_reg<4, 64>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
+      }
       double* tmp = X; X = T; T = tmp;
     }
   }
@@ -376,7 +637,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
   }
   __syncthreads();
   double* sZ = sH;  // H is no longer needed
-  const int sweeps = jacobi_eig(sK, sZ, L, lam, perm, rot, sh, &flag);
+  const int sweeps = jacobi_eig<kThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -394,7 +655,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     T[i + c * kLd] = s;
   }
   __syncthreads();
-  canonical_signs(T, 1, kLd, n, r, sg);
+  canonical_signs<kThreads>(T, 1, kLd, n, r, sg);
   for (int e = t; e < n * r; e += kThreads) {
     const int i = e % n, c = e / n;
     const double v = T[i + c * kLd] * sg[c];
@@ -420,7 +681,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
 // --------------------------------------------------------------------------
 // X = orth(M) for n x c blocks; LDS-resident when it fits, else in place in
 // global memory (M is overwritten by the reflectors).
-constexpr int kOrthLdsDoubles = 19456;   // 152 KB: n x c blocks up to this size stay in LDS
+constexpr int kOrthLdsDoubles = 19456;
+constexpr int kRegMaxN = 64 * 16;   // largest padded n of the register path (tpj <= 64, R <= 16)   // 152 KB: n x c blocks up to this size stay in LDS
 
 __global__ __launch_bounds__(kThreads) void k_orth(double* M, double* X, int n, int c) {
   __shared__ double buf[kOrthLdsDoubles];
@@ -438,27 +700,50 @@ __global__ __launch_bounds__(kThreads) void k_orth(double* M, double* X, int n, 
   }
 }
 
+// Register-resident variant for n <= R * tpj (one kernel per R so that each
+// allocates only the registers it needs).
+template <int R, int TPJ>
+__global__ __launch_bounds__(kThreads) void k_orth_reg(const double* M, double* X, int n, int c) {
+  __shared__ double vbuf[2 * R * TPJ + kCMax];
+  if constexpr (R <= 8) {
+    householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf);
+  } else {
+    __shared__ double wcols[R * kThreads];   // (kThreads / TPJ) columns of R * TPJ rows
+    householder_lds<R, TPJ>(M, 1, n, X, c, 1, n, c, wcols, vbuf);
+  }
+}
+
+template <int R>
+static void launch_orth_reg(double* M, double* X, int n, int c, hipStream_t st) {
+  const int tpj = reg_group_width(c);
+  if (tpj == 16) hipLaunchKernelGGL((k_orth_reg<R, 16>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  else if (tpj == 32) hipLaunchKernelGGL((k_orth_reg<R, 32>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  else hipLaunchKernelGGL((k_orth_reg<R, 64>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+}
+
 // --------------------------------------------------------------------------
 // Rayleigh-Ritz on span(X) from K = Y^T Y (Y = A X): eigen-decomposition
 // K = Z diag(lam) Z^T, rank decision, V1 = X Z_r (core side), W = Z_r so that
 // the carry A V1 equals Y W.
-__global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict__ K,
-                                                       const double* __restrict__ X, SolveArgs a) {
+constexpr int kRRThreads = 1024;  // measured: 16 waves finish a Jacobi round faster than 4
+
+__global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restrict__ K,
+                                                         const double* __restrict__ X, SolveArgs a) {
   __shared__ double sK[kCMax * kLd];
   __shared__ double sZ[kCMax * kLd];
-  __shared__ double lam[kCMax], rot[64], sg[kCMax], sh[32];
+  __shared__ double lam[kCMax], rot[96], sg[kCMax], sh[32];
   __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
   const int n = a.n;
   const int L = a.ell;
-  for (int e = t; e < L * L; e += kThreads) {
+  for (int e = t; e < L * L; e += kRRThreads) {
     const int i = e % L, j = e / L;
     sK[i + j * kLd] = 0.5 * (K[i + (int64_t)L * j] + K[j + (int64_t)L * i]);
   }
   if (t == 0) snormC2 = *a.normC2_src;
   __syncthreads();
-  const int sweeps = jacobi_eig(sK, sZ, L, lam, perm, rot, sh, &flag);
+  const int sweeps = jacobi_eig<kRRThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -467,7 +752,7 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
   }
   __syncthreads();
   const int r = sr;
-  for (int64_t e = t; e < (int64_t)n * r; e += kThreads) {
+  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
     const int i = (int)(e / r), c = (int)(e % r);
     const int pc = perm[c];
     double s = 0.0;
@@ -476,8 +761,8 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
   }
   __threadfence_block();
   __syncthreads();
-  canonical_signs(a.V1, r, 1, n, r, sg);
-  for (int64_t e = t; e < (int64_t)n * r; e += kThreads) {
+  canonical_signs<kRRThreads>(a.V1, r, 1, n, r, sg);
+  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
     const int i = (int)(e / r), c = (int)(e % r);
     const double v = a.V1[e] * sg[c];
     a.V1[e] = v;
@@ -486,7 +771,7 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
       else a.core[c + (int64_t)r * i] = v;
     }
   }
-  for (int e = t; e < L * r; e += kThreads) {
+  for (int e = t; e < L * r; e += kRRThreads) {
     const int k = e / r, c = e % r;
     a.W[(int64_t)k * r + c] = sZ[k + perm[c] * kLd] * sg[c];   // k-major
   }
@@ -500,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void k_rr_solve(const double* __restrict_
     rec->resid2 = -1.0;
     rec->sweeps = sweeps;
   }
-  for (int i = t; i < kCMax; i += kThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
+  for (int i = t; i < kCMax; i += kRRThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
 }
 
 }  // namespace
@@ -520,13 +805,18 @@ hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st) {
 
 hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || c > n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_orth, dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  switch (reg_rows(n, c)) {
+    case 4: launch_orth_reg<4>(M, X, n, c, st); break;
+    case 8: launch_orth_reg<8>(M, X, n, c, st); break;
+    case 16: launch_orth_reg<16>(M, X, n, c, st); break;
+    default: hipLaunchKernelGGL(k_orth, dim3(1), dim3(kThreads), 0, st, M, X, n, c); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st) {
   if (a.n < 1 || a.ell < 1 || a.ell > kCMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rr_solve, dim3(1), dim3(kThreads), 0, st, K, X, a);
+  hipLaunchKernelGGL(k_rr_solve, dim3(1), dim3(kRRThreads), 0, st, K, X, a);
   return hipGetLastError();
 }
 

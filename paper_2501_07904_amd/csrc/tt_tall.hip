@@ -112,40 +112,78 @@ __global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, cons
 }
 
 // ---------------------------------------------------------------------------
-// Y = A W with W (n x c) stored k-major (row k = the c contiguous doubles
-// W[k*c .. k*c+c)).  One thread per row of A: it streams the row once and
-// keeps the c outputs in registers; W is read with wave-uniform addresses, so
-// it comes through the scalar cache and never occupies LDS.
-template <typename TA, typename TY, int CB>
+// Y = A W on the FP64 matrix cores.  W (n x c) is k-major (row k = c
+// contiguous doubles).  A workgroup (4 waves) owns a 64-row tile; wave w owns
+// rows 16w..16w+15 and computes the 16 x 16*NT block of Y with
+// v_mfma_f64_16x16x4 (operand A: lane l holds row l%16 at k-slot l/16;
+// operand B: lane l holds column l%16 at k-slot l/16; result: lane l,
+// register v holds row l/16 + 4v, column l%16).  The k-slots are mapped to
+// contiguous k: in a 32-wide k block, lanes of group g = l/16 take
+// k = 8g .. 8g+7 over eight consecutive MFMAs, so every lane streams eight
+// consecutive elements of its row (ROW layout) and every group of 16 lanes
+// reads 16 consecutive rows (COL layout).  W is staged 64 k at a time in LDS.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kAxKC = 64;
+
+template <typename TA, typename TY, int NT>
 __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
                                                  TY* __restrict__ Y, int64_t m, int n, int c,
                                                  int layout, double* __restrict__ sumsqA,
                                                  double* __restrict__ sumsqY) {
+  __shared__ double sW[kAxKC][NT * 16 + 1];
   __shared__ double sh[8];
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
   double ssa = 0.0, ssy = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
-    double acc[CB];
+  for (int64_t tile = blockIdx.x; tile * 64 < m; tile += gridDim.x) {
+    const int64_t row = tile * 64 + 16 * w + li;
+    const bool rok = row < m;
+    d4 acc[NT];
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc[u] = 0.0;
-    const TA* a = (layout == COL) ? A + i : A + i * n;
-    const int64_t ks = (layout == COL) ? m : 1;
-#pragma unroll 8
-    for (int k = 0; k < n; ++k) {
-      const double x = (double)a[(int64_t)k * ks];
-      ssa = fma(x, x, ssa);
-      const double* w = W + (int64_t)k * c;
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += kAxKC) {
+      const int kc = min(kAxKC, n - k0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < kAxKC * NT * 16; e += kThreads) {
+        const int kk = e / (NT * 16), cc = e % (NT * 16);
+        sW[kk][cc] = (kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+      }
+      __syncthreads();
 #pragma unroll
-      for (int u = 0; u < CB; ++u)
-        if (u < c) acc[u] = fma(x, w[u], acc[u]);
+      for (int ss = 0; ss < kAxKC / 32; ++ss) {
+        const int kb = 32 * ss + 8 * g;
+        double a[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          const int k = k0 + kb + s8;
+          double x = 0.0;
+          if (rok && k < n) x = (double)A[layout == ROW ? row * n + k : row + (int64_t)k * m];
+          ssa = fma(x, x, ssa);
+          a[s8] = x;
+        }
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(a[s8], sW[kb + s8][16 * t + li], acc[t]);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      if (u < c) {
-        const TY y = (TY)acc[u];
-        const double yd = (double)y;
-        ssy = fma(yd, yd, ssy);
-        Y[at(layout, i, u, m, c)] = y;
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t yr = tile * 64 + 16 * w + g + 4 * v;
+        const int col = 16 * t + li;
+        if (yr < m && col < c) {
+          const TY y = (TY)acc[t][v];
+          const double yd = (double)y;
+          ssy = fma(yd, yd, ssy);
+          Y[at(layout, yr, col, m, c)] = y;
+        }
       }
     }
   }
@@ -157,78 +195,6 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
     const double s = block_sum(ssy, sh);
     if (threadIdx.x == 0) sumsqY[blockIdx.x] = s;
   }
-}
-
-// Same product when there are too few rows to fill the chip: a workgroup
-// owns 64 rows (one per lane) and splits the n columns of A over its KS
-// waves; the KS partial rows are summed in LDS in a fixed order, 8 output
-// columns at a time.
-template <typename TA, typename TY, int CB, int KS>
-__global__ __launch_bounds__(64 * KS) void k_ax_split(const TA* __restrict__ A, const double* __restrict__ W,
-                                                     TY* __restrict__ Y, int64_t m, int n, int c,
-                                                     int layout, double* __restrict__ sumsqA,
-                                                     double* __restrict__ sumsqY) {
-  __shared__ double red[KS][64][9];
-  __shared__ double sh[KS];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  const bool row_ok = i < m;
-  const int kper = (n + KS - 1) / KS;
-  const int k0 = w * kper, k1 = min(n, k0 + kper);
-  double acc[CB];
-#pragma unroll
-  for (int u = 0; u < CB; ++u) acc[u] = 0.0;
-  double ssa = 0.0, ssy = 0.0;
-  if (row_ok) {
-    const TA* a = (layout == COL) ? A + i : A + i * n;
-    const int64_t ks = (layout == COL) ? m : 1;
-#pragma unroll 8
-    for (int k = k0; k < k1; ++k) {
-      const double x = (double)a[(int64_t)k * ks];
-      ssa = fma(x, x, ssa);
-      const double* wr = W + (int64_t)k * c;
-#pragma unroll
-      for (int u = 0; u < CB; ++u)
-        if (u < c) acc[u] = fma(x, wr[u], acc[u]);
-    }
-  }
-#pragma unroll
-  for (int u0 = 0; u0 < CB; u0 += 8) {
-    if (u0 >= c) break;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) red[w][lane][u] = acc[u0 + u < CB ? u0 + u : 0];
-    __syncthreads();
-    if (w == 0 && row_ok) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (u0 + u < c) {
-          double s = 0.0;
-          for (int q = 0; q < KS; ++q) s += red[q][lane][u];
-          const TY y = (TY)s;
-          const double yd = (double)y;
-          ssy = fma(yd, yd, ssy);
-          Y[at(layout, i, u0 + u, m, c)] = y;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // fixed-order block sums of the squares
-  for (int o = 32; o > 0; o >>= 1) {
-    ssa += __shfl_xor(ssa, o, 64);
-    ssy += __shfl_xor(ssy, o, 64);
-  }
-  if (sumsqA) {
-    if (lane == 0) sh[w] = ssa;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < KS; ++q) s += sh[q];
-      sumsqA[blockIdx.x] = s;
-    }
-    __syncthreads();
-  }
-  if (sumsqY && threadIdx.x == 0) sumsqY[blockIdx.x] = ssy;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,48 +298,25 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
   return hipGetLastError();
 }
 
-// Split factor over the columns of A: 1 (one thread per row) when the rows
-// alone give enough waves, else 4, 8 or 16 waves per 64 rows.
-static int ax_split(int64_t m, int n) {
-  const int64_t row_waves = (m + 63) / 64;
-  if (row_waves >= 8192 || n < 64) return 1;
-  int ks = 4;
-  while (ks < 16 && row_waves * ks < 8192 && n / (2 * ks) >= 16) ks *= 2;
-  return ks;
-}
-
 int ax_chunks(int64_t m, int n, int c) {
+  (void)n;
   (void)c;
-  if (ax_split(m, n) > 1) return (int)((m + 63) / 64);
-  const int64_t blocks = (m + kThreads - 1) / kThreads;
-  return (int)(blocks < 2048 ? blocks : 2048);
-}
-
-template <typename TA, typename TY, int CB>
-static void ax_dispatch_cb(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
-                           int nchunks, double* sumsqA, double* sumsqY, hipStream_t st) {
-  const int ks = ax_split(m, n);
-  if (ks == 1)
-    hipLaunchKernelGGL((k_ax<TA, TY, CB>), dim3(nchunks), dim3(kThreads), 0, st, A, W, Y, m, n, c, layout,
-                       sumsqA, sumsqY);
-  else if (ks == 4)
-    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 4>), dim3(nchunks), dim3(256), 0, st, A, W, Y, m, n, c,
-                       layout, sumsqA, sumsqY);
-  else if (ks == 8)
-    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 8>), dim3(nchunks), dim3(512), 0, st, A, W, Y, m, n, c,
-                       layout, sumsqA, sumsqY);
-  else
-    hipLaunchKernelGGL((k_ax_split<TA, TY, CB, 16>), dim3(nchunks), dim3(1024), 0, st, A, W, Y, m, n, c,
-                       layout, sumsqA, sumsqY);
+  const int64_t tiles = (m + 63) / 64;
+  return (int)(tiles < 8192 ? tiles : 8192);
 }
 
 template <typename TA, typename TY>
 static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
                         int nchunks, double* sumsqA, double* sumsqY, hipStream_t st) {
-  if (c <= 8) ax_dispatch_cb<TA, TY, 8>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
-  else if (c <= 16) ax_dispatch_cb<TA, TY, 16>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
-  else if (c <= 32) ax_dispatch_cb<TA, TY, 32>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
-  else ax_dispatch_cb<TA, TY, 64>(A, W, Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+  dim3 grid(nchunks), block(kThreads);
+  if (c <= 16)
+    hipLaunchKernelGGL((k_ax<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+  else if (c <= 32)
+    hipLaunchKernelGGL((k_ax<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+  else if (c <= 48)
+    hipLaunchKernelGGL((k_ax<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+  else
+    hipLaunchKernelGGL((k_ax<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
 }
 
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m, int n,
