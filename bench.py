@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="order5_32_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, copy the input tensor once (a kernel of known "
+                         "traffic: its bytes read and written) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -82,6 +85,12 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = tensor_bytes / (ms_per_step * 1e-3) / 1e9
+    if args.copy_probe:
+        B = torch.empty_like(A)
+        B.copy_(A)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe moved {tensor_bytes} bytes read + {tensor_bytes} bytes written")
+        del B
     rep = dec.report()
     cores = dec.cores()
     rec = T.tt_reconstruct(cores)

@@ -68,7 +68,16 @@ typedef struct {
                                default (1/sqrt(d-1); 1/(d-1) for Alg. 4) */
   int32_t profile;          /* 1: time every kernel launch with HIP events on the
                                caller's stream and fill tt_report.kstat */
+  int32_t prec;             /* tt_prec: TT_PREC_FP64 or TT_PREC_MIXED */
 } tt_opts;
+
+/* TT_PREC_FP64: every carry, sketch and product in FP64.
+ * TT_PREC_MIXED: carries and power iterates stored in FP32 (half the traffic
+ * of every pass after the first), all accumulation in FP64; the final
+ * Rayleigh-Ritz pass, its Gram matrix, the factorisations and the rank rule
+ * stay FP64.  Storing carry k in FP32 perturbs it by rho_k (measured exactly);
+ * the report's err_bound is then sqrt(sum delta_k^2) + sum rho_k. */
+typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1 } tt_prec;
 
 /* Kernel classes of the profile (tt_kernel_class_name gives their names). */
 #define TT_NKCLASS 7
@@ -91,13 +100,14 @@ typedef struct {
   int32_t d;
   tt_kstat kstat[TT_NKCLASS];   /* filled when opts.profile = 1 */
   int32_t sweeps[TT_MAX_D];     /* Jacobi sweeps of the Rayleigh-Ritz step of unfolding k */
+  double rho[TT_MAX_D];         /* TT_PREC_MIXED: ||carry - fl32(carry)||_F of unfolding k */
 } tt_report;
 
 /* Name of kernel class c (0 <= c < TT_NKCLASS), or NULL. */
 const char* tt_kernel_class_name(int c);
 
 /* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
- * exact_delta = 0, weights = NULL, profile = 0. */
+ * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64. */
 void tt_default_opts(tt_opts* opts);
 
 /* Device bytes of workspace tt_utv_decompose needs for this problem.

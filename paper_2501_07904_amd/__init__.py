@@ -34,7 +34,8 @@ class TTError(RuntimeError):
 class tt_opts(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("max_rank", ctypes.c_int32), ("exact_delta", ctypes.c_int32),
-                ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32)]
+                ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32),
+                ("prec", ctypes.c_int32)]
 
 
 TT_NKCLASS = 7
@@ -50,7 +51,8 @@ class tt_report(ctypes.Structure):
                 ("delta", ctypes.c_double * TT_MAX_D), ("normC", ctypes.c_double * TT_MAX_D),
                 ("norm_A", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("rank_rule_met", ctypes.c_int32), ("d", ctypes.c_int32),
-                ("kstat", tt_kstat * TT_NKCLASS), ("sweeps", ctypes.c_int32 * TT_MAX_D)]
+                ("kstat", tt_kstat * TT_NKCLASS), ("sweeps", ctypes.c_int32 * TT_MAX_D),
+                ("rho", ctypes.c_double * TT_MAX_D)]
 
 
 _lib = None
@@ -119,11 +121,16 @@ def _full_ranks(ranks, d):
     return r
 
 
-def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False):
+PRECS = {"fp64": 0, "mixed": 1}
+
+
+def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
+              prec="fp64"):
     o = tt_opts()
     load_library().tt_default_opts(ctypes.byref(o))
     o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
     o.profile = int(bool(profile))
+    o.prec = PRECS[prec]
     keep = None
     if weights is not None:
         keep = (ctypes.c_double * len(weights))(*[float(w) for w in weights])
@@ -149,7 +156,7 @@ def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dty
 
 def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
                      max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
-                     profile=False):
+                     profile=False, prec="fp64"):
     """TT-UTV of the device tensor A (float64/float32, flat in ivec order, i1
     fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
     float64 view of a column-major device buffer."""
@@ -162,7 +169,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
     d = len(dims)
     if (ranks is None) == (eps is None):
         raise ValueError("give exactly one of ranks and eps")
-    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile)
+    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec)
     rk = None if ranks is None else _i64(_full_ranks(ranks, d))
     epsv = -1.0 if eps is None else float(eps)
     nbytes = ctypes.c_size_t(0)
@@ -187,6 +194,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
         "norm_A": float(rep.norm_A), "err_bound": float(rep.err_bound),
         "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
         "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
+        "rho": [float(rep.rho[k]) for k in range(d - 1)],
     }
     if profile:
         report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
@@ -279,7 +287,7 @@ class Decomposer:
 
     def __init__(self, dims, dtype=torch.float64, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                  oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-                 device="cuda"):
+                 device="cuda", prec="fp64"):
         lib = load_library()
         self.lib = lib
         self.dims = [int(x) for x in dims]
@@ -288,7 +296,7 @@ class Decomposer:
             raise ValueError("give exactly one of ranks and eps")
         self.dtype = dtype
         self.profile = profile
-        self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile)
+        self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec)
         self._dims = _i64(self.dims)
         self._ranks = None if ranks is None else _i64(_full_ranks(ranks, d))
         self.eps = -1.0 if eps is None else float(eps)
@@ -324,7 +332,8 @@ class Decomposer:
                "delta": [float(rep.delta[k]) for k in range(d - 1)],
                "normC": [float(rep.normC[k]) for k in range(d - 1)], "norm_A": float(rep.norm_A),
                "err_bound": float(rep.err_bound), "rank_rule_met": bool(rep.rank_rule_met),
-               "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)]}
+               "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
+               "rho": [float(rep.rho[k]) for k in range(d - 1)]}
         if self.profile:
             out["kstat"] = {self.lib.tt_kernel_class_name(c).decode(): {
                 "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),

@@ -101,6 +101,7 @@ struct Problem {
   tt_opts o;
   double w[TT_MAX_D];
   bool alg4;
+  bool mixed;   // carries and power iterates stored in FP32
 };
 
 int64_t prod(const int64_t* v, int a, int b) {  // v[a] * ... * v[b-1]
@@ -128,6 +129,8 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
   if (P.o.oversample < 0 || P.o.oversample > TT_MAX_ELL)
     return fail(TT_EINVAL, "oversample = %d outside [0, %d]", P.o.oversample, TT_MAX_ELL);
   if (P.o.max_rank < 0) return fail(TT_EINVAL, "max_rank < 0");
+  if (P.o.prec != TT_PREC_FP64 && P.o.prec != TT_PREC_MIXED) return fail(TT_EINVAL, "bad prec %d", P.o.prec);
+  P.mixed = (P.o.prec == TT_PREC_MIXED);
   P.sweep = sweep;
   P.variant = variant;
   P.dtype = dtype;
@@ -269,7 +272,7 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
     // (atb_chunks(m, n, c) * n <= 1024 * 64 for every n, so 65536 * kCMax covers any
     // shape a prescribed-accuracy step can take)
     if (!P.fixed) z.part = std::max<int64_t>(z.part, (int64_t)65536 * kCMax);
-    z.part = std::max<int64_t>(z.part, 8192);   // per-workgroup sums of k_ax (<= 8192 groups)
+    z.part = std::max<int64_t>(z.part, 2 * 8192);   // two per-workgroup sums of k_ax (<= 8192 groups each)
   }
   return z;
 }
@@ -314,7 +317,8 @@ int check_limits(const Problem& P, const std::vector<Step>& S) {
 struct StepIO {
   const void* A;
   int a_f32;
-  double* out;       // carry (next A) or the last core
+  void* out;         // carry (next A) or the last core
+  int out_f32;       // carry stored in FP32 (mixed precision, not the last core)
   double* core;      // core buffer of this step
 };
 
@@ -362,21 +366,24 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     const double mc = (double)m * c;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
     for (int it = 0; it <= P.o.q; ++it) {
-      LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-             launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
-                       (first && it == 0) ? W.part : nullptr, nullptr, st));
+      // power iterates: FP32 storage in mixed precision
+      const double sy = P.mixed ? 4.0 : 8.0;
+      LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
+             launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,
+                       (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
       if (first && it == 0)
         LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
       const int nch = atb_chunks(m, n, c);
-      LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-             launch_atb(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, W.part, nch, st));
+      LAUNCH(PF, KC_ATB, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
+             launch_atb(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, W.part, nch, st));
       LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
              launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
     }
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
+    // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank)
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, st));
+           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, nullptr, st));
     const int kch = atb_chunks(m, c, c);
     LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
            launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, W.part, kch, st));
@@ -395,22 +402,25 @@ int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io
   const int64_t m = s.m;
   const int ach = step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r);
   const double sa = io.a_f32 ? 4.0 : 8.0;
+  const double so = io.out_f32 ? 4.0 : 8.0;
   const double mr = (double)m * r;
+  double* rerr = io.out_f32 ? W.part + 8192 : nullptr;
   if (step_gram(P, s)) {
     const double mn = (double)m * s.n;
-    LAUNCH(PF, KC_CARRY, mn * sa + mr * 8 + (double)s.n * r * 8, 2.0 * mn * r,
-           launch_ax(io.A, io.a_f32, W.V1, io.out, 0, m, s.n, r, s.layout, ach, nullptr, W.part, st));
+    LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)s.n * r * 8, 2.0 * mn * r,
+           launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, W.part, rerr, st));
   } else {
     const double ml = (double)m * ell;
-    LAUNCH(PF, KC_CARRY, ml * 8 + mr * 8 + (double)ell * r * 8, 2.0 * ml * r,
-           launch_ax(W.Y, 0, W.W, io.out, 0, m, ell, r, s.layout, ach, nullptr, W.part, st));
+    LAUNCH(PF, KC_CARRY, ml * 8 + mr * so + (double)ell * r * 8, 2.0 * ml * r,
+           launch_ax(W.Y, 0, W.W, io.out, io.out_f32, m, ell, r, s.layout, ach, nullptr, W.part, rerr, st));
   }
   LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, &rec->carry2, nullptr, st));
+  if (rerr) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(rerr, ach, 1, &rec->rho2, nullptr, st));
   if (P.o.exact_delta) {
     const int rch = resid_chunks(m);
     const double mn = (double)m * s.n;
-    LAUNCH(PF, KC_RESID, mn * sa + mr * 8, 2.0 * mn * r + 2.0 * mn,
-           launch_resid(io.A, io.a_f32, io.out, W.V1, m, s.n, r, s.layout, rch, W.part, st));
+    LAUNCH(PF, KC_RESID, mn * sa + mr * so, 2.0 * mn * r + 2.0 * mn,
+           launch_resid(io.A, io.a_f32, io.out, io.out_f32, W.V1, m, s.n, r, s.layout, rch, W.part, st));
     LAUNCH(PF, KC_REDUCE, (double)rch * 8, rch, launch_reduce(W.part, rch, 1, &rec->resid2, nullptr, st));
   }
   return TT_OK;
@@ -509,7 +519,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     io.a_f32 = a_f32;
     io.core = cores[s.core - 1];
     const int final_core = (P.sweep == TT_L2R) ? d - 1 : 0;
-    io.out = last ? cores[final_core] : W.carry[si & 1];
+    io.out = last ? (void*)cores[final_core] : (void*)W.carry[si & 1];
+    io.out_f32 = (P.mixed && !last) ? 1 : 0;
     int ell = step_ell(P, s, first ? 2 * P.o.oversample : prev_r + P.o.oversample);
     if (ell < 1) ell = 1;
     if (ell > TT_MAX_ELL) ell = TT_MAX_ELL;
@@ -536,7 +547,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     if (P.sweep == TT_L2R) r_run[s.core] = r; else r_run[s.core - 1] = r;
     prev_r = r;
     curA = io.out;
-    a_f32 = 0;
+    a_f32 = io.out_f32;
   }
   HIP_OK(hipMemcpyAsync(host.data(), W.recs, sizeof(StepRec) * nsteps, hipMemcpyDeviceToHost, st));
   double nA2 = 0.0;
@@ -547,7 +558,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     rep->d = d;
     for (int k = 0; k <= d; ++k) rep->ranks[k] = r_run[k];
     rep->ranks[0] = rep->ranks[d] = 1;
-    double sum2 = 0.0, sum1 = 0.0;
+    double sum2 = 0.0, sum1 = 0.0, rho_sum = 0.0;
     std::vector<Step> S2;
     plan_steps(P, r_run, S2, nullptr);
     for (int si = 0; si < nsteps; ++si) {
@@ -559,6 +570,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       rep->normC[u] = sqrt(std::max(h.normC2, 0.0));
       rep->ell[u] = ells[si];
       rep->sweeps[u] = h.sweeps;
+      rep->rho[u] = sqrt(std::max(h.rho2, 0.0));
+      rho_sum += rep->rho[u];
       sum2 += dl2;
       sum1 += sqrt(dl2);
       if (!P.fixed && !h.sat) all_sat = false;
@@ -573,7 +586,10 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       k.bytes += pr.bytes;
       k.flops += pr.flops;
     }
-    rep->err_bound = P.alg4 ? sum1 : sqrt(sum2);
+    // storing a carry in FP32 perturbs the matrix the rest of the sweep
+    // factorises by rho_k; the later steps are norm-non-increasing, so the
+    // perturbations add to the bound of the exact sweep
+    rep->err_bound = (P.alg4 ? sum1 : sqrt(sum2)) + rho_sum;
     rep->rank_rule_met = P.fixed ? 1 : (all_sat ? 1 : 0);
   }
   if (!isfinite(nA2)) return fail(TT_ENONFINITE, "input holds non-finite values (||A||^2 = %g)", nA2);

@@ -21,6 +21,7 @@ struct StepRec {
   double kept2;     // sum_{i<=r} s_i^2 (energy of the rank-r part)
   double carry2;    // ||carry||_F^2 as measured on the written carry
   double resid2;    // ||C - C_r||_F^2 measured directly (exact_delta), else -1
+  double rho2;      // ||carry - fl32(carry)||_F^2 when the carry is stored in FP32
   double lam[kCMax];// squared singular values of the ell x ell triangle, descending
   int32_t r;        // rank chosen
   int32_t sat;      // eps rule met (1) / not met (0); 1 for fixed ranks
@@ -38,13 +39,14 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
 int ax_chunks(int64_t m, int n, int c);
 // Y(i, cc) = sum_j A(i,j) W(j,cc), W k-major n x c (W(j,cc) at j*c + cc, FP64); Y in `layout`.
 // If sumsqA != NULL, sumsqA[ch] = sum of squares of the A entries read by chunk ch.
-// If sumsqY != NULL, sumsqY[ch] = sum of squares of the Y entries written.
+// If sumsqY != NULL, sumsqY[ch] = sum of squares of the Y entries written (as stored).
+// If rerr != NULL, rerr[ch] = sum of squares of (FP64 result - stored FP32 value).
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m,
                      int n, int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
-                     hipStream_t st);
+                     double* rerr, hipStream_t st);
 // resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r k-major.
 int resid_chunks(int64_t m);
-hipError_t launch_resid(const void* A, int a_f32, const double* Cr, const double* V1, int64_t m,
+hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, const double* V1, int64_t m,
                         int n, int r, int layout, int nchunks, double* resid, hipStream_t st);
 // out[e] (+ out2[e] if out2) = sum_ch partials[ch*size + e], fixed order.
 hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,

@@ -673,6 +673,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     rec->sat = ssat;
     rec->ell = L;
     rec->resid2 = -1.0;
+    rec->rho2 = 0.0;
     rec->sweeps = sweeps;
   }
   for (int i = t; i < kCMax; i += kThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
@@ -783,6 +784,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
     rec->sat = ssat;
     rec->ell = L;
     rec->resid2 = -1.0;
+    rec->rho2 = 0.0;
     rec->sweeps = sweeps;
   }
   for (int i = t; i < kCMax; i += kRRThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;

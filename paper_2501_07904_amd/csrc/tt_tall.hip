@@ -134,12 +134,12 @@ template <typename TA, typename TY, int NT>
 __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
                                                  TY* __restrict__ Y, int64_t m, int n, int c,
                                                  int layout, double* __restrict__ sumsqA,
-                                                 double* __restrict__ sumsqY) {
+                                                 double* __restrict__ sumsqY, double* __restrict__ rerr) {
   __shared__ double sW[kAxKC][NT * 16 + 1];
   __shared__ double sh[8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
-  double ssa = 0.0, ssy = 0.0;
+  double ssa = 0.0, ssy = 0.0, sse = 0.0;
   for (int64_t tile = blockIdx.x; tile * 64 < m; tile += gridDim.x) {
     const int64_t row = tile * 64 + 16 * w + li;
     const bool rok = row < m;
@@ -182,6 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
           const TY y = (TY)acc[t][v];
           const double yd = (double)y;
           ssy = fma(yd, yd, ssy);
+          const double e = acc[t][v] - yd;
+          sse = fma(e, e, sse);
           Y[at(layout, yr, col, m, c)] = y;
         }
       }
@@ -195,6 +197,10 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
     const double s = block_sum(ssy, sh);
     if (threadIdx.x == 0) sumsqY[blockIdx.x] = s;
   }
+  if (rerr) {
+    const double s = block_sum(sse, sh);
+    if (threadIdx.x == 0) rerr[blockIdx.x] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -203,8 +209,8 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
 constexpr int kResTR = 64;
 constexpr int kAxKT = 32;
 
-template <typename TA>
-__global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, const double* __restrict__ Cr,
+template <typename TA, typename TC>
+__global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, const TC* __restrict__ Cr,
                                                     const double* __restrict__ V1, int64_t m, int n,
                                                     int r, int layout, int64_t rows_per_chunk,
                                                     double* __restrict__ resid) {
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, co
     for (int e = t; e < tr * r; e += kThreads) {
       int i, a;
       if (layout == ROW) { i = e / r; a = e % r; } else { i = e % tr; a = e / tr; }
-      sC[i][a] = Cr[at(layout, rb + i, a, m, r)];
+      sC[i][a] = (double)Cr[at(layout, rb + i, a, m, r)];
     }
     for (int k0 = 0; k0 < n; k0 += kAxKT) {
       const int kt = min(kAxKT, n - k0);
@@ -307,30 +313,30 @@ int ax_chunks(int64_t m, int n, int c) {
 
 template <typename TA, typename TY>
 static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
-                        int nchunks, double* sumsqA, double* sumsqY, hipStream_t st) {
+                        int nchunks, double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
   dim3 grid(nchunks), block(kThreads);
   if (c <= 16)
-    hipLaunchKernelGGL((k_ax<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+    hipLaunchKernelGGL((k_ax<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
   else if (c <= 32)
-    hipLaunchKernelGGL((k_ax<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+    hipLaunchKernelGGL((k_ax<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
   else if (c <= 48)
-    hipLaunchKernelGGL((k_ax<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+    hipLaunchKernelGGL((k_ax<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
   else
-    hipLaunchKernelGGL((k_ax<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY);
+    hipLaunchKernelGGL((k_ax<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
 }
 
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m, int n,
-                     int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
+                     int c, int layout, int nchunks, double* sumsqA, double* sumsqY, double* rerr,
                      hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks != ax_chunks(m, n, c)) return hipErrorInvalidValue;
   if (!a_f32 && !y_f32)
-    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else if (a_f32 && !y_f32)
-    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else if (a_f32 && y_f32)
-    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else
-    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, st);
+    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   return hipGetLastError();
 }
 
@@ -339,16 +345,19 @@ int resid_chunks(int64_t m) {
   return (int)(tiles < 2048 ? tiles : 2048);
 }
 
-hipError_t launch_resid(const void* A, int a_f32, const double* Cr, const double* V1, int64_t m,
+hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, const double* V1, int64_t m,
                         int n, int r, int layout, int nchunks, double* resid, hipStream_t st) {
   if (n < 1 || r < 1 || r > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
   const int64_t rpc = (m + nchunks - 1) / nchunks;
-  if (a_f32)
-    hipLaunchKernelGGL((k_resid<float>), dim3(nchunks), dim3(kThreads), 0, st, (const float*)A, Cr,
-                       V1, m, n, r, layout, rpc, resid);
+  dim3 g(nchunks), b(kThreads);
+  if (a_f32 && c_f32)
+    hipLaunchKernelGGL((k_resid<float, float>), g, b, 0, st, (const float*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
+  else if (a_f32)
+    hipLaunchKernelGGL((k_resid<float, double>), g, b, 0, st, (const float*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
+  else if (c_f32)
+    hipLaunchKernelGGL((k_resid<double, float>), g, b, 0, st, (const double*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
   else
-    hipLaunchKernelGGL((k_resid<double>), dim3(nchunks), dim3(kThreads), 0, st, (const double*)A,
-                       Cr, V1, m, n, r, layout, rpc, resid);
+    hipLaunchKernelGGL((k_resid<double, double>), g, b, 0, st, (const double*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
   return hipGetLastError();
 }
 

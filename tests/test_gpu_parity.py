@@ -304,3 +304,49 @@ def test_sample_empty_and_large_index_range():
     cores = [_dev(c) for c in ttgen.gaussian_cores(dims, [1, 2, 1], 113)]
     out = T.tt_sample(cores, torch.zeros((0, 2), dtype=torch.int64, device="cuda"))
     assert out.numel() == 0
+
+
+# --------------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("sweep,variant", COMBOS)
+def test_mixed_fixed_rank_bound_and_agreement(sweep, variant):
+    """FP32 carries with FP64 accumulation: the stated bound sqrt(sum delta^2) +
+    sum rho holds, rho > 0 is measured, and the result stays within FP32
+    storage accuracy of the FP64 form (oracle-pinned above)."""
+    dims = [12, 11, 10, 9, 8]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [4, 6, 6, 4], 1e-3, 120)
+    A = _dev(a.astype(np.float32))
+    a32 = a.astype(np.float32).astype(np.float64)
+    c64, r64 = T.tt_utv_decompose(A, dims, ranks=[4, 5, 5, 4], sweep=sweep, variant=variant, q=2, exact_delta=True)
+    cmx, rmx = T.tt_utv_decompose(A, dims, ranks=[4, 5, 5, 4], sweep=sweep, variant=variant, q=2, exact_delta=True,
+                                  prec="mixed")
+    assert rmx["ranks"] == r64["ranks"]
+    # every carry but the last (which is written into an FP64 core) is rounded to FP32
+    last = len(dims) - 2 if sweep == "L2R" else 0
+    assert all((x > 0) == (k != last) for k, x in enumerate(rmx["rho"]))
+    assert all(x == 0 for x in r64["rho"])
+    rec64 = T.tt_reconstruct(c64).cpu().numpy()
+    recmx = T.tt_reconstruct(cmx).cpu().numpy()
+    err = np.linalg.norm(recmx - a32)
+    assert err <= rmx["err_bound"] * (1 + 1e-9)
+    assert np.linalg.norm(recmx - rec64) <= 1e-5 * np.linalg.norm(a32)
+
+
+def test_mixed_eps_1e6_function_tensor():
+    """C3 shape: 8^8 FP32, eps = 1e-6 with FP32 carries meets RSE <= eps and
+    stays within one rank of the FP64 form on every bond."""
+    a32 = ttgen.inverse_sum_tensor(8, 8, dtype=np.float32)
+    dims = [8] * 8
+    A = _dev(a32)
+    a = a32.astype(np.float64)
+    # exact_delta: the bound uses measured step errors (sqrt(||C||^2 - ||carry||^2)
+    # cancels at delta ~ 1e-6 ||C|| and is only an estimate there)
+    c64, r64 = T.tt_utv_decompose(A, dims, eps=1e-6, sweep="R2L", variant="URV", q=1, oversample=8, seed=3,
+                                  exact_delta=True)
+    cmx, rmx = T.tt_utv_decompose(A, dims, eps=1e-6, sweep="R2L", variant="URV", q=1, oversample=8, seed=3,
+                                  prec="mixed", exact_delta=True)
+    for cores, rep in ((c64, r64), (cmx, rmx)):
+        rec = T.tt_reconstruct(cores).cpu().numpy()
+        rse = np.linalg.norm(rec - a) / np.linalg.norm(a)
+        assert rse <= 1e-6
+        assert np.linalg.norm(rec - a) <= rep["err_bound"] * (1 + 1e-6) + 1e-12
+    assert max(abs(x - y) for x, y in zip(rmx["ranks"], r64["ranks"])) <= 1
