@@ -437,6 +437,10 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* Z, int L, double* l
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < NT / 64; ++i) dmax = fmax(dmax, sh[i]);
+  // rotations stop at the rounding floor: below 1e-15 of the largest diagonal
+  // entry and of the geometric mean of the pair's diagonal entries (looser
+  // floors were measured to cost eigenvector accuracy of small, well
+  // separated eigenvalues)
   const double abs_floor = 1e-300 + 1e-15 * dmax;
   __syncthreads();
   int* pr = (int*)(rot + 64);   // pair indices of the round: pr[2p], pr[2p+1]

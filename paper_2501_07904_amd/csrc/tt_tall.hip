@@ -252,6 +252,25 @@ __global__ __launch_bounds__(kThreads) void k_resid(const TA* __restrict__ A, co
 }
 
 // ---------------------------------------------------------------------------
+// Scalar case (size 1, e.g. sums of squares): 256 threads take fixed strided
+// slices of the partials, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(kThreads) void k_reduce_scalar(const double* __restrict__ partials, int nchunks,
+                                                            double* __restrict__ out, double* __restrict__ out2) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int ch = threadIdx.x; ch < nchunks; ch += kThreads) s += partials[ch];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    if (out2) out2[0] = red[0];
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int nchunks,
                                                      int64_t size, double* __restrict__ out,
                                                      double* __restrict__ out2) {
@@ -364,6 +383,10 @@ hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, con
 hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,
                          double* out2, hipStream_t st) {
   if (size < 1 || nchunks < 1) return hipErrorInvalidValue;
+  if (size == 1) {
+    hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(kThreads), 0, st, partials, nchunks, out, out2);
+    return hipGetLastError();
+  }
   const int64_t blocks = (size + 15) / 16;
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
                      size, out, out2);
