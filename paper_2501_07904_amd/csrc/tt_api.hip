@@ -232,6 +232,7 @@ bool step_gram(const Problem& P, const Step& s) { return !P.alg4 && s.n <= kGram
 struct Work {
   double* carry[2];
   double* Y;
+  double* U;   // second long-side buffer (Alg. 4 orthonormalisation)
   double* X;
   double* M;
   double* part;
@@ -247,12 +248,12 @@ struct Work {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Sizes {
-  int64_t carry, Y, X, part, V1;
+  int64_t carry, Y, U, X, part, V1;
 };
 
 // Upper bounds over every step (and every ell a prescribed-accuracy step may grow to).
 Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
-  Sizes z{1, 1, 1, 1, 1};
+  Sizes z{1, 1, 1, 1, 1, 1};
   for (size_t i = 0; i < S.size(); ++i) {
     const Step& s = S[i];
     const int64_t lim = std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
@@ -267,6 +268,10 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
       z.X = std::max(z.X, (int64_t)s.n * c);
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, c) * s.n * c);
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, c, c) * c * c);
+      if (P.alg4) {
+        z.U = std::max(z.U, s.m * (int64_t)c);
+        z.part = std::max(z.part, (int64_t)atb_chunks(s.n, c, c) * c * c);
+      }
     }
     // with eps the run-time n may fall to <= kGramMax and take the Gram path
     // (atb_chunks(m, n, c) * n <= 1024 * 64 for every n, so 65536 * kCMax covers any
@@ -289,6 +294,7 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.carry[0] = (double*)take(z.carry * 8);
   W.carry[1] = (double*)take(z.carry * 8);
   W.Y = (double*)take(z.Y * 8);
+  W.U = (double*)take(z.U * 8);
   W.X = (double*)take(z.X * 8);
   W.M = (double*)take(z.X * 8);
   W.part = (double*)take(z.part * 8);
@@ -392,7 +398,58 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     if (first) a.normC2_src = W.normA2;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_rr_solve(W.K, W.X, a, st));
   } else {
-    return fail(TT_EUNSUPPORTED, "ULV right-to-left sweep (Alg. 4) is not built yet");
+    // Alg. 4: X spans (A^T A)^q G, Y = A X spans the range sketch (A A^T)^q A G
+    const int c = ell;
+    const int ach = ax_chunks(m, n, c);
+    const double mc = (double)m * c;
+    bool need_norm = first;
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
+    for (int it = 0; it < P.o.q; ++it) {
+      const double sy = P.mixed ? 4.0 : 8.0;
+      LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
+             launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,
+                       need_norm ? W.part : nullptr, nullptr, nullptr, st));
+      if (need_norm) {
+        LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
+        need_norm = false;
+      }
+      const int nch = atb_chunks(m, n, c);
+      LAUNCH(PF, KC_ATB, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
+             launch_atb(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, W.part, nch, st));
+      LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+             launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
+    }
+    LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
+                     need_norm ? W.part : nullptr, nullptr, nullptr, st));
+    if (need_norm) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
+    // U = orth(Y): two eigen-based Cholesky-QR rounds, Y -> U (round 1) -> Y (round 2)
+    const int kch = atb_chunks(m, c, c);
+    const int ych = ax_chunks(m, c, c);
+    for (int round = 0; round < 2; ++round) {
+      double* src = round == 0 ? W.Y : W.U;
+      double* dst = round == 0 ? W.U : W.Y;
+      LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
+             launch_atb(src, 0, src, 0, m, c, c, s.layout, W.part, kch, st));
+      LAUNCH(PF, KC_REDUCE, (double)(kch + 1) * c * c * 8, (double)kch * c * c,
+             launch_reduce(W.part, kch, (int64_t)c * c, W.K, nullptr, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_alg4_basis(W.K, W.H, c, st));
+      LAUNCH(PF, KC_GRAM_Y, 2.0 * mc * 8 + (double)c * c * 8, 2.0 * mc * c,
+             launch_ax(src, 0, W.H, dst, 0, m, c, c, s.layout, ych, nullptr, nullptr, nullptr, st));
+    }
+    // Bt = A^T U (n x ell), E = Bt^T Bt
+    const int nch = atb_chunks(m, n, c);
+    LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+           launch_atb(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, W.part, nch, st));
+    LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+           launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+    const int ech = atb_chunks(n, c, c);
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_atb(W.M, 0, W.M, 0, n, c, c, COL, W.part, ech, st));
+    LAUNCH(PF, KC_REDUCE, (double)(ech + 1) * c * c * 8, (double)ech * c * c,
+           launch_reduce(W.part, ech, (int64_t)c * c, W.K, nullptr, st));
+    if (first) a.normC2_src = W.normA2;
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_alg4_solve(W.K, W.M, a, st));
   }
   return TT_OK;
 }

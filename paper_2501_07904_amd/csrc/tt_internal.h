@@ -79,6 +79,14 @@ hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st);
 // Rayleigh-Ritz on span(X) (X k-major): K = (A X)^T (A X) (ell x ell) -> rank,
 // V1 = X Z_r, W = Z_r.
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st);
+// Alg. 4 step, one round of the long-side orthonormalisation: T =
+// P Lambda^{-1/2} (ell x ell, k-major) from K = Y^T Y = P Lambda P^T, so that
+// Y T is orthonormal on the numerical span of Y.
+hipError_t launch_alg4_basis(const double* K, double* T, int ell, hipStream_t st);
+// Alg. 4 step, factorisation: from E = Bt^T Bt (ell x ell) and Bt = A^T U
+// (n x ell column-major, U orthonormal): rank, core V1 = Bt W_r S_r^{-1},
+// carry weights W_r S_r (ell x r k-major, carry = U W).
+hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs& a, hipStream_t st);
 
 // ---- train contractions (tt_train.hip) ------------------------------------
 // C (M x N) = A (M x K) B (K x N), all column-major, K <= kCMax; C is double or float.

@@ -55,7 +55,8 @@ __global__ void k_gen_sketch(double* G, SolveArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)a.n * a.ell) return;
   const int row = (int)(e / a.ell), j = (int)(e % a.ell);
-  G[e] = sketch_row_entry(a, row, j);   // k-major: G[row * ell + j]
+  // k-major: G[row * ell + j]; ell >= n means the exact step, G = I
+  G[e] = (a.ell >= a.n) ? (row == j ? 1.0 : 0.0) : sketch_row_entry(a, row, j);
 }
 
 // --------------------------------------------------------------------------
@@ -794,6 +795,108 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
   for (int i = t; i < kCMax; i += kRRThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
 }
 
+// --------------------------------------------------------------------------
+// Alg. 4 (ULV, right-to-left): range-side factorisation C ~ U L V^T with
+// U^T E = 0.  U is an orthonormal basis of Y = C X, found on the long side by
+// two rounds of an eigen-based Cholesky-QR: K = Y^T Y = P Lambda P^T,
+// T = P Lambda^{-1/2}, Y <- Y T.  Directions with Lambda at or below
+// 1e-14 Lambda_max (outside the numerical span) get a zero column; the
+// second round restores orthonormality lost to K's rounding.  Then
+// B^T = C^T U (one pass over C), B B^T = W S^2 W^T, V1 = B^T W_r S_r^{-1}
+// (core side) and the carry U W_r S_r (the part of C outside span(U), the
+// U2 L21 term, is not carried).
+//
+// k_alg4_basis: T (ell x ell, k-major: T(i,j) at i*ell + j) from K.
+__global__ __launch_bounds__(kRRThreads) void k_alg4_basis(const double* __restrict__ K,
+                                                           double* __restrict__ Tout, int L) {
+  __shared__ double sK[kCMax * kLd];
+  __shared__ double sZ[kCMax * kLd];
+  __shared__ double lam[kCMax], rot[96], sh[32];
+  __shared__ int perm[kCMax], flag;
+  const int t = threadIdx.x;
+  for (int e = t; e < L * L; e += kRRThreads) {
+    const int i = e % L, j = e / L;
+    sK[i + j * kLd] = 0.5 * (K[i + (int64_t)L * j] + K[j + (int64_t)L * i]);
+  }
+  __syncthreads();
+  jacobi_eig<kRRThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
+  const double lmax = fmax(lam[0], 0.0);
+  for (int e = t; e < L * L; e += kRRThreads) {
+    const int i = e / L, j = e % L;
+    const double lj = lam[j];
+    Tout[e] = (lj > 1e-14 * lmax && lj > 0.0) ? sZ[i + perm[j] * kLd] / sqrt(lj) : 0.0;
+  }
+}
+
+// k_alg4_solve: from E = Bt^T Bt (ell x ell) and Bt = C^T U (n x ell,
+// column-major): rank, V1 = Bt W_r S_r^{-1} (canonical signs), core, carry
+// weights W_r S_r (ell x r k-major, into a.W; carry = U a.W).
+__global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restrict__ E,
+                                                           const double* __restrict__ Bt, SolveArgs a) {
+  __shared__ double sE[kCMax * kLd];
+  __shared__ double sW[kCMax * kLd];
+  __shared__ double lam[kCMax], rot[96], sg[kCMax], sinv[kCMax], sh[32];
+  __shared__ int perm[kCMax], flag, sr, ssat;
+  __shared__ double skept, snormC2;
+  const int t = threadIdx.x;
+  const int n = a.n;
+  const int L = a.ell;
+  for (int e = t; e < L * L; e += kRRThreads) {
+    const int i = e % L, j = e / L;
+    sE[i + j * kLd] = 0.5 * (E[i + (int64_t)L * j] + E[j + (int64_t)L * i]);
+  }
+  if (t == 0) snormC2 = *a.normC2_src;
+  __syncthreads();
+  const int sweeps = jacobi_eig<kRRThreads>(sE, sW, L, lam, perm, rot, sh, &flag);
+  if (t == 0) {
+    int r, sat;
+    double kept;
+    decide_rank(a, lam, L, snormC2, *a.normA2, &r, &sat, &kept);
+    sr = r; ssat = sat; skept = kept;
+  }
+  if (t < L) {
+    const double sv = sqrt(fmax(lam[t], 0.0));
+    sinv[t] = sv > 0.0 ? 1.0 / sv : 0.0;
+  }
+  __syncthreads();
+  const int r = sr;
+  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
+    const int i = (int)(e / r), c = (int)(e % r);
+    const int pc = perm[c];
+    double s = 0.0;
+    for (int k = 0; k < L; ++k) s = fma(Bt[i + (int64_t)n * k], sW[k + pc * kLd], s);
+    a.V1[e] = s * sinv[c];
+  }
+  __threadfence_block();
+  __syncthreads();
+  canonical_signs<kRRThreads>(a.V1, r, 1, n, r, sg);
+  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
+    const int i = (int)(e / r), c = (int)(e % r);
+    const double v = a.V1[e] * sg[c];
+    a.V1[e] = v;
+    if (a.core) {
+      if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
+      else a.core[c + (int64_t)r * i] = v;
+    }
+  }
+  for (int e = t; e < L * r; e += kRRThreads) {
+    const int k = e / r, c = e % r;
+    a.W[(int64_t)k * r + c] = sW[k + perm[c] * kLd] * sqrt(fmax(lam[c], 0.0)) * sg[c];
+  }
+  if (t == 0) {
+    StepRec* rec = a.rec;
+    rec->normC2 = snormC2;
+    rec->kept2 = skept;
+    rec->r = r;
+    rec->sat = ssat;
+    rec->ell = L;
+    rec->resid2 = -1.0;
+    rec->rho2 = 0.0;
+    rec->sweeps = sweeps;
+  }
+  for (int i = t; i < kCMax; i += kRRThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
+}
+
 }  // namespace
 
 hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st) {
@@ -826,4 +929,17 @@ hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a,
   return hipGetLastError();
 }
 
+}  // namespace ttutv
+
+namespace ttutv {
+hipError_t launch_alg4_basis(const double* K, double* T, int ell, hipStream_t st) {
+  if (ell < 1 || ell > kCMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_alg4_basis, dim3(1), dim3(kRRThreads), 0, st, K, T, ell);
+  return hipGetLastError();
+}
+hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs& a, hipStream_t st) {
+  if (a.n < 1 || a.ell < 1 || a.ell > kCMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_alg4_solve, dim3(1), dim3(kRRThreads), 0, st, E, Bt, a);
+  return hipGetLastError();
+}
 }  // namespace ttutv

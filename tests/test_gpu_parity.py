@@ -88,6 +88,8 @@ def _run(a, dims, sweep, variant, ranks=None, eps=None, q=1, p=8, seed=0, dtype=
 
 
 COMBOS = [("R2L", "URV"), ("L2R", "ULV"), ("L2R", "URV")]
+ALG4 = ("R2L", "ULV")           # appendix sweep: ULV factors, right-to-left
+ALL = COMBOS + [ALG4]
 
 
 # --------------------------------------------------------------------- generator
@@ -98,14 +100,14 @@ def test_sketch_matches_oracle_spec():
     dims = [40, 30]
     rng = np.random.default_rng(1)
     a = rng.standard_normal(40 * 30)
-    for sweep, variant in COMBOS:
+    for sweep, variant in ALL:
         cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[5], q=0, p=3, seed=77)
         # a full-rank random matrix: the rank-5 subspace found by one sketch depends on G
         _compare(cores, oc, sweep, tol=1e-9)
 
 
 # --------------------------------------------------------------------- fixed ranks
-@pytest.mark.parametrize("sweep,variant", COMBOS)
+@pytest.mark.parametrize("sweep,variant", ALL)
 def test_c1_order4_16(sweep, variant):
     """16^4 Gaussian-TT tensor, ranks (1,4,6,4,1), noise 1e-8, q = 1."""
     dims = [16] * 4
@@ -117,9 +119,12 @@ def test_c1_order4_16(sweep, variant):
     np.testing.assert_allclose(rec, oracle.tt_reconstruct(oc), rtol=0, atol=TOL * np.max(np.abs(a)))
     np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
     assert rep["norm_A"] == pytest.approx(orep["norm_A"], rel=1e-13)
+    assert rep["err_bound"] == pytest.approx(orep["err_bound"], rel=1e-6)
+    # equality for the Pythagorean sweeps; the error itself is formed by cancellation
+    assert np.linalg.norm(rec - a) <= rep["err_bound"] * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("sweep,variant", COMBOS)
+@pytest.mark.parametrize("sweep,variant", ALL)
 def test_ragged_shapes(sweep, variant):
     """Extents and ranks that are not multiples of any tile; a step with n > 64
     (the sketched path) and one with m < n."""
@@ -145,12 +150,32 @@ def test_truncation_below_true_rank(sweep, variant):
     assert abs(err2 - rep["err_bound"] ** 2) <= 1e-8 * err2
 
 
+@pytest.mark.parametrize("q", [0, 1, 3])
+def test_alg4_truncation_sum_bound(q):
+    """Appendix sweep (ULV, right-to-left) with real truncation: the carry is
+    U_hat L11 without the U2 L21 term, so at q = 0 the result differs from
+    TT-URV's (checked on the oracle side) and must match the oracle's Alg. 4;
+    the error obeys the sum bound ||A - A_hat|| <= sum_k delta_k."""
+    dims = [9, 10, 8, 11]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [6, 8, 6], 1e-3, 102)
+    cores, rep, oc, orep = _run(a, dims, "R2L", "ULV", ranks=[3, 4, 3], q=q, p=6, exact_delta=True)
+    a_hat = T.tt_reconstruct(cores).cpu().numpy()
+    o_hat = oracle.tt_reconstruct(oc)
+    np.testing.assert_allclose(a_hat, o_hat, rtol=0, atol=1e-9 * np.max(np.abs(o_hat)))
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-8)
+    assert rep["err_bound"] == pytest.approx(sum(orep["delta"]), rel=1e-8)
+    assert np.linalg.norm(a_hat - a) <= rep["err_bound"]
+    if q == 0:
+        ou, _ = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep="R2L", variant="URV", q=0, p=6)
+        assert np.linalg.norm(oracle.tt_reconstruct(ou) - o_hat) > 1e-6 * np.linalg.norm(a)
+
+
 def test_exact_rank_no_noise_rank_deficient_sketch():
     """Exact TT-ranks and ell > rank: the sketch is rank-deficient; the
     Householder orthonormalisation keeps the basis orthonormal."""
     dims = [6, 70, 5, 8]
     a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 0.0, 103)
-    for sweep, variant in COMBOS:
+    for sweep, variant in ALL:
         A = _dev(a)
         cores, rep = T.tt_utv_decompose(A, dims, ranks=[3, 4, 3], sweep=sweep, variant=variant, q=1, oversample=8)
         rec = T.tt_reconstruct(cores).cpu().numpy()
@@ -170,7 +195,7 @@ def test_tt_svd_variant_small_n():
 def test_order2_matrix():
     rng = np.random.default_rng(5)
     a = rng.standard_normal(37 * 53)
-    for sweep, variant in COMBOS:
+    for sweep, variant in ALL:
         cores, rep, oc, orep = _run(a, [37, 53], sweep, variant, ranks=[6], q=2, p=4)
         _compare(cores, oc, sweep, tol=1e-9)
 
@@ -178,7 +203,7 @@ def test_order2_matrix():
 def test_unit_extents():
     dims = [1, 9, 1, 12, 1]
     a, _ = ttgen.gaussian_tt_tensor(dims, [1, 3, 3, 1], 1e-5, 105)
-    for sweep, variant in COMBOS:
+    for sweep, variant in ALL:
         cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=[1, 3, 3, 1], q=1)
         _compare(cores, oc, sweep)
 
@@ -205,7 +230,7 @@ def test_c2_full_size_order5_32():
 
 
 # --------------------------------------------------------------------- prescribed accuracy
-@pytest.mark.parametrize("sweep,variant", COMBOS)
+@pytest.mark.parametrize("sweep,variant", ALL)
 def test_eps_mode_function_tensor(sweep, variant):
     a = ttgen.inverse_sum_tensor(6, 8, dtype=np.float64)
     dims = [8] * 6
@@ -307,7 +332,7 @@ def test_sample_empty_and_large_index_range():
 
 
 # --------------------------------------------------------------------- mixed precision
-@pytest.mark.parametrize("sweep,variant", COMBOS)
+@pytest.mark.parametrize("sweep,variant", ALL)
 def test_mixed_fixed_rank_bound_and_agreement(sweep, variant):
     """FP32 carries with FP64 accumulation: the stated bound sqrt(sum delta^2) +
     sum rho holds, rho > 0 is measured, and the result stays within FP32
