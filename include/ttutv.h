@@ -66,8 +66,10 @@ typedef struct {
                                pass over C; 0: from ||C||^2 - ||carry||^2 */
   const double* weights;    /* host, d-1 entries with sum w_k^2 = 1, or NULL for the
                                default (1/sqrt(d-1); 1/(d-1) for Alg. 4) */
-  int32_t profile;          /* 1: time every kernel launch with HIP events on the
-                               caller's stream and fill tt_report.kstat */
+  int32_t profile;          /* bit mask of kernel classes (bit c = class c,
+                               TT_PROFILE_ALL = every class) whose launches are timed
+                               with HIP events on the caller's stream, filling
+                               tt_report.kstat; 0 = no events */
   int32_t prec;             /* tt_prec: TT_PREC_FP64 or TT_PREC_MIXED */
 } tt_opts;
 
@@ -81,6 +83,7 @@ typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1 } tt_prec;
 
 /* Kernel classes of the profile (tt_kernel_class_name gives their names). */
 #define TT_NKCLASS 7
+#define TT_PROFILE_ALL ((1 << TT_NKCLASS) - 1)
 typedef struct {
   int64_t launches;
   double ms;        /* summed launch durations (HIP events around each launch) */
@@ -98,7 +101,7 @@ typedef struct {
                                    sum delta for Alg. 4 (Prop. A.1) */
   int32_t rank_rule_met;        /* eps mode: 1 if every step met its tolerance */
   int32_t d;
-  tt_kstat kstat[TT_NKCLASS];   /* filled when opts.profile = 1 */
+  tt_kstat kstat[TT_NKCLASS];   /* classes selected by opts.profile */
   int32_t sweeps[TT_MAX_D];     /* Jacobi sweeps of the Rayleigh-Ritz step of unfolding k */
   double rho[TT_MAX_D];         /* TT_PREC_MIXED: ||carry - fl32(carry)||_F of unfolding k */
 } tt_report;

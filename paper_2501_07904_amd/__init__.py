@@ -39,6 +39,7 @@ class tt_opts(ctypes.Structure):
 
 
 TT_NKCLASS = 7
+TT_PROFILE_ALL = (1 << TT_NKCLASS) - 1
 
 
 class tt_kstat(ctypes.Structure):
@@ -129,7 +130,8 @@ def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=
     o = tt_opts()
     load_library().tt_default_opts(ctypes.byref(o))
     o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
-    o.profile = int(bool(profile))
+    # profile: False/0 = off, True = every kernel class, an int = bit mask of classes
+    o.profile = TT_PROFILE_ALL if profile is True else int(profile)
     o.prec = PRECS[prec]
     keep = None
     if weights is not None:
@@ -321,6 +323,12 @@ class Decomposer:
                                        ctypes.byref(self.rep), _stream(stream))
         _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
         return rc
+
+    def set_profile(self, profile):
+        """Kernel classes timed with HIP events from the next call on: False/0
+        none, True all, an int a bit mask of classes."""
+        self.profile = profile
+        self.opts.profile = TT_PROFILE_ALL if profile is True else int(profile)
 
     def cores(self):
         r = [int(self.rep.ranks[k]) for k in range(self.d + 1)]

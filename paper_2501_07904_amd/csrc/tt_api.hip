@@ -40,6 +40,7 @@ thread_local std::vector<hipEvent_t> g_events;
 
 struct Prof {
   bool on = false;
+  int mask = 0;     // classes whose launches are timed
   hipStream_t st = nullptr;
   size_t next = 0;
   struct Rec {
@@ -63,12 +64,13 @@ struct Prof {
 #define LAUNCH(P, cls, nbytes, nflops, expr)                                        \
   do {                                                                             \
     hipEvent_t ea_ = nullptr, eb_ = nullptr;                                       \
-    if ((P).on) {                                                                  \
+    const bool tm_ = (P).on && (((P).mask >> (cls)) & 1);                          \
+    if (tm_) {                                                                     \
       HIP_OK((P).event(&ea_));                                                     \
       HIP_OK(hipEventRecord(ea_, (P).st));                                         \
     }                                                                              \
     HIP_OK(expr);                                                                  \
-    if ((P).on) {                                                                  \
+    if (tm_) {                                                                     \
       HIP_OK((P).event(&eb_));                                                     \
       HIP_OK(hipEventRecord(eb_, (P).st));                                         \
       (P).recs.push_back({(cls), ea_, eb_, (double)(nbytes), (double)(nflops)});  \
@@ -553,6 +555,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   hipStream_t st = (hipStream_t)stream;
   Prof PF;
   PF.on = P.o.profile != 0;
+  PF.mask = P.o.profile;
   PF.st = st;
 
   const int nsteps = d - 1;

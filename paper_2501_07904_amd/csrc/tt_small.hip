@@ -11,8 +11,43 @@ namespace {
 constexpr int kThreads = 1024;   // single-workgroup solvers: 16 waves
 constexpr int kLd = kCMax + 1;   // padded leading dimension of LDS matrices
 
+// Cross-lane sums without LDS round trips: DPP moves inside rows of 16
+// lanes, then v_readlane across the rows of a wave.  Every lane of a group
+// ends with the bit-identical sum (each pairing adds the same two operands).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]: pairs
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]: quads
+  v += dpp_mov<0x141>(v);   // row_half_mirror: lane i with 7-i, eights
+  v += dpp_mov<0x140>(v);   // row_mirror: lane i with 15-i, rows of 16
+  return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of tpj lanes, tpj in {16, 32, 64}; the lanes of a
+// summed row must all be active.
+__device__ __forceinline__ double group_sum(double v, int tpj) {
+  v = row16_sum(v);
+  if (tpj == 16) return v;
+  const double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16);
+  const double r2 = readlane_d(v, 32), r3 = readlane_d(v, 48);
+  if (tpj == 32) return (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
+  return (r0 + r1) + (r2 + r3);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = group_sum(v, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
@@ -92,10 +127,8 @@ __device__ __forceinline__ void householder_inplace(double* X, int64_t ld, int n
         gj = fma(xk, X[i + j * ld], gj);
       }
     }
-    for (int o = tpj >> 1; o > 0; o >>= 1) {
-      sig += __shfl_xor(sig, o, 64);
-      gj += __shfl_xor(gj, o, 64);
-    }
+    sig = group_sum(sig, tpj);
+    gj = group_sum(gj, tpj);
     if (on) {
       const double alpha = X[k + k * ld];
       double tk = 0.0, sc = 0.0;
@@ -128,7 +161,7 @@ __device__ __forceinline__ void householder_inplace(double* X, int64_t ld, int n
       double dsum = 0.0;
       if (on && tk != 0.0)
         for (int i = k + 1 + lane; i < n; i += tpj) dsum = fma(X[i + k * ld], X[i + j * ld], dsum);
-      for (int o = tpj >> 1; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+      dsum = group_sum(dsum, tpj);
       if (on) {
         // row k of column j is zero before H_k (it held an entry of R)
         const double f = tk * sc * dsum;
@@ -166,36 +199,48 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
                                                 int64_t qj, int n, int c, double* vbuf) {
   // rows are padded to NP = R * TPJ with zeros, so the loops below need no row
   // guards; TPJ (= reg_group_width(c)) is a compile-time constant so that the
-  // LDS offsets of a thread's rows are immediates
+  // LDS offsets of a thread's rows are immediates.  Step k of the
+  // factorisation first applies H_{k-1} to the columns g >= k, then group k
+  // forms reflector k from its freshly updated column: one barrier per step.
   const int t = threadIdx.x;
-  constexpr int tpj = TPJ;
   constexpr int NP = R * TPJ;
-  const int g = t / tpj, lane = t % tpj;
+  const int g = t / TPJ, lane = t % TPJ;
   const bool own = g < c;
   double x[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = lane + tpj * r;
-    x[r] = 0.0;
-    if (own && i < n) x[r] = X[i * xi + g * xj];
+    const int i = lane + TPJ * r;
+    x[r] = (own && i < n) ? X[i * xi + g * xj] : 0.0;
   }
   double* taus = vbuf + 2 * NP;
   double my_tau = 0.0;
   // ---- factorisation
   for (int k = 0; k < c; ++k) {
-    double* v = vbuf + (k & 1) * NP;
+    if (k > 0 && own && g >= k) {
+      const double* v = vbuf + ((k - 1) & 1) * NP + lane;
+      const double tk = taus[k - 1];
+      double vr[R];
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vr[r] = v[TPJ * r];
+        if (r & 1) d1 = fma(vr[r], x[r], d1);
+        else d0 = fma(vr[r], x[r], d0);
+      }
+      const double f = tk * group_sum(d0 + d1, TPJ);
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
+    }
     if (g == k) {
       double sig = 0.0, alpha = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
+        const int i = lane + TPJ * r;
         sig = fma(i > k ? x[r] : 0.0, x[r], sig);
-        alpha += (i == k) ? x[r] : 0.0;
+        alpha = (i == k) ? x[r] : alpha;
       }
-      for (int o = tpj >> 1; o > 0; o >>= 1) {
-        sig += __shfl_xor(sig, o, 64);
-        alpha += __shfl_xor(alpha, o, 64);
-      }
+      sig = group_sum(sig, TPJ);
+      alpha = group_sum(alpha, TPJ);   // one lane holds row k, the others add zero
       double tk = 0.0, sc = 0.0;
       if (sig > 0.0) {
         const double mu = sqrt(fma(alpha, alpha, sig));
@@ -204,53 +249,49 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
         sc = 1.0 / (alpha - beta);
       }
       my_tau = tk;
+      double* v = vbuf + (k & 1) * NP + lane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
+        const int i = lane + TPJ * r;
         const double vi = (i < k) ? 0.0 : (i == k ? 1.0 : sc * x[r]);
-        v[i] = vi;
+        v[TPJ * r] = vi;
         x[r] = (i > k) ? vi : x[r];   // keep the scaled reflector below the diagonal
       }
       if (lane == 0) taus[k] = tk;
     }
     __syncthreads();
-    if (own && g > k) {
-      const double tk = taus[k];
-      double dot = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dot = fma(v[lane + tpj * r], x[r], dot);
-      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-      const double f = tk * dot;
-#pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = fma(-f, v[lane + tpj * r], x[r]);
-    }
   }
-  __syncthreads();
-  // ---- Q = H_0 ... H_{c-1} [I; 0], backwards, in registers
+  // ---- Q = H_0 ... H_{c-1} [I; 0], backwards: group k publishes v_k, the
+  // groups g > k apply H_k to their columns, group k forms H_k e_k
   for (int k = c - 1; k >= 0; --k) {
-    double* v = vbuf + (k & 1) * NP;
     if (g == k) {
+      double* v = vbuf + (k & 1) * NP + lane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
-        v[i] = (i < k) ? 0.0 : (i == k ? 1.0 : x[r]);
+        const int i = lane + TPJ * r;
+        v[TPJ * r] = (i < k) ? 0.0 : (i == k ? 1.0 : x[r]);
       }
       if (lane == 0) taus[k] = my_tau;
     }
     __syncthreads();
     if (own && g > k) {
+      const double* v = vbuf + (k & 1) * NP + lane;
       const double tk = taus[k];
-      double dot = 0.0;
+      double vr[R];
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dot = fma(v[lane + tpj * r], x[r], dot);
-      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-      const double f = tk * dot;
+      for (int r = 0; r < R; ++r) {
+        vr[r] = v[TPJ * r];
+        if (r & 1) d1 = fma(vr[r], x[r], d1);
+        else d0 = fma(vr[r], x[r], d0);
+      }
+      const double f = tk * group_sum(d0 + d1, TPJ);
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = fma(-f, v[lane + tpj * r], x[r]);
+      for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
     } else if (g == k) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
+        const int i = lane + TPJ * r;
         x[r] = (i < k) ? 0.0 : (i == k ? 1.0 - my_tau : -my_tau * x[r]);
       }
     }
@@ -259,7 +300,7 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
   if (own) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = lane + tpj * r;
+      const int i = lane + TPJ * r;
       if (i < n) Q[i * qi + g * qj] = x[r];
     }
   }
@@ -299,10 +340,8 @@ __device__ __forceinline__ void householder_lds(const double* X, int64_t xi, int
         sig = fma(i > k ? xr : 0.0, xr, sig);
         alpha += (i == k) ? xr : 0.0;
       }
-      for (int o = tpj >> 1; o > 0; o >>= 1) {
-        sig += __shfl_xor(sig, o, 64);
-        alpha += __shfl_xor(alpha, o, 64);
-      }
+      sig = group_sum(sig, tpj);
+      alpha = group_sum(alpha, tpj);
       double tk = 0.0, sc = 0.0;
       if (sig > 0.0) {
         const double mu = sqrt(fma(alpha, alpha, sig));
@@ -331,7 +370,7 @@ __device__ __forceinline__ void householder_lds(const double* X, int64_t xi, int
         if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
       }
       double dot = d0 + d1;
-      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      dot = group_sum(dot, tpj);
       const double f = tk * dot;
 #pragma unroll
       for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
@@ -358,7 +397,7 @@ __device__ __forceinline__ void householder_lds(const double* X, int64_t xi, int
         if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
       }
       double dot = d0 + d1;
-      for (int o = tpj >> 1; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+      dot = group_sum(dot, tpj);
       const double f = tk * dot;
 #pragma unroll
       for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
@@ -418,8 +457,49 @@ __device__ __forceinline__ void rr_pair(int p, int round, int Le, int* a, int* b
   *b = max(x, y);
 }
 
+// Rotation (cs, sn) of a pair with diagonal entries app, aqq and coupling
+// apq, zeroing apq; the identity when apq is below the rounding floor.
+// Branch-free, so that a thread evaluates its two pairs with overlapping
+// latency: tan(theta) t = 2 apq / (d + sign(d) sqrt(d^2 + 4 apq^2)),
+// d = aqq - app, |t| <= 1, from operands scaled to max(|d|, |2 apq|) ~ 1 (t is
+// scale invariant); reciprocal and reciprocal square roots by the hardware
+// estimate plus two Newton steps.  cs = 1/sqrt(1 + t^2) to working accuracy
+// keeps the rotation orthogonal; t itself need only be close to the exact
+// angle.  Every thread that evaluates a pair does so from the same operands
+// with the same operations, so all copies agree bitwise.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+__device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, double abs_floor, double* cs,
+                                           double* sn) {
+  const bool on = fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(app * aqq);
+  const double dd = aqq - app, tw = 2.0 * apq;
+  const double sc = __builtin_amdgcn_rcp(on ? fmax(fabs(dd), fabs(tw)) : 1.0);
+  const double d1 = dd * sc, t1 = tw * sc;
+  const double d2 = fma(d1, d1, t1 * t1);   // in [1, 2] when on
+  const double rr = d2 * rsq_nr(d2);
+  const double den = d1 >= 0.0 ? d1 + rr : d1 - rr;   // |den| >= 1
+  double q = __builtin_amdgcn_rcp(den);
+  q = fma(q, fma(-den, q, 1.0), q);
+  q = fma(q, fma(-den, q, 1.0), q);
+  const double tt = t1 * q;
+  const double c = rsq_nr(fma(tt, tt, 1.0));
+  *cs = on ? c : 1.0;
+  *sn = on ? tt * c : 0.0;
+  return on;
+}
+
+// K is L x L in LDS (ld kLd); K2 is scratch of the same size: the rounds
+// alternate between the two, so that every thread reads the entries of the
+// previous round while others write the next.  A round is one barrier: the
+// thread of block (P, Q) evaluates the rotations of pairs P and Q itself,
+// writes the 2 x 2 block of J^T K J and applies the rotation of Q to the
+// 2 x 2 block (rows of P, columns of Q) of Z.
 template <int NT>
-__device__ __forceinline__ int jacobi_eig(double* K, double* Z, int L, double* lam, int* perm, double* rot,
+__device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int L, double* lam, int* perm,
                                           double* sh, int* flag) {
   // K and Z are padded to Le = L rounded up to even with a zero row and column;
   // the pair holding the padding index then always gets the identity rotation
@@ -444,59 +524,44 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* Z, int L, double* l
   // separated eigenvalues)
   const double abs_floor = 1e-300 + 1e-15 * dmax;
   __syncthreads();
-  int* pr = (int*)(rot + 64);   // pair indices of the round: pr[2p], pr[2p+1]
+  double* Kc = K;
+  double* Kn = K2;
   int sweeps = 0;
   for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
     sweeps = sweep + 1;
     if (t == 0) *flag = 0;
     __syncthreads();
     for (int round = 0; round < Le - 1; ++round) {
-      if (t < h) {
-        int a, b;
-        rr_pair(t, round, Le, &a, &b);
-        const double app = K[a + a * kLd], aqq = K[b + b * kLd], apq = K[a + b * kLd];
-        double cs = 1.0, sn = 0.0;
-        if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(app * aqq)) {
-          // t = tan(theta) of the rotation zeroing apq, |t| <= 1:
-          // t = 2 apq / (d + sign(d) sqrt(d^2 + 4 apq^2)), d = aqq - app
-          const double dd = aqq - app, tw = 2.0 * apq;
-          const double rr = sqrt(fma(dd, dd, tw * tw));
-          const double tt = tw / (dd >= 0.0 ? dd + rr : dd - rr);
-          cs = rsqrt(fma(tt, tt, 1.0));
-          sn = tt * cs;
-          *flag = 1;
-        }
-        rot[2 * t] = cs;
-        rot[2 * t + 1] = sn;
-        pr[2 * t] = a;
-        pr[2 * t + 1] = b;
+      for (int e = t; e < h * h; e += NT) {
+        const int P = e % h, Q = e / h;
+        int aP, bP, aQ, bQ;
+        rr_pair(P, round, Le, &aP, &bP);
+        rr_pair(Q, round, Le, &aQ, &bQ);
+        // every operand of the thread first (one LDS round trip), then the math
+        const double pa = Kc[aP + aP * kLd], pb = Kc[bP + bP * kLd], pab = Kc[aP + bP * kLd];
+        const double qa = Kc[aQ + aQ * kLd], qb = Kc[bQ + bQ * kLd], qab = Kc[aQ + bQ * kLd];
+        const double kaa = Kc[aP + aQ * kLd], kab = Kc[aP + bQ * kLd];
+        const double kba = Kc[bP + aQ * kLd], kbb = Kc[bP + bQ * kLd];
+        const double zaa = Z[aP + aQ * kLd], zab = Z[aP + bQ * kLd];
+        const double zba = Z[bP + aQ * kLd], zbb = Z[bP + bQ * kLd];
+        double cP, sP, cQ, sQ;
+        const bool rot = jacobi_rot(pa, pb, pab, abs_floor, &cP, &sP);
+        jacobi_rot(qa, qb, qab, abs_floor, &cQ, &sQ);
+        const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
+        const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
+        Kn[aP + aQ * kLd] = cP * raa - sP * rba;
+        Kn[aP + bQ * kLd] = cP * rab - sP * rbb;
+        Kn[bP + aQ * kLd] = sP * raa + cP * rba;
+        Kn[bP + bQ * kLd] = sP * rab + cP * rbb;
+        // Z <- Z J on rows {aP, bP} and columns {aQ, bQ}
+        Z[aP + aQ * kLd] = cQ * zaa - sQ * zab;
+        Z[aP + bQ * kLd] = sQ * zaa + cQ * zab;
+        Z[bP + aQ * kLd] = cQ * zba - sQ * zbb;
+        Z[bP + bQ * kLd] = sQ * zba + cQ * zbb;
+        if (rot && P == Q) *flag = 1;   // pair P rotated (evaluated once per pair here)
       }
       __syncthreads();
-      // K <- J^T K J on the 2 x 2 blocks (P, Q); Z <- Z J on the 1 x 2 blocks (i, Q)
-      for (int e = t; e < h * h + Le * h; e += NT) {
-        if (e < h * h) {
-          const int P = e % h, Q = e / h;
-          const double cP = rot[2 * P], sP = rot[2 * P + 1], cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
-          const int aP = pr[2 * P], bP = pr[2 * P + 1], aQ = pr[2 * Q], bQ = pr[2 * Q + 1];
-          const double kaa = K[aP + aQ * kLd], kab = K[aP + bQ * kLd];
-          const double kba = K[bP + aQ * kLd], kbb = K[bP + bQ * kLd];
-          const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
-          const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
-          K[aP + aQ * kLd] = cP * raa - sP * rba;
-          K[aP + bQ * kLd] = cP * rab - sP * rbb;
-          K[bP + aQ * kLd] = sP * raa + cP * rba;
-          K[bP + bQ * kLd] = sP * rab + cP * rbb;
-        } else {
-          const int f = e - h * h;
-          const int i = f % Le, Q = f / Le;
-          const double cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
-          const int aQ = pr[2 * Q], bQ = pr[2 * Q + 1];
-          const double za = Z[i + aQ * kLd], zb = Z[i + bQ * kLd];
-          Z[i + aQ * kLd] = cQ * za - sQ * zb;
-          Z[i + bQ * kLd] = sQ * za + cQ * zb;
-        }
-      }
-      __syncthreads();
+      double* tmp = Kc; Kc = Kn; Kn = tmp;
     }
     const int any = *flag;
     __syncthreads();
@@ -504,16 +569,16 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* Z, int L, double* l
   }
   // descending order, ties by index
   if (t < L) {
-    const double v = K[t + t * kLd];
+    const double v = Kc[t + t * kLd];
     int rank = 0;
     for (int j = 0; j < L; ++j) {
-      const double w = K[j + j * kLd];
+      const double w = Kc[j + j * kLd];
       rank += (w > v) || (w == v && j < t);
     }
     perm[rank] = t;
   }
   __syncthreads();
-  if (t < L) lam[t] = K[perm[t] + perm[t] * kLd];
+  if (t < L) lam[t] = Kc[perm[t] + perm[t] * kLd];
   __syncthreads();
   return sweeps;
 }
@@ -578,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
   __shared__ double sB0[kCMax * kLd];
   __shared__ double sB1[kCMax * kLd];
   __shared__ double sK[kCMax * kLd];
-  __shared__ double lam[kCMax], tau[kCMax], scal[kCMax], rot[96], sg[kCMax], sh[32];
+  __shared__ double lam[kCMax], tau[kCMax], scal[kCMax], sg[kCMax], sh[32];
   __shared__ double vbuf[2 * 64 * 4 + kCMax];   // register Householder with R = 4, tpj <= 64
   __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
@@ -641,8 +706,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     sK[j + i * kLd] = v;
   }
   __syncthreads();
-  double* sZ = sH;  // H is no longer needed
-  const int sweeps = jacobi_eig<kThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
+  double* sZ = sH;  // H is no longer needed; T is free until V1 is formed
+  const int sweeps = jacobi_eig<kThreads>(sK, T, sZ, L, lam, perm, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -711,7 +776,7 @@ __global__ __launch_bounds__(kThreads) void k_orth(double* M, double* X, int n, 
 template <int R, int TPJ>
 __global__ __launch_bounds__(kThreads) void k_orth_reg(const double* M, double* X, int n, int c) {
   __shared__ double vbuf[2 * R * TPJ + kCMax];
-  if constexpr (R <= 8) {
+  if constexpr (R <= 16) {
     householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf);
   } else {
     __shared__ double wcols[R * kThreads];   // (kThreads / TPJ) columns of R * TPJ rows
@@ -736,8 +801,9 @@ constexpr int kRRThreads = 1024;  // measured: 16 waves finish a Jacobi round fa
 __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restrict__ K,
                                                          const double* __restrict__ X, SolveArgs a) {
   __shared__ double sK[kCMax * kLd];
+  __shared__ double sK2[kCMax * kLd];
   __shared__ double sZ[kCMax * kLd];
-  __shared__ double lam[kCMax], rot[96], sg[kCMax], sh[32];
+  __shared__ double lam[kCMax], sg[kCMax], sh[32];
   __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
@@ -749,7 +815,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
   }
   if (t == 0) snormC2 = *a.normC2_src;
   __syncthreads();
-  const int sweeps = jacobi_eig<kRRThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
+  const int sweeps = jacobi_eig<kRRThreads>(sK, sK2, sZ, L, lam, perm, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
@@ -810,8 +876,9 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
 __global__ __launch_bounds__(kRRThreads) void k_alg4_basis(const double* __restrict__ K,
                                                            double* __restrict__ Tout, int L) {
   __shared__ double sK[kCMax * kLd];
+  __shared__ double sK2[kCMax * kLd];
   __shared__ double sZ[kCMax * kLd];
-  __shared__ double lam[kCMax], rot[96], sh[32];
+  __shared__ double lam[kCMax], sh[32];
   __shared__ int perm[kCMax], flag;
   const int t = threadIdx.x;
   for (int e = t; e < L * L; e += kRRThreads) {
@@ -819,7 +886,7 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_basis(const double* __restr
     sK[i + j * kLd] = 0.5 * (K[i + (int64_t)L * j] + K[j + (int64_t)L * i]);
   }
   __syncthreads();
-  jacobi_eig<kRRThreads>(sK, sZ, L, lam, perm, rot, sh, &flag);
+  jacobi_eig<kRRThreads>(sK, sK2, sZ, L, lam, perm, sh, &flag);
   const double lmax = fmax(lam[0], 0.0);
   for (int e = t; e < L * L; e += kRRThreads) {
     const int i = e / L, j = e % L;
@@ -834,8 +901,9 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_basis(const double* __restr
 __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restrict__ E,
                                                            const double* __restrict__ Bt, SolveArgs a) {
   __shared__ double sE[kCMax * kLd];
+  __shared__ double sK2[kCMax * kLd];
   __shared__ double sW[kCMax * kLd];
-  __shared__ double lam[kCMax], rot[96], sg[kCMax], sinv[kCMax], sh[32];
+  __shared__ double lam[kCMax], sg[kCMax], sinv[kCMax], sh[32];
   __shared__ int perm[kCMax], flag, sr, ssat;
   __shared__ double skept, snormC2;
   const int t = threadIdx.x;
@@ -847,7 +915,7 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restr
   }
   if (t == 0) snormC2 = *a.normC2_src;
   __syncthreads();
-  const int sweeps = jacobi_eig<kRRThreads>(sE, sW, L, lam, perm, rot, sh, &flag);
+  const int sweeps = jacobi_eig<kRRThreads>(sE, sK2, sW, L, lam, perm, sh, &flag);
   if (t == 0) {
     int r, sat;
     double kept;
