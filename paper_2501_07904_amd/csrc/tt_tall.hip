@@ -129,6 +129,114 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 }
 
 constexpr int kAxKC = 64;
+constexpr int kAxSplitTiles = 128;   // A*W splits its k range when A has fewer 64-row tiles
+
+// ---------------------------------------------------------------------------
+// partials[chunk] = A[rows of chunk, j0:j0+64]^T Y[rows of chunk, :] for FP64
+// operands on the matrix cores.  Row tiles of 32 rows of A (64 columns) and Y
+// (all c columns, zero-padded to 16*NT) are staged in LDS with coalesced loads
+// (COL: each column segment is contiguous; ROW: each row segment is); wave w
+// then owns output rows j0+16w .. j0+16w+15 and computes their 16 x 16*NT block
+// with v_mfma_f64_16x16x4, the k-slots running over the rows of the tile
+// (operand A: lane l holds A(i0 + l/16, j0 + 16w + l%16); operand B: lane l
+// holds Y(i0 + l/16, 16t + l%16)).  With Y == A (Gram) the tile of A serves
+// both sides.
+constexpr int kAtbMR = 32;
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_atb_mfma(const double* __restrict__ A, const double* __restrict__ Y,
+                                                       int64_t m, int n, int c, int layout,
+                                                       int64_t rows_per_chunk, double* __restrict__ partials) {
+  __shared__ double sA[kAtbMR][kAtbJT + 1];
+  __shared__ double sY[kAtbMR][NT * 16 + 1];
+  const bool gram = (A == Y);
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t chunk = blockIdx.x;
+  const int j0 = blockIdx.y * kAtbJT;
+  const int jt = min(kAtbJT, n - j0);
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = min(m, r0 + rows_per_chunk);
+  d4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0; rb < r1; rb += kAtbMR) {
+    const int tr = (int)min((int64_t)kAtbMR, r1 - rb);
+    __syncthreads();
+    for (int e = t; e < kAtbMR * kAtbJT; e += kThreads) {
+      int i, j;
+      if (layout == ROW) { i = e / kAtbJT; j = e % kAtbJT; } else { i = e % kAtbMR; j = e / kAtbMR; }
+      sA[i][j] = (i < tr && j < jt) ? A[at(layout, rb + i, j0 + j, m, n)] : 0.0;
+    }
+    if (!gram) {
+      for (int e = t; e < kAtbMR * NT * 16; e += kThreads) {
+        int i, j;
+        if (layout == ROW) { i = e / (NT * 16); j = e % (NT * 16); } else { i = e % kAtbMR; j = e / kAtbMR; }
+        sY[i][j] = (i < tr && j < c) ? Y[at(layout, rb + i, j, m, c)] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kAtbMR / 4; ++ks) {
+      const int i = 4 * ks + g;
+      const double a = sA[i][16 * w + li];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const double b = gram ? sA[i][16 * q + li] : sY[i][16 * q + li];
+        acc[q] = mfma_f64(a, b, acc[q]);
+      }
+    }
+  }
+  double* out = partials + chunk * (int64_t)n * c;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * w + g + 4 * v, cc = 16 * q + li;
+      if (j < jt && cc < c) out[(j0 + j) + (int64_t)n * cc] = acc[q][v];
+    }
+  }
+}
+
+// Accumulate the 64-row tile `tile` of Y = A W over columns [k_begin, k_end)
+// of A (multiples of kAxKC apart from the end) into acc; ssa collects the sum
+// of squares of the A entries read.
+template <typename TA, int NT>
+__device__ __forceinline__ void ax_accumulate(const TA* __restrict__ A, const double* __restrict__ W,
+                                              double (*sW)[NT * 16 + 1], int64_t m, int n, int c, int layout,
+                                              int64_t tile, int k_begin, int k_end, d4* acc, double& ssa) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t row = tile * 64 + 16 * w + li;
+  const bool rok = row < m;
+  for (int k0 = k_begin; k0 < k_end; k0 += kAxKC) {
+    const int kc = min(kAxKC, k_end - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kAxKC * NT * 16; e += kThreads) {
+      const int kk = e / (NT * 16), cc = e % (NT * 16);
+      sW[kk][cc] = (kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ss = 0; ss < kAxKC / 32; ++ss) {
+      const int kb = 32 * ss + 8 * g;
+      double a[8];
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int k = k0 + kb + s8;
+        double x = 0.0;
+        if (rok && k < k_end) x = (double)A[layout == ROW ? row * n + k : row + (int64_t)k * m];
+        ssa = fma(x, x, ssa);
+        a[s8] = x;
+      }
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(a[s8], sW[kb + s8][16 * t + li], acc[t]);
+    }
+  }
+}
 
 template <typename TA, typename TY, int NT>
 __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
@@ -141,37 +249,10 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
   const int g = lane >> 4, li = lane & 15;
   double ssa = 0.0, ssy = 0.0, sse = 0.0;
   for (int64_t tile = blockIdx.x; tile * 64 < m; tile += gridDim.x) {
-    const int64_t row = tile * 64 + 16 * w + li;
-    const bool rok = row < m;
     d4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < n; k0 += kAxKC) {
-      const int kc = min(kAxKC, n - k0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < kAxKC * NT * 16; e += kThreads) {
-        const int kk = e / (NT * 16), cc = e % (NT * 16);
-        sW[kk][cc] = (kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int ss = 0; ss < kAxKC / 32; ++ss) {
-        const int kb = 32 * ss + 8 * g;
-        double a[8];
-#pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-          const int k = k0 + kb + s8;
-          double x = 0.0;
-          if (rok && k < n) x = (double)A[layout == ROW ? row * n + k : row + (int64_t)k * m];
-          ssa = fma(x, x, ssa);
-          a[s8] = x;
-        }
-#pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(a[s8], sW[kb + s8][16 * t + li], acc[t]);
-      }
-    }
+    ax_accumulate<TA, NT>(A, W, sW, m, n, c, layout, tile, 0, n, acc, ssa);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -200,6 +281,84 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
   if (rerr) {
     const double s = block_sum(sse, sh);
     if (threadIdx.x == 0) rerr[blockIdx.x] = s;
+  }
+}
+
+// Split-k form for short A (few 64-row tiles): workgroup (tile, sl) of the
+// grid tiles x ks accumulates the columns of slice sl and stores its partial
+// tile; the last workgroup of a tile to finish (counted with one atomic per
+// workgroup) sums the ks partials in slice order, so the result does not
+// depend on which one that is, writes Y and resets the counter to zero.
+// Per-workgroup sums: sumsqA over the entries each group read; the Y sums of
+// a tile land in the slot of slice 0 and the other slices' slots hold zero.
+template <typename TA, typename TY, int NT>
+__global__ __launch_bounds__(kThreads) void k_ax_sk(const TA* __restrict__ A, const double* __restrict__ W,
+                                                    TY* __restrict__ Y, int64_t m, int n, int c, int layout, int ks,
+                                                    double* __restrict__ part, unsigned* __restrict__ cnt,
+                                                    double* __restrict__ sumsqA, double* __restrict__ sumsqY,
+                                                    double* __restrict__ rerr) {
+  __shared__ double sW[kAxKC][NT * 16 + 1];
+  __shared__ double sh[8];
+  __shared__ int s_last;
+  constexpr int WP = NT * 16;
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int tile = blockIdx.x / ks, sl = blockIdx.x % ks;
+  const int kchunks = (n + kAxKC - 1) / kAxKC;
+  const int kc0 = (int)((int64_t)kchunks * sl / ks), kc1 = (int)((int64_t)kchunks * (sl + 1) / ks);
+  double ssa = 0.0;
+  d4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  ax_accumulate<TA, NT>(A, W, sW, m, n, c, layout, tile, kc0 * kAxKC, min(n, kc1 * kAxKC), acc, ssa);
+  double* pp = part + (int64_t)blockIdx.x * 64 * WP;
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pp[(16 * w + g + 4 * v) * WP + 16 * q + li] = acc[q][v];
+  __threadfence();
+  __syncthreads();
+  if (t == 0) s_last = (atomicAdd(&cnt[tile], 1u) == (unsigned)(ks - 1));
+  __syncthreads();
+  const bool last = s_last != 0;
+  double ssy = 0.0, sse = 0.0;
+  if (last) {
+    __threadfence();
+    const double* base = part + (int64_t)tile * ks * 64 * WP;
+    for (int e = t; e < 64 * c; e += kThreads) {
+      int rr, col;
+      if (layout == ROW) { rr = e / c; col = e % c; } else { rr = e % 64; col = e / 64; }
+      const int64_t row = (int64_t)tile * 64 + rr;
+      if (row >= m) continue;
+      double sum = 0.0;
+      for (int q = 0; q < ks; ++q) sum += base[((int64_t)q * 64 + rr) * WP + col];
+      const TY y = (TY)sum;
+      const double yd = (double)y;
+      ssy = fma(yd, yd, ssy);
+      const double er = sum - yd;
+      sse = fma(er, er, sse);
+      Y[at(layout, row, col, m, c)] = y;
+    }
+    if (t == 0) cnt[tile] = 0u;
+  }
+  if (sumsqA) {
+    const double s = block_sum(ssa, sh);
+    if (t == 0) sumsqA[blockIdx.x] = s;
+  }
+  if (sumsqY) {
+    const double s = block_sum(ssy, sh);
+    if (t == 0) {
+      if (last) sumsqY[(int64_t)tile * ks] = s;
+      if (sl != 0) sumsqY[blockIdx.x] = 0.0;
+    }
+  }
+  if (rerr) {
+    const double s = block_sum(sse, sh);
+    if (t == 0) {
+      if (last) rerr[(int64_t)tile * ks] = s;
+      if (sl != 0) rerr[blockIdx.x] = 0.0;
+    }
   }
 }
 
@@ -308,9 +467,23 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
   const int64_t rpc = (m + nchunks - 1) / nchunks;
   dim3 grid(nchunks, (n + kAtbJT - 1) / kAtbJT);
-  if (!a_f32 && !y_f32)
-    hipLaunchKernelGGL((k_atb<double, double>), grid, dim3(kThreads), 0, st, (const double*)A,
-                       (const double*)Y, m, n, c, layout, rpc, partials);
+  if (!a_f32 && !y_f32) {
+    // FP64 operands: matrix-core kernel (Gram: Y == A with c == n <= 64)
+    const bool gram = (A == Y);
+    if (gram && (c != n || n > kAtbJT)) return hipErrorInvalidValue;
+    if (c <= 16)
+      hipLaunchKernelGGL((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+                         layout, rpc, partials);
+    else if (c <= 32)
+      hipLaunchKernelGGL((k_atb_mfma<2>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+                         layout, rpc, partials);
+    else if (c <= 48)
+      hipLaunchKernelGGL((k_atb_mfma<3>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+                         layout, rpc, partials);
+    else
+      hipLaunchKernelGGL((k_atb_mfma<4>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+                         layout, rpc, partials);
+  }
   else if (a_f32 && y_f32)
     hipLaunchKernelGGL((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
                        (const float*)Y, m, n, c, layout, rpc, partials);
@@ -323,17 +496,46 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
   return hipGetLastError();
 }
 
+int ax_ksplit(int64_t m, int n) {
+  const int64_t tiles = (m + 63) / 64;
+  const int kchunks = (n + kAxKC - 1) / kAxKC;
+  if (tiles >= kAxSplitTiles || kchunks < 2) return 1;
+  const int ks = (int)((256 + tiles - 1) / tiles);
+  return ks < kchunks ? ks : kchunks;
+}
+
 int ax_chunks(int64_t m, int n, int c) {
-  (void)n;
   (void)c;
   const int64_t tiles = (m + 63) / 64;
+  const int ks = ax_ksplit(m, n);
+  if (ks > 1) return (int)(tiles * ks);
   return (int)(tiles < 8192 ? tiles : 8192);
+}
+
+int64_t ax_split_elems(int64_t m, int n, int c) {
+  const int ks = ax_ksplit(m, n);
+  if (ks <= 1) return 0;
+  const int64_t tiles = (m + 63) / 64;
+  return tiles * ks * 64 * (int64_t)(((c + 15) / 16) * 16);
 }
 
 template <typename TA, typename TY>
 static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
-                        int nchunks, double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
+                        int nchunks, double* sumsqA, double* sumsqY, double* rerr, double* skpart, unsigned* skcnt,
+                        hipStream_t st) {
   dim3 grid(nchunks), block(kThreads);
+  const int ks = ax_ksplit(m, n);
+  if (ks > 1) {
+    if (c <= 16)
+      hipLaunchKernelGGL((k_ax_sk<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
+    else if (c <= 32)
+      hipLaunchKernelGGL((k_ax_sk<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
+    else if (c <= 48)
+      hipLaunchKernelGGL((k_ax_sk<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
+    else
+      hipLaunchKernelGGL((k_ax_sk<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
+    return;
+  }
   if (c <= 16)
     hipLaunchKernelGGL((k_ax<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
   else if (c <= 32)
@@ -346,16 +548,30 @@ static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, i
 
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m, int n,
                      int c, int layout, int nchunks, double* sumsqA, double* sumsqY, double* rerr,
-                     hipStream_t st) {
+                     const AxScratch& sk, hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks != ax_chunks(m, n, c)) return hipErrorInvalidValue;
+  if (ax_ksplit(m, n) > 1 && (!sk.part || !sk.cnt || sk.part_elems < ax_split_elems(m, n, c) ||
+                              sk.ncnt < (m + 63) / 64))
+    return hipErrorInvalidValue;
   if (!a_f32 && !y_f32)
-    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
+    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
   else if (a_f32 && !y_f32)
-    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
+    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
   else if (a_f32 && y_f32)
-    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
+    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
   else
-    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
+    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_counters(unsigned* cnt, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, cnt, n);
   return hipGetLastError();
 }
 
