@@ -244,19 +244,18 @@ struct Work {
   double* W;
   double* normA2;
   StepRec* recs;
-  AxScratch ax;   // split-k partial tiles and counters of A*W on short A
   size_t bytes;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Sizes {
-  int64_t carry, Y, U, X, part, V1, axpart;
+  int64_t carry, Y, U, X, part, V1;
 };
 
 // Upper bounds over every step (and every ell a prescribed-accuracy step may grow to).
 Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
-  Sizes z{1, 1, 1, 1, 1, 1, 0};
+  Sizes z{1, 1, 1, 1, 1, 1};
   for (size_t i = 0; i < S.size(); ++i) {
     const Step& s = S[i];
     const int64_t lim = std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
@@ -264,8 +263,6 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
     if (i + 1 < S.size()) z.carry = std::max(z.carry, s.m * (int64_t)s.r);
     z.V1 = std::max(z.V1, (int64_t)s.n * s.r);
     const int c = std::max(1, std::min(ellmax, (int)kCMax));
-    // A*W over the full core side (sketch, power and Rayleigh-Ritz passes) may split k
-    z.axpart = std::max(z.axpart, ax_split_elems(s.m, s.n, kCMax));
     if (step_gram(P, s)) {
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, s.n) * s.n * s.n);
     } else {
@@ -307,10 +304,6 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.K = (double*)take((size_t)kCMax * kCMax * 8);
   W.V1 = (double*)take(z.V1 * 8);
   W.W = (double*)take((size_t)kCMax * kCMax * 8);
-  W.ax.part_elems = z.axpart;
-  W.ax.part = z.axpart > 0 ? (double*)take(z.axpart * 8) : nullptr;
-  W.ax.ncnt = z.axpart > 0 ? kAxMaxCounters : 0;
-  W.ax.cnt = z.axpart > 0 ? (unsigned*)take(sizeof(unsigned) * kAxMaxCounters) : nullptr;
   W.normA2 = (double*)take(64);
   W.recs = (StepRec*)take(sizeof(StepRec) * (size_t)d);
   W.bytes = off;
@@ -385,7 +378,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
       const double sy = P.mixed ? 4.0 : 8.0;
       LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
              launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,
-                       (first && it == 0) ? W.part : nullptr, nullptr, nullptr, W.ax, st));
+                       (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
       if (first && it == 0)
         LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
       const int nch = atb_chunks(m, n, c);
@@ -398,7 +391,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
     // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank)
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, nullptr, W.ax, st));
+           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, nullptr, st));
     const int kch = atb_chunks(m, c, c);
     LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
            launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, W.part, kch, st));
@@ -417,7 +410,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
       const double sy = P.mixed ? 4.0 : 8.0;
       LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
              launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,
-                       need_norm ? W.part : nullptr, nullptr, nullptr, W.ax, st));
+                       need_norm ? W.part : nullptr, nullptr, nullptr, st));
       if (need_norm) {
         LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
         need_norm = false;
@@ -431,7 +424,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     }
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
            launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
-                     need_norm ? W.part : nullptr, nullptr, nullptr, W.ax, st));
+                     need_norm ? W.part : nullptr, nullptr, nullptr, st));
     if (need_norm) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
     // U = orth(Y): two eigen-based Cholesky-QR rounds, Y -> U (round 1) -> Y (round 2)
     const int kch = atb_chunks(m, c, c);
@@ -445,7 +438,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
              launch_reduce(W.part, kch, (int64_t)c * c, W.K, nullptr, st));
       LAUNCH(PF, KC_SMALL, 0, 0, launch_alg4_basis(W.K, W.H, c, st));
       LAUNCH(PF, KC_GRAM_Y, 2.0 * mc * 8 + (double)c * c * 8, 2.0 * mc * c,
-             launch_ax(src, 0, W.H, dst, 0, m, c, c, s.layout, ych, nullptr, nullptr, nullptr, W.ax, st));
+             launch_ax(src, 0, W.H, dst, 0, m, c, c, s.layout, ych, nullptr, nullptr, nullptr, st));
     }
     // Bt = A^T U (n x ell), E = Bt^T Bt
     const int nch = atb_chunks(m, n, c);
@@ -474,11 +467,11 @@ int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io
   if (step_gram(P, s)) {
     const double mn = (double)m * s.n;
     LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)s.n * r * 8, 2.0 * mn * r,
-           launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, W.part, rerr, W.ax, st));
+           launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, W.part, rerr, st));
   } else {
     const double ml = (double)m * ell;
     LAUNCH(PF, KC_CARRY, ml * 8 + mr * so + (double)ell * r * 8, 2.0 * ml * r,
-           launch_ax(W.Y, 0, W.W, io.out, io.out_f32, m, ell, r, s.layout, ach, nullptr, W.part, rerr, W.ax, st));
+           launch_ax(W.Y, 0, W.W, io.out, io.out_f32, m, ell, r, s.layout, ach, nullptr, W.part, rerr, st));
   }
   LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, &rec->carry2, nullptr, st));
   if (rerr) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(rerr, ach, 1, &rec->rho2, nullptr, st));
@@ -564,8 +557,6 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   PF.on = P.o.profile != 0;
   PF.mask = P.o.profile;
   PF.st = st;
-  // split-k counters of A*W start at zero (every split launch leaves them at zero)
-  if (W.ax.cnt) HIP_OK(launch_zero_counters(W.ax.cnt, (int)W.ax.ncnt, st));
 
   const int nsteps = d - 1;
   int64_t r_run[TT_MAX_D + 1];

@@ -37,27 +37,9 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
                       int c, int layout, double* partials, int nchunks, hipStream_t st);
 // Number of workgroups (and of sum-of-squares partials) the A*W kernel uses.
 int ax_chunks(int64_t m, int n, int c);
-// Short A (fewer than 128 tiles of 64 rows) splits the k range of A*W over
-// ax_ksplit(m, n) workgroups per tile; their partial tiles need
-// ax_split_elems(m, n, c) doubles and one counter per tile (zero between launches).
-int ax_ksplit(int64_t m, int n);
-int64_t ax_split_elems(int64_t m, int n, int c);
-constexpr int kAxMaxCounters = 128;
-struct AxScratch {
-  double* part;
-  int64_t part_elems;
-  unsigned* cnt;
-  int64_t ncnt;
-};
-// Sets n counters to zero.
-hipError_t launch_zero_counters(unsigned* cnt, int n, hipStream_t st);
-// Y(i, cc) = sum_j A(i,j) W(j,cc), W k-major n x c (W(j,cc) at j*c + cc, FP64); Y in `layout`.
-// If sumsqA != NULL, sumsqA[ch] = sum of squares of the A entries read by chunk ch.
-// If sumsqY != NULL, sumsqY[ch] = sum of squares of the Y entries written (as stored).
-// If rerr != NULL, rerr[ch] = sum of squares of (FP64 result - stored FP32 value).
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m,
                      int n, int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
-                     double* rerr, const AxScratch& sk, hipStream_t st);
+                     double* rerr, hipStream_t st);
 // resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r k-major.
 int resid_chunks(int64_t m);
 hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, const double* V1, int64_t m,

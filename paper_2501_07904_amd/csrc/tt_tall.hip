@@ -199,51 +199,97 @@ __global__ __launch_bounds__(kThreads) void k_atb_mfma(const double* __restrict_
   }
 }
 
+// Loads of one kAxKC-column chunk of A for the MFMA operand of this lane:
+// a[ss*8 + s8] = A(row, k0 + 32 ss + 8 g + s8), zero outside the matrix; ssa
+// collects the squares.
+template <typename TA, int LY>
+__device__ __forceinline__ void ax_load_chunk(const TA* __restrict__ A, int64_t m, int n, int64_t row, bool rok,
+                                              int k0, int k_end, double* a) {
+  const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int ss = 0; ss < kAxKC / 32; ++ss) {
+    const int kb = k0 + 32 * ss + 8 * g;
+    const TA* p = (LY == ROW) ? A + row * n + kb : A + row + (int64_t)kb * m;
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+      const bool ok = rok && kb + s8 < k_end;
+      a[ss * 8 + s8] = ok ? (double)p[(LY == ROW) ? (int64_t)s8 : (int64_t)s8 * m] : 0.0;
+    }
+  }
+}
+
 // Accumulate the 64-row tile `tile` of Y = A W over columns [k_begin, k_end)
-// of A (multiples of kAxKC apart from the end) into acc; ssa collects the sum
-// of squares of the A entries read.
-template <typename TA, int NT>
+// of A into acc; ssa collects the sum of squares of the A entries read.  The
+// chunk loop is software-pipelined: the loads of chunk k+1 of A (registers)
+// and of W (into the other half of the double-buffered sW) are in flight
+// while chunk k runs on the matrix cores; one barrier per chunk.
+template <typename TA, int NT, int LY>
 __device__ __forceinline__ void ax_accumulate(const TA* __restrict__ A, const double* __restrict__ W,
-                                              double (*sW)[NT * 16 + 1], int64_t m, int n, int c, int layout,
+                                              double (*sW)[kAxKC][NT * 16 + 1], int64_t m, int n, int c,
                                               int64_t tile, int k_begin, int k_end, d4* acc, double& ssa) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row = tile * 64 + 16 * w + li;
   const bool rok = row < m;
-  for (int k0 = k_begin; k0 < k_end; k0 += kAxKC) {
+  constexpr int NA = kAxKC / 4;   // A values per lane per chunk
+  constexpr int NWS = (kAxKC * NT * 16 + kThreads - 1) / kThreads;
+  if (k_begin >= k_end) return;
+  double a[NA], an[NA], wn[NWS];
+  auto load_w = [&](int k0, double* dst) {
     const int kc = min(kAxKC, k_end - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kAxKC * NT * 16; e += kThreads) {
+#pragma unroll
+    for (int u = 0; u < NWS; ++u) {
+      const int e = threadIdx.x + kThreads * u;
       const int kk = e / (NT * 16), cc = e % (NT * 16);
-      sW[kk][cc] = (kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+      dst[u] = (e < kAxKC * NT * 16 && kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
     }
-    __syncthreads();
+  };
+  auto store_w = [&](const double* src, int buf) {
+#pragma unroll
+    for (int u = 0; u < NWS; ++u) {
+      const int e = threadIdx.x + kThreads * u;
+      if (e < kAxKC * NT * 16) sW[buf][e / (NT * 16)][e % (NT * 16)] = src[u];
+    }
+  };
+  __syncthreads();   // sW may still be read by a previous tile
+  load_w(k_begin, wn);
+  ax_load_chunk<TA, LY>(A, m, n, row, rok, k_begin, k_end, a);
+  store_w(wn, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = k_begin; k0 < k_end; k0 += kAxKC) {
+    const int k1 = k0 + kAxKC;
+    const bool more = k1 < k_end;
+    if (more) {
+      load_w(k1, wn);
+      ax_load_chunk<TA, LY>(A, m, n, row, rok, k1, k_end, an);
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ssa = fma(a[u], a[u], ssa);
 #pragma unroll
     for (int ss = 0; ss < kAxKC / 32; ++ss) {
       const int kb = 32 * ss + 8 * g;
-      double a[8];
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) {
-        const int k = k0 + kb + s8;
-        double x = 0.0;
-        if (rok && k < k_end) x = (double)A[layout == ROW ? row * n + k : row + (int64_t)k * m];
-        ssa = fma(x, x, ssa);
-        a[s8] = x;
-      }
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(a[s8], sW[kb + s8][16 * t + li], acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = mfma_f64(a[ss * 8 + s8], sW[buf][kb + s8][16 * t + li], acc[t]);
     }
+    if (more) {
+      store_w(wn, buf ^ 1);
+#pragma unroll
+      for (int u = 0; u < NA; ++u) a[u] = an[u];
+    }
+    __syncthreads();
+    buf ^= 1;
   }
 }
 
-template <typename TA, typename TY, int NT>
-__global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
+template <typename TA, typename TY, int NT, int LY>
+__global__ __launch_bounds__(kThreads, 2) void k_ax(const TA* __restrict__ A, const double* __restrict__ W,
                                                  TY* __restrict__ Y, int64_t m, int n, int c,
-                                                 int layout, double* __restrict__ sumsqA,
+                                                 double* __restrict__ sumsqA,
                                                  double* __restrict__ sumsqY, double* __restrict__ rerr) {
-  __shared__ double sW[kAxKC][NT * 16 + 1];
+  __shared__ double sW[2][kAxKC][NT * 16 + 1];
   __shared__ double sh[8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -252,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
     d4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    ax_accumulate<TA, NT>(A, W, sW, m, n, c, layout, tile, 0, n, acc, ssa);
+    ax_accumulate<TA, NT, LY>(A, W, sW, m, n, c, tile, 0, n, acc, ssa);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -265,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
           ssy = fma(yd, yd, ssy);
           const double e = acc[t][v] - yd;
           sse = fma(e, e, sse);
-          Y[at(layout, yr, col, m, c)] = y;
+          Y[at(LY, yr, col, m, c)] = y;
         }
       }
     }
@@ -284,63 +330,76 @@ __global__ __launch_bounds__(kThreads) void k_ax(const TA* __restrict__ A, const
   }
 }
 
-// Split-k form for short A (few 64-row tiles): workgroup (tile, sl) of the
-// grid tiles x ks accumulates the columns of slice sl and stores its partial
-// tile; the last workgroup of a tile to finish (counted with one atomic per
-// workgroup) sums the ks partials in slice order, so the result does not
-// depend on which one that is, writes Y and resets the counter to zero.
-// Per-workgroup sums: sumsqA over the entries each group read; the Y sums of
-// a tile land in the slot of slice 0 and the other slices' slots hold zero.
-template <typename TA, typename TY, int NT>
-__global__ __launch_bounds__(kThreads) void k_ax_sk(const TA* __restrict__ A, const double* __restrict__ W,
-                                                    TY* __restrict__ Y, int64_t m, int n, int c, int layout, int ks,
-                                                    double* __restrict__ part, unsigned* __restrict__ cnt,
+// Short A (few row tiles): workgroup b owns rows 16b .. 16b+15 and its four
+// waves split the k range (wave w takes chunks w, w+4, ...); the four partial
+// 16 x 16*NT blocks are summed through LDS in wave order, so the result is
+// independent of timing.  W chunks are staged per wave (no block barrier in
+// the k loop).
+template <typename TA, typename TY, int NT, int LY>
+__global__ __launch_bounds__(kThreads) void k_ax_kw(const TA* __restrict__ A, const double* __restrict__ W,
+                                                    TY* __restrict__ Y, int64_t m, int n, int c,
                                                     double* __restrict__ sumsqA, double* __restrict__ sumsqY,
                                                     double* __restrict__ rerr) {
-  __shared__ double sW[kAxKC][NT * 16 + 1];
+  __shared__ double sW[kThreads / 64][kAxKC][NT * 16 + 1];
   __shared__ double sh[8];
-  __shared__ int s_last;
-  constexpr int WP = NT * 16;
+  // after its k loop, wave w reuses its own W stage for its partial block
+  auto sR = [&](int q, int rr, int col) -> double& { return sW[q][rr][col]; };
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int tile = blockIdx.x / ks, sl = blockIdx.x % ks;
+  const int64_t row = (int64_t)blockIdx.x * 16 + li;
+  const bool rok = row < m;
   const int kchunks = (n + kAxKC - 1) / kAxKC;
-  const int kc0 = (int)((int64_t)kchunks * sl / ks), kc1 = (int)((int64_t)kchunks * (sl + 1) / ks);
   double ssa = 0.0;
   d4 acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  ax_accumulate<TA, NT>(A, W, sW, m, n, c, layout, tile, kc0 * kAxKC, min(n, kc1 * kAxKC), acc, ssa);
-  double* pp = part + (int64_t)blockIdx.x * 64 * WP;
+  for (int kc = w; kc < kchunks; kc += kThreads / 64) {
+    const int k0 = kc * kAxKC;
+    const int kl = min(kAxKC, n - k0);
+    for (int e = lane; e < kAxKC * NT * 16; e += 64) {
+      const int kk = e / (NT * 16), cc = e % (NT * 16);
+      sW[w][kk][cc] = (kk < kl && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double a[kAxKC / 4];
+    ax_load_chunk<TA, LY>(A, m, n, row, rok, k0, n, a);
+#pragma unroll
+    for (int u = 0; u < kAxKC / 4; ++u) ssa = fma(a[u], a[u], ssa);
+#pragma unroll
+    for (int ss = 0; ss < kAxKC / 32; ++ss) {
+      const int kb = 32 * ss + 8 * g;
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[ss * 8 + s8], sW[w][kb + s8][16 * q + li], acc[q]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 #pragma unroll
   for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) pp[(16 * w + g + 4 * v) * WP + 16 * q + li] = acc[q][v];
-  __threadfence();
+    for (int v = 0; v < 4; ++v) sR(w, g + 4 * v, 16 * q + li) = acc[q][v];
   __syncthreads();
-  if (t == 0) s_last = (atomicAdd(&cnt[tile], 1u) == (unsigned)(ks - 1));
-  __syncthreads();
-  const bool last = s_last != 0;
   double ssy = 0.0, sse = 0.0;
-  if (last) {
-    __threadfence();
-    const double* base = part + (int64_t)tile * ks * 64 * WP;
-    for (int e = t; e < 64 * c; e += kThreads) {
-      int rr, col;
-      if (layout == ROW) { rr = e / c; col = e % c; } else { rr = e % 64; col = e / 64; }
-      const int64_t row = (int64_t)tile * 64 + rr;
-      if (row >= m) continue;
-      double sum = 0.0;
-      for (int q = 0; q < ks; ++q) sum += base[((int64_t)q * 64 + rr) * WP + col];
-      const TY y = (TY)sum;
-      const double yd = (double)y;
-      ssy = fma(yd, yd, ssy);
-      const double er = sum - yd;
-      sse = fma(er, er, sse);
-      Y[at(layout, row, col, m, c)] = y;
-    }
-    if (t == 0) cnt[tile] = 0u;
+  for (int e = t; e < 16 * c; e += kThreads) {
+    int rr, col;
+    if (LY == ROW) { rr = e / c; col = e % c; } else { rr = e % 16; col = e / 16; }
+    const int64_t yr = (int64_t)blockIdx.x * 16 + rr;
+    if (yr >= m) continue;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) sum += sR(q, rr, col);
+    const TY y = (TY)sum;
+    const double yd = (double)y;
+    ssy = fma(yd, yd, ssy);
+    const double er = sum - yd;
+    sse = fma(er, er, sse);
+    Y[at(LY, yr, col, m, c)] = y;
   }
   if (sumsqA) {
     const double s = block_sum(ssa, sh);
@@ -348,17 +407,11 @@ __global__ __launch_bounds__(kThreads) void k_ax_sk(const TA* __restrict__ A, co
   }
   if (sumsqY) {
     const double s = block_sum(ssy, sh);
-    if (t == 0) {
-      if (last) sumsqY[(int64_t)tile * ks] = s;
-      if (sl != 0) sumsqY[blockIdx.x] = 0.0;
-    }
+    if (t == 0) sumsqY[blockIdx.x] = s;
   }
   if (rerr) {
     const double s = block_sum(sse, sh);
-    if (t == 0) {
-      if (last) rerr[(int64_t)tile * ks] = s;
-      if (sl != 0) rerr[blockIdx.x] = 0.0;
-    }
+    if (t == 0) rerr[blockIdx.x] = s;
   }
 }
 
@@ -496,82 +549,60 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
   return hipGetLastError();
 }
 
-int ax_ksplit(int64_t m, int n) {
-  const int64_t tiles = (m + 63) / 64;
-  const int kchunks = (n + kAxKC - 1) / kAxKC;
-  if (tiles >= kAxSplitTiles || kchunks < 2) return 1;
-  const int ks = (int)((256 + tiles - 1) / tiles);
-  return ks < kchunks ? ks : kchunks;
-}
+// Short A: the k range is split over the waves of a workgroup of 16 rows.
+static bool ax_short(int64_t m, int n) { return (m + 63) / 64 < kAxSplitTiles && n > kAxKC; }
 
 int ax_chunks(int64_t m, int n, int c) {
   (void)c;
+  if (ax_short(m, n)) return (int)((m + 15) / 16);
   const int64_t tiles = (m + 63) / 64;
-  const int ks = ax_ksplit(m, n);
-  if (ks > 1) return (int)(tiles * ks);
   return (int)(tiles < 8192 ? tiles : 8192);
 }
 
-int64_t ax_split_elems(int64_t m, int n, int c) {
-  const int ks = ax_ksplit(m, n);
-  if (ks <= 1) return 0;
-  const int64_t tiles = (m + 63) / 64;
-  return tiles * ks * 64 * (int64_t)(((c + 15) / 16) * 16);
+template <typename TA, typename TY, int LY>
+static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int nchunks,
+                          double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
+  dim3 grid(nchunks), block(kThreads);
+  if (ax_short(m, n)) {
+    if (c <= 16)
+      hipLaunchKernelGGL((k_ax_kw<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    else if (c <= 32)
+      hipLaunchKernelGGL((k_ax_kw<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    else if (c <= 48)
+      hipLaunchKernelGGL((k_ax_kw<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    else
+      hipLaunchKernelGGL((k_ax_kw<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    return;
+  }
+  if (c <= 16)
+    hipLaunchKernelGGL((k_ax<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+  else if (c <= 32)
+    hipLaunchKernelGGL((k_ax<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+  else if (c <= 48)
+    hipLaunchKernelGGL((k_ax<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+  else
+    hipLaunchKernelGGL((k_ax<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
 }
 
 template <typename TA, typename TY>
 static void ax_dispatch(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int layout,
-                        int nchunks, double* sumsqA, double* sumsqY, double* rerr, double* skpart, unsigned* skcnt,
-                        hipStream_t st) {
-  dim3 grid(nchunks), block(kThreads);
-  const int ks = ax_ksplit(m, n);
-  if (ks > 1) {
-    if (c <= 16)
-      hipLaunchKernelGGL((k_ax_sk<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
-    else if (c <= 32)
-      hipLaunchKernelGGL((k_ax_sk<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
-    else if (c <= 48)
-      hipLaunchKernelGGL((k_ax_sk<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
-    else
-      hipLaunchKernelGGL((k_ax_sk<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, ks, skpart, skcnt, sumsqA, sumsqY, rerr);
-    return;
-  }
-  if (c <= 16)
-    hipLaunchKernelGGL((k_ax<TA, TY, 1>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
-  else if (c <= 32)
-    hipLaunchKernelGGL((k_ax<TA, TY, 2>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
-  else if (c <= 48)
-    hipLaunchKernelGGL((k_ax<TA, TY, 3>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
-  else
-    hipLaunchKernelGGL((k_ax<TA, TY, 4>), grid, block, 0, st, A, W, Y, m, n, c, layout, sumsqA, sumsqY, rerr);
+                        int nchunks, double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
+  if (layout == ROW) ax_dispatch_l<TA, TY, ROW>(A, W, Y, m, n, c, nchunks, sumsqA, sumsqY, rerr, st);
+  else ax_dispatch_l<TA, TY, COL>(A, W, Y, m, n, c, nchunks, sumsqA, sumsqY, rerr, st);
 }
 
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m, int n,
                      int c, int layout, int nchunks, double* sumsqA, double* sumsqY, double* rerr,
-                     const AxScratch& sk, hipStream_t st) {
+                     hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks != ax_chunks(m, n, c)) return hipErrorInvalidValue;
-  if (ax_ksplit(m, n) > 1 && (!sk.part || !sk.cnt || sk.part_elems < ax_split_elems(m, n, c) ||
-                              sk.ncnt < (m + 63) / 64))
-    return hipErrorInvalidValue;
   if (!a_f32 && !y_f32)
-    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
+    ax_dispatch((const double*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else if (a_f32 && !y_f32)
-    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
+    ax_dispatch((const float*)A, W, (double*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else if (a_f32 && y_f32)
-    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
+    ax_dispatch((const float*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   else
-    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, sk.part, sk.cnt, st);
-  return hipGetLastError();
-}
-
-__global__ void k_zero_u32(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
-hipError_t launch_zero_counters(unsigned* cnt, int n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, cnt, n);
+    ax_dispatch((const double*)A, W, (float*)Y, m, n, c, layout, nchunks, sumsqA, sumsqY, rerr, st);
   return hipGetLastError();
 }
 
