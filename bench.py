@@ -147,10 +147,12 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = tensor_bytes / (ms_per_step * 1e-3) / 1e9
     if args.copy_probe:
+        # an elementwise kernel (a device-to-device copy_ would go to the DMA engines,
+        # which the counters do not see): reads and writes the tensor once
         B = torch.empty_like(A)
-        B.copy_(A)
+        torch.mul(A, 1.0, out=B)
         torch.cuda.synchronize()
-        log(f"bench: copy probe moved {tensor_bytes} bytes read + {tensor_bytes} bytes written")
+        log(f"bench: copy probe kernel read {tensor_bytes} bytes and wrote {tensor_bytes} bytes")
         del B
     rep = dec.report()
     cores = dec.cores()

@@ -37,6 +37,13 @@ enum KClass { KC_ATB = 0, KC_AX = 1, KC_GRAM_Y = 2, KC_CARRY = 3, KC_RESID = 4, 
 const char* const kClassNames[TT_NKCLASS] = {"tall_atb", "tall_ax", "gram_y", "carry", "resid", "reduce", "small"};
 
 thread_local std::vector<hipEvent_t> g_events;
+}  // namespace
+
+namespace ttutv {
+thread_local LaunchTiming g_launch_timing;
+}
+
+namespace {
 
 struct Prof {
   bool on = false;
@@ -67,14 +74,13 @@ struct Prof {
     const bool tm_ = (P).on && (((P).mask >> (cls)) & 1);                          \
     if (tm_) {                                                                     \
       HIP_OK((P).event(&ea_));                                                     \
-      HIP_OK(hipEventRecord(ea_, (P).st));                                         \
-    }                                                                              \
-    HIP_OK(expr);                                                                  \
-    if (tm_) {                                                                     \
       HIP_OK((P).event(&eb_));                                                     \
-      HIP_OK(hipEventRecord(eb_, (P).st));                                         \
-      (P).recs.push_back({(cls), ea_, eb_, (double)(nbytes), (double)(nflops)});  \
+      g_launch_timing = LaunchTiming{ea_, eb_};                                    \
     }                                                                              \
+    const hipError_t le_ = (expr);                                                 \
+    g_launch_timing = LaunchTiming{};                                              \
+    HIP_OK(le_);                                                                   \
+    if (tm_) (P).recs.push_back({(cls), ea_, eb_, (double)(nbytes), (double)(nflops)}); \
   } while (0)
 
 // One truncated UTV step of the sweep, in the tall frame: the m x n matrix A

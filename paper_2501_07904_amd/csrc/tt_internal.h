@@ -1,10 +1,28 @@
 // Internal declarations shared by the HIP translation units of libttutv.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 #include <stdint.h>
 
 namespace ttutv {
+
+// Kernel timing: while `timing.start` is set on the calling thread, the one
+// kernel the next launcher enqueues carries the two events in its own
+// dispatch (hipExtLaunchKernelGGL), so the events bracket exactly that kernel.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+#define TT_LAUNCH(kernel, grid, block, shm, st, ...)                                                  \
+  do {                                                                                              \
+    if (::ttutv::g_launch_timing.start)                                                             \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ::ttutv::g_launch_timing.start,           \
+                            ::ttutv::g_launch_timing.stop, 0, __VA_ARGS__);                         \
+    else                                                                                            \
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                                \
+  } while (0)
 
 // Storage of a tall m x n matrix (m >= 1 rows on the long side, n columns on
 // the core side).  ROW: element (i, j) at i*n + j (left-to-right sweep, where

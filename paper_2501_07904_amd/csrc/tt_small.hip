@@ -787,9 +787,9 @@ __global__ __launch_bounds__(kThreads) void k_orth_reg(const double* M, double* 
 template <int R>
 static void launch_orth_reg(double* M, double* X, int n, int c, hipStream_t st) {
   const int tpj = reg_group_width(c);
-  if (tpj == 16) hipLaunchKernelGGL((k_orth_reg<R, 16>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
-  else if (tpj == 32) hipLaunchKernelGGL((k_orth_reg<R, 32>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
-  else hipLaunchKernelGGL((k_orth_reg<R, 64>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  if (tpj == 16) TT_LAUNCH((k_orth_reg<R, 16>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  else if (tpj == 32) TT_LAUNCH((k_orth_reg<R, 32>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
+  else TT_LAUNCH((k_orth_reg<R, 64>), dim3(1), dim3(kThreads), 0, st, M, X, n, c);
 }
 
 // --------------------------------------------------------------------------
@@ -969,14 +969,14 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restr
 
 hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st) {
   if (a.n < 1 || a.n > kGramMax || a.ell < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gram_solve, dim3(1), dim3(kThreads), 0, st, H, a);
+  TT_LAUNCH(k_gram_solve, dim3(1), dim3(kThreads), 0, st, H, a);
   return hipGetLastError();
 }
 
 hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st) {
   const int64_t total = (int64_t)a.n * a.ell;
   if (total < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gen_sketch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, G, a);
+  TT_LAUNCH(k_gen_sketch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, G, a);
   return hipGetLastError();
 }
 
@@ -986,14 +986,14 @@ hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st) {
     case 4: launch_orth_reg<4>(M, X, n, c, st); break;
     case 8: launch_orth_reg<8>(M, X, n, c, st); break;
     case 16: launch_orth_reg<16>(M, X, n, c, st); break;
-    default: hipLaunchKernelGGL(k_orth, dim3(1), dim3(kThreads), 0, st, M, X, n, c); break;
+    default: TT_LAUNCH(k_orth, dim3(1), dim3(kThreads), 0, st, M, X, n, c); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st) {
   if (a.n < 1 || a.ell < 1 || a.ell > kCMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rr_solve, dim3(1), dim3(kRRThreads), 0, st, K, X, a);
+  TT_LAUNCH(k_rr_solve, dim3(1), dim3(kRRThreads), 0, st, K, X, a);
   return hipGetLastError();
 }
 
@@ -1002,12 +1002,12 @@ hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a,
 namespace ttutv {
 hipError_t launch_alg4_basis(const double* K, double* T, int ell, hipStream_t st) {
   if (ell < 1 || ell > kCMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_alg4_basis, dim3(1), dim3(kRRThreads), 0, st, K, T, ell);
+  TT_LAUNCH(k_alg4_basis, dim3(1), dim3(kRRThreads), 0, st, K, T, ell);
   return hipGetLastError();
 }
 hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs& a, hipStream_t st) {
   if (a.n < 1 || a.ell < 1 || a.ell > kCMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_alg4_solve, dim3(1), dim3(kRRThreads), 0, st, E, Bt, a);
+  TT_LAUNCH(k_alg4_solve, dim3(1), dim3(kRRThreads), 0, st, E, Bt, a);
   return hipGetLastError();
 }
 }  // namespace ttutv

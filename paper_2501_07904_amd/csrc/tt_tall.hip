@@ -416,6 +416,172 @@ __global__ __launch_bounds__(kThreads) void k_ax_kw(const TA* __restrict__ A, co
 }
 
 // ---------------------------------------------------------------------------
+// Narrow A (n <= 64 columns).  No LDS staging and no block barrier in the row
+// loop: every wave streams its own 16-row blocks straight into the MFMA
+// operands, prefetching the next block while the current one is multiplied.
+// Within a block of 16 rows the k-slot g of MFMA step s is row 4s + g, so one
+// load instruction covers four consecutive rows of 16 columns.
+
+// partials[chunk] = A^T A over the rows of chunk (n <= 64, NB = ceil(n/16)
+// column blocks).  Only the blocks I <= J are multiplied (both operands of a
+// Gram block come from the same registers); the lower blocks are written by
+// symmetry.  The four waves' partial blocks are summed in LDS in wave order.
+template <int NB, int LY>
+__global__ __launch_bounds__(kThreads) void k_gram_narrow(const double* __restrict__ A, int64_t m, int n,
+                                                          int64_t rows_per_chunk, double* __restrict__ partials) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  __shared__ double sR[kThreads / 64][NP][16][17];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(m, r0 + rows_per_chunk);
+  d4 acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  auto load = [&](int64_t i0, double (*a)[4]) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t i = i0 + 4 * s4 + g;
+      const bool rok = i < r1;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = 16 * b + li;
+        a[b][s4] = (rok && j < n) ? A[LY == ROW ? i * n + j : i + (int64_t)j * m] : 0.0;
+      }
+    }
+  };
+  double a[NB][4], an[NB][4];
+  int64_t i0 = r0 + 16 * w;
+  if (i0 < r1) load(i0, a);
+  for (; i0 < r1; i0 += 16 * (kThreads / 64)) {
+    const int64_t i1 = i0 + 16 * (kThreads / 64);
+    if (i1 < r1) load(i1, an);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      int q = 0;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj, ++q) acc[q] = mfma_f64(a[bi][s4], a[bj][s4], acc[q]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) a[b][s4] = an[b][s4];
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sR[w][q][g + 4 * v][li] = acc[q][v];
+  __syncthreads();
+  double* out = partials + (int64_t)blockIdx.x * n * n;
+  for (int e = t; e < NP * 256; e += kThreads) {
+    const int q = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+    int bi = 0, bj = 0, k = 0;
+#pragma unroll
+    for (int x = 0; x < NB; ++x)
+#pragma unroll
+      for (int y = x; y < NB; ++y, ++k)
+        if (k == q) { bi = x; bj = y; }
+    const double v = ((sR[0][q][rr][cc] + sR[1][q][rr][cc]) + (sR[2][q][rr][cc] + sR[3][q][rr][cc]));
+    const int j = 16 * bi + rr, c2 = 16 * bj + cc;
+    if (j < n && c2 < n) {
+      out[j + (int64_t)n * c2] = v;
+      if (bi != bj) out[c2 + (int64_t)n * j] = v;
+    }
+  }
+}
+
+// Y = A W for n <= 64: W (k-major) stays in registers as the B operand for the
+// whole launch (lane (g, li) holds W(4s + g, 16t + li)); each wave streams
+// 16-row blocks; the result block goes through a wave-private LDS tile so that
+// Y is written in full cache lines (16 consecutive rows of a column, or the
+// contiguous 16 x c block in row-major storage).
+template <typename TA, typename TY, int NT, int NK, int LY>
+__global__ __launch_bounds__(kThreads) void k_ax_narrow(const TA* __restrict__ A, const double* __restrict__ W,
+                                                        TY* __restrict__ Y, int64_t m, int n, int c,
+                                                        double* __restrict__ sumsqA, double* __restrict__ sumsqY,
+                                                        double* __restrict__ rerr) {
+  __shared__ double sT[kThreads / 64][16][NT * 16 + 1];
+  __shared__ double sh[8];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  double wr[NK][NT];
+#pragma unroll
+  for (int s4 = 0; s4 < NK; ++s4)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int k = 4 * s4 + g, col = 16 * q + li;
+      wr[s4][q] = (k < n && col < c) ? W[(int64_t)k * c + col] : 0.0;
+    }
+  double ssa = 0.0, ssy = 0.0, sse = 0.0;
+  const int64_t nblk = (m + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
+  auto load = [&](int64_t b, double* a) {
+    const int64_t row = b * 16 + li;
+    const bool rok = row < m;
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      const int k = 4 * s4 + g;
+      a[s4] = (rok && k < n) ? (double)A[LY == ROW ? row * n + k : row + (int64_t)k * m] : 0.0;
+    }
+  };
+  double a[NK], an[NK];
+  int64_t b = (int64_t)blockIdx.x * (kThreads / 64) + w;
+  if (b < nblk) load(b, a);
+  for (; b < nblk; b += stride) {
+    if (b + stride < nblk) load(b + stride, an);
+    d4 acc[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      ssa = fma(a[s4], a[s4], ssa);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[s4], wr[s4][q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sT[w][g + 4 * v][16 * q + li] = acc[q][v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < 16 * c; e += 64) {
+      int rr, col;
+      if (LY == ROW) { rr = e / c; col = e % c; } else { rr = e & 15; col = e >> 4; }
+      const int64_t yr = b * 16 + rr;
+      if (yr < m) {
+        const double s = sT[w][rr][col];
+        const TY y = (TY)s;
+        const double yd = (double)y;
+        ssy = fma(yd, yd, ssy);
+        const double er = s - yd;
+        sse = fma(er, er, sse);
+        Y[at(LY, yr, col, m, c)] = y;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) a[s4] = an[s4];
+  }
+  if (sumsqA) {
+    const double s = block_sum(ssa, sh);
+    if (t == 0) sumsqA[blockIdx.x] = s;
+  }
+  if (sumsqY) {
+    const double s = block_sum(ssy, sh);
+    if (t == 0) sumsqY[blockIdx.x] = s;
+  }
+  if (rerr) {
+    const double s = block_sum(sse, sh);
+    if (t == 0) rerr[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // resid[chunk] = sum over rows of ||A(i,:) - Cr(i,:) V1^T||^2 (direct step
 // error); V1 (n x r) is stored k-major like the right operand of k_ax.
 constexpr int kResTR = 64;
@@ -524,27 +690,42 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
     // FP64 operands: matrix-core kernel (Gram: Y == A with c == n <= 64)
     const bool gram = (A == Y);
     if (gram && (c != n || n > kAtbJT)) return hipErrorInvalidValue;
+    if (gram) {
+      const int nb = (n + 15) / 16;
+#define TT_GRN(NBV)                                                                                        \
+  do {                                                                                                     \
+    if (layout == ROW)                                                                                     \
+      TT_LAUNCH((k_gram_narrow<NBV, ROW>), dim3(nchunks), dim3(kThreads), 0, st, (const double*)A, m, n, rpc, \
+                partials);                                                                                 \
+    else                                                                                                   \
+      TT_LAUNCH((k_gram_narrow<NBV, COL>), dim3(nchunks), dim3(kThreads), 0, st, (const double*)A, m, n, rpc, \
+                partials);                                                                                 \
+  } while (0)
+      if (nb == 1) TT_GRN(1); else if (nb == 2) TT_GRN(2); else if (nb == 3) TT_GRN(3); else TT_GRN(4);
+#undef TT_GRN
+      return hipGetLastError();
+    }
     if (c <= 16)
-      hipLaunchKernelGGL((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+      TT_LAUNCH((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
     else if (c <= 32)
-      hipLaunchKernelGGL((k_atb_mfma<2>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+      TT_LAUNCH((k_atb_mfma<2>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
     else if (c <= 48)
-      hipLaunchKernelGGL((k_atb_mfma<3>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+      TT_LAUNCH((k_atb_mfma<3>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
     else
-      hipLaunchKernelGGL((k_atb_mfma<4>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
+      TT_LAUNCH((k_atb_mfma<4>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
   }
   else if (a_f32 && y_f32)
-    hipLaunchKernelGGL((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
+    TT_LAUNCH((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
                        (const float*)Y, m, n, c, layout, rpc, partials);
   else if (a_f32)
-    hipLaunchKernelGGL((k_atb<float, double>), grid, dim3(kThreads), 0, st, (const float*)A,
+    TT_LAUNCH((k_atb<float, double>), grid, dim3(kThreads), 0, st, (const float*)A,
                        (const double*)Y, m, n, c, layout, rpc, partials);
   else
-    hipLaunchKernelGGL((k_atb<double, float>), grid, dim3(kThreads), 0, st, (const double*)A,
+    TT_LAUNCH((k_atb<double, float>), grid, dim3(kThreads), 0, st, (const double*)A,
                        (const float*)Y, m, n, c, layout, rpc, partials);
   return hipGetLastError();
 }
@@ -552,8 +733,20 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
 // Short A: the k range is split over the waves of a workgroup of 16 rows.
 static bool ax_short(int64_t m, int n) { return (m + 63) / 64 < kAxSplitTiles && n > kAxKC; }
 
+// Narrow A: W fits the registers of every lane (NK * ceil(c/16) <= 32 doubles, NK =
+// ceil(n/4) rounded up to the instantiated 4, 8 or 16).
+static int ax_nk(int n) {
+  const int nk = (n + 3) / 4;
+  return nk <= 4 ? 4 : (nk <= 8 ? 8 : 16);
+}
+static bool ax_narrow(int n, int c) { return n <= 64 && ax_nk(n) * ((c + 15) / 16) <= 32; }
+constexpr int kNarrowGroups = 2048;   // workgroups of the narrow kernel (grid-stride over row blocks)
+
 int ax_chunks(int64_t m, int n, int c) {
-  (void)c;
+  if (ax_narrow(n, c)) {
+    const int64_t groups = ((m + 15) / 16 + 3) / 4;
+    return (int)(groups < kNarrowGroups ? groups : kNarrowGroups);
+  }
   if (ax_short(m, n)) return (int)((m + 15) / 16);
   const int64_t tiles = (m + 63) / 64;
   return (int)(tiles < 8192 ? tiles : 8192);
@@ -563,25 +756,35 @@ template <typename TA, typename TY, int LY>
 static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int nchunks,
                           double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
   dim3 grid(nchunks), block(kThreads);
+  if (ax_narrow(n, c)) {
+    const int nk = ax_nk(n);
+#define TT_AXN(NTV, NKV) TT_LAUNCH((k_ax_narrow<TA, TY, NTV, NKV, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
+    if (c <= 16) { if (nk <= 4) TT_AXN(1, 4); else if (nk <= 8) TT_AXN(1, 8); else TT_AXN(1, 16); }
+    else if (c <= 32) { if (nk <= 4) TT_AXN(2, 4); else if (nk <= 8) TT_AXN(2, 8); else TT_AXN(2, 16); }
+    else if (c <= 48) { if (nk <= 4) TT_AXN(3, 4); else TT_AXN(3, 8); }
+    else { if (nk <= 4) TT_AXN(4, 4); else TT_AXN(4, 8); }
+#undef TT_AXN
+    return;
+  }
   if (ax_short(m, n)) {
     if (c <= 16)
-      hipLaunchKernelGGL((k_ax_kw<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else if (c <= 32)
-      hipLaunchKernelGGL((k_ax_kw<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else if (c <= 48)
-      hipLaunchKernelGGL((k_ax_kw<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else
-      hipLaunchKernelGGL((k_ax_kw<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     return;
   }
   if (c <= 16)
-    hipLaunchKernelGGL((k_ax<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    TT_LAUNCH((k_ax<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
   else if (c <= 32)
-    hipLaunchKernelGGL((k_ax<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    TT_LAUNCH((k_ax<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
   else if (c <= 48)
-    hipLaunchKernelGGL((k_ax<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    TT_LAUNCH((k_ax<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
   else
-    hipLaunchKernelGGL((k_ax<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    TT_LAUNCH((k_ax<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
 }
 
 template <typename TA, typename TY>
@@ -617,13 +820,13 @@ hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, con
   const int64_t rpc = (m + nchunks - 1) / nchunks;
   dim3 g(nchunks), b(kThreads);
   if (a_f32 && c_f32)
-    hipLaunchKernelGGL((k_resid<float, float>), g, b, 0, st, (const float*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
+    TT_LAUNCH((k_resid<float, float>), g, b, 0, st, (const float*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
   else if (a_f32)
-    hipLaunchKernelGGL((k_resid<float, double>), g, b, 0, st, (const float*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
+    TT_LAUNCH((k_resid<float, double>), g, b, 0, st, (const float*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
   else if (c_f32)
-    hipLaunchKernelGGL((k_resid<double, float>), g, b, 0, st, (const double*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
+    TT_LAUNCH((k_resid<double, float>), g, b, 0, st, (const double*)A, (const float*)Cr, V1, m, n, r, layout, rpc, resid);
   else
-    hipLaunchKernelGGL((k_resid<double, double>), g, b, 0, st, (const double*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
+    TT_LAUNCH((k_resid<double, double>), g, b, 0, st, (const double*)A, (const double*)Cr, V1, m, n, r, layout, rpc, resid);
   return hipGetLastError();
 }
 
@@ -631,11 +834,11 @@ hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, doub
                          double* out2, hipStream_t st) {
   if (size < 1 || nchunks < 1) return hipErrorInvalidValue;
   if (size == 1) {
-    hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(kThreads), 0, st, partials, nchunks, out, out2);
+    TT_LAUNCH(k_reduce_scalar, dim3(1), dim3(kThreads), 0, st, partials, nchunks, out, out2);
     return hipGetLastError();
   }
   const int64_t blocks = (size + 15) / 16;
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
+  TT_LAUNCH(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
                      size, out, out2);
   return hipGetLastError();
 }

@@ -183,9 +183,9 @@ hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f
   if (gy > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)gx, (unsigned)gy);
   if (c_f32)
-    hipLaunchKernelGGL((k_gemm_smallk<float>), grid, dim3(kThreads), 0, st, A, B, (float*)C, M, N, K);
+    TT_LAUNCH((k_gemm_smallk<float>), grid, dim3(kThreads), 0, st, A, B, (float*)C, M, N, K);
   else
-    hipLaunchKernelGGL((k_gemm_smallk<double>), grid, dim3(kThreads), 0, st, A, B, (double*)C, M, N, K);
+    TT_LAUNCH((k_gemm_smallk<double>), grid, dim3(kThreads), 0, st, A, B, (double*)C, M, N, K);
   return hipGetLastError();
 }
 
@@ -203,7 +203,7 @@ hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
   TrainDesc D;
   if (!fill_desc(D, d, dims, ranks, cores) || N < 0) return hipErrorInvalidValue;
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sample, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, out);
+  TT_LAUNCH(k_sample, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, out);
   return hipGetLastError();
 }
 
@@ -216,10 +216,10 @@ hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
   for (int k = 0; k < d; ++k) G.cores[k] = gcores[k];
   for (int k = 0; k < d; ++k) {
     const int64_t sz = ranks[k] * dims[k] * ranks[k + 1];
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((sz + 255) / 256)), dim3(256), 0, st, gcores[k], sz);
+    TT_LAUNCH(k_fill_zero, dim3((unsigned)((sz + 255) / 256)), dim3(256), 0, st, gcores[k], sz);
   }
   if (N > 0)
-    hipLaunchKernelGGL(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, gout, G);
+    TT_LAUNCH(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, gout, G);
   return hipGetLastError();
 }
 
