@@ -70,16 +70,22 @@ typedef struct {
                                TT_PROFILE_ALL = every class) whose launches are timed
                                with HIP events on the caller's stream, filling
                                tt_report.kstat; 0 = no events */
-  int32_t prec;             /* tt_prec: TT_PREC_FP64 or TT_PREC_MIXED */
+  int32_t prec;             /* tt_prec: TT_PREC_FP64, TT_PREC_MIXED or TT_PREC_MIXED_BF16 */
 } tt_opts;
 
 /* TT_PREC_FP64: every carry, sketch and product in FP64.
  * TT_PREC_MIXED: carries and power iterates stored in FP32 (half the traffic
- * of every pass after the first), all accumulation in FP64; the final
- * Rayleigh-Ritz pass, its Gram matrix, the factorisations and the rank rule
+ * of every pass after the first); the power products run on FP32 matrix cores
+ * (FP32 operands and accumulation); the final Rayleigh-Ritz pass reads A with
+ * FP64 accumulation, and its Gram matrix, the factorisations and the rank rule
  * stay FP64.  Storing carry k in FP32 perturbs it by rho_k (measured exactly);
- * the report's err_bound is then sqrt(sum delta_k^2) + sum rho_k. */
-typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1 } tt_prec;
+ * the report's err_bound is then sqrt(sum delta_k^2) + sum rho_k (sum delta_k
+ * + sum rho_k for Alg. 4).
+ * TT_PREC_MIXED_BF16: as TT_PREC_MIXED with the power products on BF16
+ * operands (FP32 accumulation): the sketch resolves singular directions only
+ * to about 4e-3 of the largest, which costs rank (or, under a rank cap, the
+ * tolerance) at prescribed accuracies below about 1e-3; the bound stays valid. */
+typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1, TT_PREC_MIXED_BF16 = 2 } tt_prec;
 
 /* Kernel classes of the profile (tt_kernel_class_name gives their names). */
 #define TT_NKCLASS 7
@@ -103,7 +109,7 @@ typedef struct {
   int32_t d;
   tt_kstat kstat[TT_NKCLASS];   /* classes selected by opts.profile */
   int32_t sweeps[TT_MAX_D];     /* Jacobi sweeps of the Rayleigh-Ritz step of unfolding k */
-  double rho[TT_MAX_D];         /* TT_PREC_MIXED: ||carry - fl32(carry)||_F of unfolding k */
+  double rho[TT_MAX_D];         /* mixed forms: ||carry - fl32(carry)||_F of unfolding k */
 } tt_report;
 
 /* Name of kernel class c (0 <= c < TT_NKCLASS), or NULL. */

@@ -6,5 +6,5 @@ baseline leg of the benchmark do.  It shares no code with the HIP library.
 """
 from .ttutv_oracle import (  # noqa: F401
     sketch_gaussian, splitmix64, tt_utv, tt_svd, tt_reconstruct, tt_sample,
-    tt_sample_grad, step_tall_view, canonical_signs,
+    tt_sample_grad, step_tall_view, canonical_signs, completion_step,
 )

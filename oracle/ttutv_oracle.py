@@ -489,3 +489,23 @@ def tt_sample_grad(cores, idx, w):
         np.add.at(g, (slice(None), idx[:, k], slice(None)), np.transpose(contrib, (1, 0, 2)))
         grads.append(g)
     return grads
+
+
+# --------------------------------------------------------------------------
+# Masked completion (the differentiation extension): gradient descent on the
+# cores of f = 1/2 sum over observed entries (A_TT[idx_s] - m_s)^2.
+def completion_step(cores, idx, vals):
+    """One gradient step with the linearised exact step size: with residual
+    e = A_TT[idx] - m and core gradients g, the sampled directional derivative
+    J g = sum_k (train with core k replaced by g_k)[idx]; alpha minimises
+    ||e - alpha J g||^2, i.e. alpha = <e, J g> / ||J g||^2.  Returns (new
+    cores, f before the step, alpha)."""
+    e = tt_sample(cores, idx) - np.asarray(vals, dtype=np.float64)
+    f = 0.5 * float(e @ e)
+    g = tt_sample_grad(cores, idx, e)
+    jg = np.zeros_like(e)
+    for k in range(len(cores)):
+        jg += tt_sample(cores[:k] + [g[k]] + cores[k + 1:], idx)
+    den = float(jg @ jg)
+    alpha = float(e @ jg) / den if den > 0 else 0.0
+    return [c - alpha * gk for c, gk in zip(cores, g)], f, alpha

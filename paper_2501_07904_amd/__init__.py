@@ -122,7 +122,7 @@ def _full_ranks(ranks, d):
     return r
 
 
-PRECS = {"fp64": 0, "mixed": 1}
+PRECS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 
 
 def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,

@@ -110,6 +110,7 @@ struct Problem {
   double w[TT_MAX_D];
   bool alg4;
   bool mixed;   // carries and power iterates stored in FP32
+  int bf16;     // mixed form with BF16 power products
 };
 
 int64_t prod(const int64_t* v, int a, int b) {  // v[a] * ... * v[b-1]
@@ -137,8 +138,10 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
   if (P.o.oversample < 0 || P.o.oversample > TT_MAX_ELL)
     return fail(TT_EINVAL, "oversample = %d outside [0, %d]", P.o.oversample, TT_MAX_ELL);
   if (P.o.max_rank < 0) return fail(TT_EINVAL, "max_rank < 0");
-  if (P.o.prec != TT_PREC_FP64 && P.o.prec != TT_PREC_MIXED) return fail(TT_EINVAL, "bad prec %d", P.o.prec);
-  P.mixed = (P.o.prec == TT_PREC_MIXED);
+  if (P.o.prec != TT_PREC_FP64 && P.o.prec != TT_PREC_MIXED && P.o.prec != TT_PREC_MIXED_BF16)
+    return fail(TT_EINVAL, "bad prec %d", P.o.prec);
+  P.mixed = (P.o.prec != TT_PREC_FP64);
+  P.bf16 = (P.o.prec == TT_PREC_MIXED_BF16) ? 1 : 0;
   P.sweep = sweep;
   P.variant = variant;
   P.dtype = dtype;
@@ -337,7 +340,7 @@ struct StepIO {
 };
 
 int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
-             const StepRec* prev, const Work& W, hipStream_t st, Prof& PF) {
+             const StepRec* prev, const Work& W, hipStream_t st, Prof& PF, bool retry) {
   SolveArgs a{};
   a.n = s.n;
   a.ell = ell;
@@ -366,12 +369,15 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double mn = (double)m * n;
   if (step_gram(P, s)) {
-    // H = A^T A in one pass, then everything else on n x n
-    const int nch = atb_chunks(m, n, n);
-    LAUNCH(PF, KC_ATB, mn * sa + (double)n * n * 8, 2.0 * mn * n,
-           launch_atb(io.A, io.a_f32, io.A, io.a_f32, m, n, n, s.layout, W.part, nch, st));
-    LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * n * 8, (double)nch * n * n,
-           launch_reduce(W.part, nch, (int64_t)n * n, W.H, nullptr, st));
+    // H = A^T A in one pass, then everything else on n x n (a retry with a wider
+    // sketch reuses H: it does not depend on ell)
+    if (!retry) {
+      const int nch = atb_chunks(m, n, n);
+      LAUNCH(PF, KC_ATB, mn * sa + (double)n * n * 8, 2.0 * mn * n,
+             launch_atb(io.A, io.a_f32, io.A, io.a_f32, m, n, n, s.layout, W.part, nch, st));
+      LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * n * 8, (double)nch * n * n,
+             launch_reduce(W.part, nch, (int64_t)n * n, W.H, nullptr, st));
+    }
     LAUNCH(PF, KC_SMALL, 0, 0, launch_gram_solve(W.H, a, st));
   } else if (!P.alg4) {
     // sketch and q+1 power steps: X <- orth(A^T (A X)), starting from X = G
@@ -380,24 +386,42 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     const double mc = (double)m * c;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
     for (int it = 0; it <= P.o.q; ++it) {
-      // power iterates: FP32 storage in mixed precision
-      const double sy = P.mixed ? 4.0 : 8.0;
-      LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
-             launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,
-                       (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
-      if (first && it == 0)
-        LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
-      const int nch = atb_chunks(m, n, c);
-      LAUNCH(PF, KC_ATB, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
-             launch_atb(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, W.part, nch, st));
-      LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
-             launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      if (P.mixed) {
+        // mixed precision: power products on FP32 (or BF16) operands with FP32
+        // accumulation, FP32 iterate
+        LAUNCH(PF, KC_AX, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
+               launch_ax_lp(io.A, io.a_f32, W.X, (float*)W.Y, m, n, c, s.layout, P.bf16, st));
+        const int nch = atb_lp_chunks(m, n);
+        if (P.bf16)
+          LAUNCH(PF, KC_ATB, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
+                 launch_atb_lp(io.A, io.a_f32, (const float*)W.Y, m, n, c, s.layout, W.part, nch, 1, st));
+        else
+          LAUNCH(PF, KC_ATB, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
+                 launch_atb2(io.A, io.a_f32, W.Y, 1, m, n, c, s.layout, io.a_f32, W.part, nch, st));
+        LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+               launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      } else {
+        LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+               launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
+                         (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
+        if (first && it == 0)
+          LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
+        const int nch = atb2_chunks(m, n);
+        LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+               launch_atb2(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, 0, W.part, nch, st));
+        LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+               launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      }
       LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
     }
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
-    // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank)
+    // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank); in the
+    // mixed form it is also the pass that measures ||A||^2 on the first step
+    const bool rr_norm = first && P.mixed;
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, nullptr, nullptr, nullptr, st));
+           launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach, rr_norm ? W.part : nullptr, nullptr,
+                     nullptr, st));
+    if (rr_norm) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
     const int kch = atb_chunks(m, c, c);
     LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
            launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, W.part, kch, st));
@@ -421,9 +445,9 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
         LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
         need_norm = false;
       }
-      const int nch = atb_chunks(m, n, c);
+      const int nch = atb2_chunks(m, n);
       LAUNCH(PF, KC_ATB, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
-             launch_atb(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, W.part, nch, st));
+             launch_atb2(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, 0, W.part, nch, st));
       LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
              launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
@@ -447,9 +471,9 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
              launch_ax(src, 0, W.H, dst, 0, m, c, c, s.layout, ych, nullptr, nullptr, nullptr, st));
     }
     // Bt = A^T U (n x ell), E = Bt^T Bt
-    const int nch = atb_chunks(m, n, c);
+    const int nch = atb2_chunks(m, n);
     LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-           launch_atb(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, W.part, nch, st));
+           launch_atb2(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, 0, W.part, nch, st));
     LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
            launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
     const int ech = atb_chunks(n, c, c);
@@ -591,8 +615,10 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     if (ell < 1) ell = 1;
     if (ell > TT_MAX_ELL) ell = TT_MAX_ELL;
     int r;
+    bool retry = false;
     while (true) {
-      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, W, st, PF);
+      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, W, st, PF, retry);
+      retry = true;
       if (rc) return rc;
       if (P.fixed) { r = std::min(s.r, ell); break; }
       HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));

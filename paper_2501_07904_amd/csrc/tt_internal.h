@@ -58,6 +58,22 @@ int ax_chunks(int64_t m, int n, int c);
 hipError_t launch_ax(const void* A, int a_f32, const double* W, void* Y, int y_f32, int64_t m,
                      int n, int c, int layout, int nchunks, double* sumsqA, double* sumsqY,
                      double* rerr, hipStream_t st);
+// Mixed-precision power-iteration products on FP32-accumulating matrix cores,
+// operands rounded to BF16 (bf16 = 1) or kept FP32 (bf16 = 0).  Y (FP32,
+// layout) = A W; partials[ch] = A^T Y over the rows of chunk ch (stored FP64),
+// atb_lp_chunks(m, n) chunks.
+hipError_t launch_ax_lp(const void* A, int a_f32, const double* W, float* Y, int64_t m, int n, int c, int layout,
+                        int bf16, hipStream_t st);
+int atb_lp_chunks(int64_t m, int n);
+hipError_t launch_atb_lp(const void* A, int a_f32, const float* Y, int64_t m, int n, int c, int layout,
+                         double* partials, int nchunks, int bf16, hipStream_t st);
+// partials[ch] = A^T Y over the rows of chunk ch (n x c column-major, FP64) for
+// any n: 128 columns of A per workgroup, row tiles prefetched into registers;
+// FP64 matrix cores, or FP32 ones (f32_mma, FP32 data only).  atb2_chunks(m, n)
+// chunks (never more than atb_chunks).
+int atb2_chunks(int64_t m, int n);
+hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c, int layout,
+                       int f32_mma, double* partials, int nchunks, hipStream_t st);
 // resid[ch] = sum over chunk rows of (A - Cr V1^T)^2, Cr m x r in `layout`, V1 n x r k-major.
 int resid_chunks(int64_t m);
 hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, const double* V1, int64_t m,

@@ -1,6 +1,8 @@
 // Streaming kernels over the tall side of an unfolding: the passes that read
 // the m x n matrix A from HBM.  All accumulation is FP64; partial sums per row
 // chunk are reduced in a fixed order, so results are bitwise reproducible.
+#include <type_traits>
+
 #include "tt_internal.h"
 
 namespace ttutv {
@@ -426,8 +428,8 @@ __global__ __launch_bounds__(kThreads) void k_ax_kw(const TA* __restrict__ A, co
 // column blocks).  Only the blocks I <= J are multiplied (both operands of a
 // Gram block come from the same registers); the lower blocks are written by
 // symmetry.  The four waves' partial blocks are summed in LDS in wave order.
-template <int NB, int LY>
-__global__ __launch_bounds__(kThreads) void k_gram_narrow(const double* __restrict__ A, int64_t m, int n,
+template <typename TA, int NB, int LY>
+__global__ __launch_bounds__(kThreads) void k_gram_narrow(const TA* __restrict__ A, int64_t m, int n,
                                                           int64_t rows_per_chunk, double* __restrict__ partials) {
   constexpr int NP = NB * (NB + 1) / 2;
   __shared__ double sR[kThreads / 64][NP][16][17];
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_narrow(const double* __restri
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = 16 * b + li;
-        a[b][s4] = (rok && j < n) ? A[LY == ROW ? i * n + j : i + (int64_t)j * m] : 0.0;
+        a[b][s4] = (rok && j < n) ? (double)A[LY == ROW ? i * n + j : i + (int64_t)j * m] : 0.0;
       }
     }
   };
@@ -536,6 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_ax_narrow(const TA* __restrict__ A
     for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s4 = 0; s4 < NK; ++s4) {
+      if (4 * s4 >= n) break;   // k-steps past the last column only add zeros
       ssa = fma(a[s4], a[s4], ssa);
 #pragma unroll
       for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[s4], wr[s4][q], acc[q]);
@@ -579,6 +582,344 @@ __global__ __launch_bounds__(kThreads) void k_ax_narrow(const TA* __restrict__ A
     const double s = block_sum(sse, sh);
     if (t == 0) rerr[blockIdx.x] = s;
   }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 power-iteration products of the mixed-precision form (FP32
+// accumulation on v_mfma_f32_16x16x16_bf16: operand A lane l holds row l%16 at
+// k = 4(l/16) .. 4(l/16)+3, operand B lane l holds column l%16 at the same k,
+// result lane l register v holds row 4(l/16)+v, column l%16).  Inputs are
+// rounded to BF16 (nearest even) as they are loaded.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (short)(u >> 16);   // inf / nan pass through
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f4 mfma_bf16(bf4 a, bf4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Y (m x c, FP32, layout LY) = A W on FP32-accumulating matrix cores with the
+// operands rounded to BF16 (BF) or kept FP32 (v_mfma_f32_16x16x4_f32: operand A
+// lane l holds row l%16 at k = l/16, operand B column l%16 at k = l/16, result
+// as for BF16).  Workgroup = 64-row tile, wave w rows 16w .. 16w+15, k in
+// chunks of 64 with W staged in LDS column-wise.
+// FP32-operand form of ax_accumulate (v_mfma_f32_16x16x4_f32, k-slot g of step
+// u is column 4u + g): W double-buffered in LDS as FP32, the next chunk of A
+// loaded while the current one is multiplied, one barrier per chunk.
+template <typename TA, int NT, int LY>
+__device__ __forceinline__ void ax_accumulate_f32(const TA* __restrict__ A, const double* __restrict__ W,
+                                                  float (*sW)[kAxKC][NT * 16 + 1], int64_t m, int n, int c,
+                                                  int64_t tile, f4* acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t row = tile * 64 + 16 * w + li;
+  const bool rok = row < m;
+  constexpr int NA = kAxKC / 4;
+  constexpr int NWS = (kAxKC * NT * 16 + kThreads - 1) / kThreads;
+  float a[NA], an[NA], wn[NWS];
+  auto load_a = [&](int k0, float* dst) {
+    const TA* p = (LY == ROW) ? A + row * n + k0 + g : A + row + (int64_t)(k0 + g) * m;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const bool ok = rok && k0 + 4 * u + g < n;
+      dst[u] = ok ? (float)p[(LY == ROW) ? (int64_t)4 * u : (int64_t)4 * u * m] : 0.f;
+    }
+  };
+  auto load_w = [&](int k0, float* dst) {
+    const int kc = min(kAxKC, n - k0);
+#pragma unroll
+    for (int u = 0; u < NWS; ++u) {
+      const int e = threadIdx.x + kThreads * u;
+      const int kk = e / (NT * 16), cc = e % (NT * 16);
+      dst[u] = (e < kAxKC * NT * 16 && kk < kc && cc < c) ? (float)W[(int64_t)(k0 + kk) * c + cc] : 0.f;
+    }
+  };
+  auto store_w = [&](const float* src, int buf) {
+#pragma unroll
+    for (int u = 0; u < NWS; ++u) {
+      const int e = threadIdx.x + kThreads * u;
+      if (e < kAxKC * NT * 16) sW[buf][e / (NT * 16)][e % (NT * 16)] = src[u];
+    }
+  };
+  __syncthreads();
+  load_w(0, wn);
+  load_a(0, a);
+  store_w(wn, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < n; k0 += kAxKC) {
+    const int k1 = k0 + kAxKC;
+    const bool more = k1 < n;
+    if (more) {
+      load_w(k1, wn);
+      load_a(k1, an);
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[q] = mfma_f32(a[u], sW[buf][4 * u + g][16 * q + li], acc[q]);
+    if (more) {
+      store_w(wn, buf ^ 1);
+#pragma unroll
+      for (int u = 0; u < NA; ++u) a[u] = an[u];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+template <typename TA, int NT, int LY>
+__global__ __launch_bounds__(kThreads, 2) void k_ax_f32(const TA* __restrict__ A, const double* __restrict__ W,
+                                                        float* __restrict__ Y, int64_t m, int n, int c) {
+  __shared__ float sW[2][kAxKC][NT * 16 + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  for (int64_t tile = blockIdx.x; tile * 64 < m; tile += gridDim.x) {
+    f4 acc[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    ax_accumulate_f32<TA, NT, LY>(A, W, sW, m, n, c, tile, acc);
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t yr = tile * 64 + 16 * w + 4 * g + v;
+        const int col = 16 * q + li;
+        if (yr < m && col < c) Y[at(LY, yr, col, m, c)] = acc[q][v];
+      }
+  }
+}
+
+template <typename TA, int NT, int LY, bool BF>
+__global__ __launch_bounds__(kThreads) void k_ax_lp(const TA* __restrict__ A, const double* __restrict__ W,
+                                                    float* __restrict__ Y, int64_t m, int n, int c) {
+  __shared__ __align__(16) short sWb[BF ? NT * 16 : 1][kAxKC + 4];
+  __shared__ float sWf[BF ? 1 : NT * 16][kAxKC + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  for (int64_t tile = blockIdx.x; tile * 64 < m; tile += gridDim.x) {
+    const int64_t row = tile * 64 + 16 * w + li;
+    const bool rok = row < m;
+    f4 acc[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < n; k0 += kAxKC) {
+      const int kc = min(kAxKC, n - k0);
+      __syncthreads();
+      for (int e = t; e < kAxKC * NT * 16; e += kThreads) {
+        const int kk = e / (NT * 16), cc = e % (NT * 16);
+        const float v = (kk < kc && cc < c) ? (float)W[(int64_t)(k0 + kk) * c + cc] : 0.f;
+        if constexpr (BF) sWb[cc][kk] = bf16_rne(v);
+        else sWf[cc][kk] = v;
+      }
+      __syncthreads();
+      // k of value u of this lane: BF: 16(u/4) + 4g + u%4; FP32: 4u + g
+      float av[kAxKC / 4];
+#pragma unroll
+      for (int u = 0; u < kAxKC / 4; ++u) {
+        const int k = k0 + (BF ? 16 * (u >> 2) + 4 * g + (u & 3) : 4 * u + g);
+        av[u] = (rok && k < n) ? (float)A[LY == ROW ? row * n + k : row + (int64_t)k * m] : 0.f;
+      }
+      if constexpr (BF) {
+#pragma unroll
+        for (int s4 = 0; s4 < kAxKC / 16; ++s4) {
+          bf4 a;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = bf16_rne(av[4 * s4 + i]);
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const bf4 b = *reinterpret_cast<const bf4*>(&sWb[16 * q + li][16 * s4 + 4 * g]);
+            acc[q] = mfma_bf16(a, b, acc[q]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kAxKC / 4; ++u)
+#pragma unroll
+          for (int q = 0; q < NT; ++q) acc[q] = mfma_f32(av[u], sWf[16 * q + li][4 * u + g], acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t yr = tile * 64 + 16 * w + 4 * g + v;
+        const int col = 16 * q + li;
+        if (yr < m && col < c) Y[at(LY, yr, col, m, c)] = acc[q][v];
+      }
+  }
+}
+
+// partials[chunk] = A[rows of chunk, j0:j0+64]^T Y[rows of chunk, :] on
+// FP32-accumulating matrix cores, operands rounded to BF16 (BF) or kept FP32,
+// stored as FP64.  Operands come straight from global memory: lane (g, li) of
+// wave w takes column j0+16w+li of A and column 16q+li of Y at rows i0+4g ..
+// i0+4g+3 (BF16, one MFMA per 16 rows) or at row i0+4s+g of step s (FP32,
+// four MFMAs per 16 rows).
+template <typename TA, int NT, int LY, bool BF>
+__global__ __launch_bounds__(kThreads) void k_atb_lp(const TA* __restrict__ A, const float* __restrict__ Y,
+                                                     int64_t m, int n, int c, int64_t rows_per_chunk,
+                                                     double* __restrict__ partials) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t chunk = blockIdx.x;
+  const int j0 = blockIdx.y * kAtbJT;
+  const int j = j0 + 16 * w + li;
+  const bool jok = j < n;
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = min(m, r0 + rows_per_chunk);
+  f4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+  if (j0 + 16 * w < n) {
+    for (int64_t i0 = r0; i0 < r1; i0 += 16) {
+      float av[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = BF ? i0 + 4 * g + i : i0 + 4 * i + g;
+        av[i] = (jok && r < r1) ? (float)A[LY == ROW ? r * n + j : r + (int64_t)j * m] : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int col = 16 * q + li;
+        float bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t r = BF ? i0 + 4 * g + i : i0 + 4 * i + g;
+          bv[i] = (col < c && r < r1) ? Y[LY == ROW ? r * c + col : r + (int64_t)col * m] : 0.f;
+        }
+        if constexpr (BF) {
+          bf4 a, b;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) { a[i] = bf16_rne(av[i]); b[i] = bf16_rne(bv[i]); }
+          acc[q] = mfma_bf16(a, b, acc[q]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[q] = mfma_f32(av[i], bv[i], acc[q]);
+        }
+      }
+    }
+  }
+  double* out = partials + chunk * (int64_t)n * c;
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int jj = j0 + 16 * w + 4 * g + v, cc = 16 * q + li;
+      if (jj < n && cc < c) out[jj + (int64_t)n * cc] = (double)acc[q][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// partials[chunk] = A[rows of chunk, j0:j0+128]^T Y[rows of chunk, :] on the
+// matrix cores: FP64 (v_mfma_f64_16x16x4, result lane l register v at row
+// l/16 + 4v) or FP32 (v_mfma_f32_16x16x4_f32, row 4(l/16) + v); both take
+// operand A as lane l -> (row l%16, k l/16) and operand B as (k l/16, column
+// l%16), the k-slots running over the rows of the tile.  Eight waves own 16
+// columns of A each, so one staged tile of Y serves 128 columns.  Row tiles
+// (32 rows) of A and Y are loaded with coalesced reads into registers one
+// tile ahead (the loads of tile t+1 are in flight while tile t is
+// multiplied), then stored to LDS behind a barrier.
+constexpr int kAtb2Threads = 512;
+constexpr int kAtb2JB = 128;
+constexpr int kAtb2TR = 32;
+
+template <typename TA, typename TY, int NT, int LY, bool F32>
+__global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A, const TY* __restrict__ Y, int64_t m,
+                                                       int n, int c, int64_t rows_per_chunk,
+                                                       double* __restrict__ partials) {
+  typedef typename std::conditional<F32, float, double>::type T;
+  typedef typename std::conditional<F32, f4, d4>::type V4;
+  constexpr int NTH = kAtb2Threads;
+  constexpr int WY = NT * 16;
+  constexpr int LA = kAtb2TR * kAtb2JB / NTH;   // A values per thread per tile
+  constexpr int LYV = (kAtb2TR * WY + NTH - 1) / NTH;
+  __shared__ T sA[kAtb2TR][kAtb2JB + 1];
+  __shared__ T sY[kAtb2TR][WY + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t chunk = blockIdx.x;
+  const int j0 = blockIdx.y * kAtb2JB;
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = min(m, r0 + rows_per_chunk);
+  // element e of a tile: COL -> (row e % TR, col e / TR); ROW -> (row e / W, col e % W)
+  T ra[LA], ry[LYV];
+  auto load = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = t + NTH * u;
+      int i, j;
+      if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+      const int64_t r = rb + i;
+      ra[u] = (r < r1 && j0 + j < n) ? (T)A[at(LY, r, j0 + j, m, n)] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < LYV; ++u) {
+      const int e = t + NTH * u;
+      int i, j;
+      if (LY == ROW) { i = e / WY; j = e % WY; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+      const int64_t r = rb + i;
+      ry[u] = (e < kAtb2TR * WY && r < r1 && j < c) ? (T)Y[at(LY, r, j, m, c)] : (T)0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = t + NTH * u;
+      int i, j;
+      if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+      sA[i][j] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LYV; ++u) {
+      const int e = t + NTH * u;
+      if (e >= kAtb2TR * WY) break;
+      int i, j;
+      if (LY == ROW) { i = e / WY; j = e % WY; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+      sY[i][j] = ry[u];
+    }
+  };
+  V4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = V4{0, 0, 0, 0};
+  const bool active = j0 + 16 * w < n;
+  if (r0 < r1) load(r0);
+  for (int64_t rb = r0; rb < r1; rb += kAtb2TR) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (rb + kAtb2TR < r1) load(rb + kAtb2TR);
+    if (active) {
+#pragma unroll
+      for (int ks = 0; ks < kAtb2TR / 4; ++ks) {
+        const int i = 4 * ks + g;
+        const T a = sA[i][16 * w + li];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          if constexpr (F32) acc[q] = mfma_f32(a, sY[i][16 * q + li], acc[q]);
+          else acc[q] = mfma_f64(a, sY[i][16 * q + li], acc[q]);
+        }
+      }
+    }
+  }
+  double* out = partials + chunk * (int64_t)n * c;
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int jj = j0 + 16 * w + (F32 ? 4 * g + v : g + 4 * v), cc = 16 * q + li;
+      if (jj < n && cc < c) out[jj + (int64_t)n * cc] = (double)acc[q][v];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,6 +1022,22 @@ int atb_chunks(int64_t m, int n, int c) {
   return (int)(tiles < want ? tiles : want);
 }
 
+template <typename TA>
+static hipError_t launch_gram_narrow(const TA* A, int64_t m, int n, int layout, int64_t rpc, double* partials,
+                                     int nchunks, hipStream_t st) {
+  const int nb = (n + 15) / 16;
+#define TT_GRN(NBV)                                                                                          \
+  do {                                                                                                       \
+    if (layout == ROW)                                                                                       \
+      TT_LAUNCH((k_gram_narrow<TA, NBV, ROW>), dim3(nchunks), dim3(kThreads), 0, st, A, m, n, rpc, partials); \
+    else                                                                                                     \
+      TT_LAUNCH((k_gram_narrow<TA, NBV, COL>), dim3(nchunks), dim3(kThreads), 0, st, A, m, n, rpc, partials); \
+  } while (0)
+  if (nb == 1) TT_GRN(1); else if (nb == 2) TT_GRN(2); else if (nb == 3) TT_GRN(3); else TT_GRN(4);
+#undef TT_GRN
+  return hipGetLastError();
+}
+
 hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c,
                       int layout, double* partials, int nchunks, hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
@@ -690,21 +1047,7 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
     // FP64 operands: matrix-core kernel (Gram: Y == A with c == n <= 64)
     const bool gram = (A == Y);
     if (gram && (c != n || n > kAtbJT)) return hipErrorInvalidValue;
-    if (gram) {
-      const int nb = (n + 15) / 16;
-#define TT_GRN(NBV)                                                                                        \
-  do {                                                                                                     \
-    if (layout == ROW)                                                                                     \
-      TT_LAUNCH((k_gram_narrow<NBV, ROW>), dim3(nchunks), dim3(kThreads), 0, st, (const double*)A, m, n, rpc, \
-                partials);                                                                                 \
-    else                                                                                                   \
-      TT_LAUNCH((k_gram_narrow<NBV, COL>), dim3(nchunks), dim3(kThreads), 0, st, (const double*)A, m, n, rpc, \
-                partials);                                                                                 \
-  } while (0)
-      if (nb == 1) TT_GRN(1); else if (nb == 2) TT_GRN(2); else if (nb == 3) TT_GRN(3); else TT_GRN(4);
-#undef TT_GRN
-      return hipGetLastError();
-    }
+    if (gram) return launch_gram_narrow<double>((const double*)A, m, n, layout, rpc, partials, nchunks, st);
     if (c <= 16)
       TT_LAUNCH((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
@@ -718,6 +1061,8 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
       TT_LAUNCH((k_atb_mfma<4>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
   }
+  else if (a_f32 && y_f32 && A == Y && c == n && n <= kAtbJT)
+    return launch_gram_narrow<float>((const float*)A, m, n, layout, rpc, partials, nchunks, st);
   else if (a_f32 && y_f32)
     TT_LAUNCH((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
                        (const float*)Y, m, n, c, layout, rpc, partials);
@@ -840,6 +1185,120 @@ hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, doub
   const int64_t blocks = (size + 15) / 16;
   TT_LAUNCH(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
                      size, out, out2);
+  return hipGetLastError();
+}
+
+}  // namespace ttutv
+
+namespace ttutv {
+
+hipError_t launch_ax_lp(const void* A, int a_f32, const double* W, float* Y, int64_t m, int n, int c, int layout,
+                        int bf16, hipStream_t st) {
+  if (n < 1 || c < 1 || c > kCMax || m < 1) return hipErrorInvalidValue;
+  const int64_t tiles = (m + 63) / 64;
+  dim3 grid((unsigned)(tiles < 8192 ? tiles : 8192)), block(kThreads);
+#define TT_AXL(TAV, NTV, BFV)                                                                             \
+  do {                                                                                                    \
+    if (layout == ROW)                                                                                    \
+      TT_LAUNCH((k_ax_lp<TAV, NTV, ROW, BFV>), grid, block, 0, st, (const TAV*)A, W, Y, m, n, c);         \
+    else                                                                                                  \
+      TT_LAUNCH((k_ax_lp<TAV, NTV, COL, BFV>), grid, block, 0, st, (const TAV*)A, W, Y, m, n, c);         \
+  } while (0)
+#define TT_AXL_NT(TAV, BFV)                                                                               \
+  do {                                                                                                    \
+    const int nt = (c + 15) / 16;                                                                         \
+    if (nt == 1) TT_AXL(TAV, 1, BFV); else if (nt == 2) TT_AXL(TAV, 2, BFV);                              \
+    else if (nt == 3) TT_AXL(TAV, 3, BFV); else TT_AXL(TAV, 4, BFV);                                      \
+  } while (0)
+#define TT_AXF(TAV, NTV)                                                                                  \
+  do {                                                                                                    \
+    if (layout == ROW)                                                                                    \
+      TT_LAUNCH((k_ax_f32<TAV, NTV, ROW>), grid, block, 0, st, (const TAV*)A, W, Y, m, n, c);             \
+    else                                                                                                  \
+      TT_LAUNCH((k_ax_f32<TAV, NTV, COL>), grid, block, 0, st, (const TAV*)A, W, Y, m, n, c);             \
+  } while (0)
+#define TT_AXF_NT(TAV)                                                                                    \
+  do {                                                                                                    \
+    const int nt = (c + 15) / 16;                                                                         \
+    if (nt == 1) TT_AXF(TAV, 1); else if (nt == 2) TT_AXF(TAV, 2);                                        \
+    else if (nt == 3) TT_AXF(TAV, 3); else TT_AXF(TAV, 4);                                                \
+  } while (0)
+  if (a_f32) { if (bf16) TT_AXL_NT(float, true); else TT_AXF_NT(float); }
+  else { if (bf16) TT_AXL_NT(double, true); else TT_AXF_NT(double); }
+#undef TT_AXF_NT
+#undef TT_AXF
+#undef TT_AXL_NT
+#undef TT_AXL
+  return hipGetLastError();
+}
+
+int atb_lp_chunks(int64_t m, int n) {
+  return atb_chunks(m, n, 0);   // the same number of partials as the FP64 kernel (workspace bound)
+}
+
+hipError_t launch_atb_lp(const void* A, int a_f32, const float* Y, int64_t m, int n, int c, int layout,
+                         double* partials, int nchunks, int bf16, hipStream_t st) {
+  if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
+  int64_t rpc = (m + nchunks - 1) / nchunks;
+  rpc = (rpc + 15) / 16 * 16;
+  dim3 grid(nchunks, (n + kAtbJT - 1) / kAtbJT), block(kThreads);
+#define TT_ATBL(TAV, NTV, BFV)                                                                               \
+  do {                                                                                                       \
+    if (layout == ROW)                                                                                       \
+      TT_LAUNCH((k_atb_lp<TAV, NTV, ROW, BFV>), grid, block, 0, st, (const TAV*)A, Y, m, n, c, rpc, partials); \
+    else                                                                                                     \
+      TT_LAUNCH((k_atb_lp<TAV, NTV, COL, BFV>), grid, block, 0, st, (const TAV*)A, Y, m, n, c, rpc, partials); \
+  } while (0)
+#define TT_ATBL_NT(TAV, BFV)                                                                                 \
+  do {                                                                                                       \
+    const int nt = (c + 15) / 16;                                                                            \
+    if (nt == 1) TT_ATBL(TAV, 1, BFV); else if (nt == 2) TT_ATBL(TAV, 2, BFV);                               \
+    else if (nt == 3) TT_ATBL(TAV, 3, BFV); else TT_ATBL(TAV, 4, BFV);                                       \
+  } while (0)
+  if (a_f32) { if (bf16) TT_ATBL_NT(float, true); else TT_ATBL_NT(float, false); }
+  else { if (bf16) TT_ATBL_NT(double, true); else TT_ATBL_NT(double, false); }
+#undef TT_ATBL_NT
+#undef TT_ATBL
+  return hipGetLastError();
+}
+
+}  // namespace ttutv
+
+namespace ttutv {
+
+int atb2_chunks(int64_t m, int n) {
+  return atb_chunks(m, n, 0);   // no more partials than the 64-column kernel (workspace bound)
+}
+
+hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c, int layout,
+                       int f32_mma, double* partials, int nchunks, hipStream_t st) {
+  if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
+  const int64_t rpc = (m + nchunks - 1) / nchunks;
+  dim3 grid(nchunks, (n + kAtb2JB - 1) / kAtb2JB), block(kAtb2Threads);
+#define TT_A2(TAV, TYV, NTV, F32V)                                                                           \
+  do {                                                                                                       \
+    if (layout == ROW)                                                                                       \
+      TT_LAUNCH((k_atb2<TAV, TYV, NTV, ROW, F32V>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, n, c, \
+                rpc, partials);                                                                              \
+    else                                                                                                     \
+      TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, n, c, \
+                rpc, partials);                                                                              \
+  } while (0)
+#define TT_A2_NT(TAV, TYV, F32V)                                                                              \
+  do {                                                                                                       \
+    const int nt = (c + 15) / 16;                                                                            \
+    if (nt == 1) TT_A2(TAV, TYV, 1, F32V); else if (nt == 2) TT_A2(TAV, TYV, 2, F32V);                       \
+    else if (nt == 3) TT_A2(TAV, TYV, 3, F32V); else TT_A2(TAV, TYV, 4, F32V);                               \
+  } while (0)
+  if (f32_mma) {
+    if (!a_f32 || !y_f32) return hipErrorInvalidValue;   // FP32 products only on FP32 data
+    TT_A2_NT(float, float, true);
+  } else if (!a_f32 && !y_f32) TT_A2_NT(double, double, false);
+  else if (a_f32 && y_f32) TT_A2_NT(float, float, false);
+  else if (a_f32) TT_A2_NT(float, double, false);
+  else TT_A2_NT(double, float, false);
+#undef TT_A2_NT
+#undef TT_A2
   return hipGetLastError();
 }
 

@@ -249,3 +249,62 @@ def test_table_beps_ttsvd_ranks():
         want = [1] + [int(x) for x in row[1:]] + [1]
         _, rep = oracle.tt_svd(a, [160] * 4, eps=eps, sweep="L2R")
         assert rep["ranks"] == want, (eps, rep["ranks"])
+
+
+# --------------------------------------------------------------------- masked completion
+def test_completion_direction_is_the_directional_derivative():
+    """J g (sum over k of the train with core k replaced by g_k) is the exact
+    first-order term of A(G + h g): central differences agree to O(h^2)."""
+    dims = [3, 4, 2, 5]
+    cores = ttgen.gaussian_cores(dims, [1, 2, 3, 2, 1], 31)
+    rng = np.random.default_rng(32)
+    idx = np.stack([rng.integers(0, n, 40) for n in dims], axis=1)
+    vals = rng.standard_normal(40)
+    e = oracle.tt_sample(cores, idx) - vals
+    g = oracle.tt_sample_grad(cores, idx, e)
+    jg = sum(oracle.tt_sample(cores[:k] + [g[k]] + cores[k + 1:], idx) for k in range(len(cores)))
+    h = 1e-5
+    plus = oracle.tt_sample([c + h * gk for c, gk in zip(cores, g)], idx)
+    minus = oracle.tt_sample([c - h * gk for c, gk in zip(cores, g)], idx)
+    fd = (plus - minus) / (2 * h)
+    np.testing.assert_allclose(jg, fd, rtol=1e-6, atol=1e-6 * np.max(np.abs(jg)))
+
+
+def test_completion_step_size_minimises_the_linearised_residual():
+    dims = [4, 3, 5]
+    cores = ttgen.gaussian_cores(dims, [1, 2, 2, 1], 33)
+    rng = np.random.default_rng(34)
+    idx = np.stack([rng.integers(0, n, 30) for n in dims], axis=1)
+    vals = rng.standard_normal(30)
+    new, f, alpha = oracle.completion_step(cores, idx, vals)
+    e = oracle.tt_sample(cores, idx) - vals
+    assert f == pytest.approx(0.5 * float(e @ e), rel=1e-14)
+    g = oracle.tt_sample_grad(cores, idx, e)
+    jg = sum(oracle.tt_sample(cores[:k] + [g[k]] + cores[k + 1:], idx) for k in range(len(cores)))
+    lin = lambda a: float(np.sum((e - a * jg) ** 2))
+    assert lin(alpha) <= lin(alpha * 1.01) and lin(alpha) <= lin(alpha * 0.99)
+    # the step is along -g with that size
+    for c, n, gk in zip(cores, new, g):
+        np.testing.assert_allclose(n, c - alpha * gk, rtol=1e-15, atol=1e-15)
+
+
+def test_completion_descends_on_a_low_rank_tensor():
+    """Observed entries of an exact TT of ranks (1,2,2,1): steps from a nearby
+    start decrease f and bring the unobserved entries closer."""
+    dims = [6, 5, 7]
+    true = ttgen.gaussian_cores(dims, [1, 2, 2, 1], 35)
+    full = oracle.tt_reconstruct(true)
+    rng = np.random.default_rng(36)
+    flat = rng.permutation(full.size)[: full.size // 2]
+    idx = np.stack(np.unravel_index(flat, dims, order="F"), axis=1)
+    cores = [c + 0.05 * rng.standard_normal(c.shape) for c in true]
+    fs = []
+    for _ in range(20):
+        cores, f, _ = oracle.completion_step(cores, idx, full[flat])
+        fs.append(f)
+    assert fs[-1] < 0.1 * fs[0]
+    rest = np.setdiff1d(np.arange(full.size), flat)
+    err0 = np.linalg.norm(oracle.tt_reconstruct([c for c in true])[rest] - full[rest])
+    assert err0 == 0.0
+    err = np.linalg.norm(oracle.tt_reconstruct(cores)[rest] - full[rest]) / np.linalg.norm(full[rest])
+    assert err < 0.05

@@ -15,6 +15,9 @@ available):
   sin_norm_tensor     -- Example 2: sin(sqrt(sum_k ((i_k-1)/(I-1))^2)).
   mri_like_volume     -- sum of random 3-D Gaussian ellipsoids plus Rician
                          noise (stand-in for the MRI volume).
+  gaussian_tt_tensor_device -- the Example 1 recipe built on the GPU with
+                         PyTorch (tensors of many GB: 40^6 FP32), split as
+                         (left half-train) x (right half-train) + noise.
 """
 import numpy as np
 
@@ -104,3 +107,40 @@ def mri_like_volume(shape=(256, 256, 160), n_ell=12, sigma=0.02, seed=0):
     n2 = rng.standard_normal(shape).astype(np.float32)
     vol = np.sqrt((vol + sigma * n1) ** 2 + (sigma * n2) ** 2)
     return vol.reshape(-1, order="F").astype(np.float32)
+
+
+def gaussian_tt_tensor_device(dims, ranks, noise_rel, seed, dtype="float32", device="cuda"):
+    """The gaussian_tt_tensor recipe built with PyTorch on `device` (for tensors
+    of many GB, e.g. 40^6 in FP32): the same seeded Gaussian cores, contracted
+    as P = L R with L the left half-train over modes 1..h (rows, i_1 fastest)
+    and R the right half-train over modes h+1..d (columns, i_{h+1} fastest);
+    N i.i.d. N(0,1) from a seeded generator on `device`; beta = noise_rel *
+    ||P||_F / ||N||_F.  Returns the flat tensor (i_1 fastest) in `dtype`."""
+    import torch
+
+    dims = [int(x) for x in dims]
+    d = len(dims)
+    ranks = list(ranks)
+    if len(ranks) == d - 1:
+        ranks = [1] + ranks + [1]
+    cores = [torch.from_numpy(c).to(device) for c in gaussian_cores(dims, ranks, seed)]
+    h = max(1, d // 2)
+    L = cores[0][0]                                               # (I_1, r_1)
+    for g in cores[1:h]:
+        # rows (i_prev, i_k) with i_prev fastest
+        L = torch.einsum("pa,aib->ipb", L, g).reshape(-1, g.shape[2])
+    R = cores[d - 1][:, :, 0]                                      # (r_{d-1}, I_d)
+    for g in cores[h:d - 1][::-1]:
+        # columns (i_k, rest) with i_k fastest
+        R = torch.einsum("aib,br->ari", g, R).reshape(g.shape[0], -1)
+    dt = getattr(torch, dtype)
+    P = (R.transpose(0, 1).to(dt) @ L.transpose(0, 1).to(dt)).reshape(-1)   # flat index row_L + |L| col_R
+    if noise_rel > 0:
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed + 7919)
+        N = torch.randn(P.numel(), generator=gen, dtype=dt, device=device)
+        beta = noise_rel * float(torch.linalg.vector_norm(P, dtype=torch.float64)) / \
+            float(torch.linalg.vector_norm(N, dtype=torch.float64))
+        P.add_(N, alpha=beta)
+        del N
+    return P
