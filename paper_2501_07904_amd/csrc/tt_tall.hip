@@ -18,6 +18,11 @@ __device__ __forceinline__ int64_t at(int layout, int64_t i, int64_t j, int64_t 
 template <typename T>
 __device__ __forceinline__ double ldv(const T* p, int64_t i) { return (double)p[i]; }
 
+__device__ __forceinline__ double group_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int w = threadIdx.x >> 6;
@@ -332,70 +337,70 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax(const TA* __restrict__ A, co
   }
 }
 
-// Short A (few row tiles): workgroup b owns rows 16b .. 16b+15 and its four
-// waves split the k range (wave w takes chunks w, w+4, ...); the four partial
-// 16 x 16*NT blocks are summed through LDS in wave order, so the result is
-// independent of timing.  W chunks are staged per wave (no block barrier in
-// the k loop).
+// Short A (few row tiles): workgroup b owns rows 16b .. 16b+15; its 16 waves
+// split the k range in slices of 32 columns (wave w takes slices w, w+16, ...).
+// A wave issues all loads of a slice at once -- its 8 values of A and the
+// matching 8*NT values of W, read straight from L2 into the MFMA operand
+// registers -- then multiplies; the 16 partial 16 x 16*NT blocks are summed in
+// LDS in wave order, so the result is independent of timing.
+constexpr int kAxKwSlice = 32;
+// 16 waves, or 8 when the wider W operand (NT >= 3) needs more registers per lane
+__host__ __device__ constexpr int ax_kw_threads(int nt) { return nt <= 2 ? 1024 : 512; }
+
 template <typename TA, typename TY, int NT, int LY>
-__global__ __launch_bounds__(kThreads) void k_ax_kw(const TA* __restrict__ A, const double* __restrict__ W,
-                                                    TY* __restrict__ Y, int64_t m, int n, int c,
-                                                    double* __restrict__ sumsqA, double* __restrict__ sumsqY,
-                                                    double* __restrict__ rerr) {
-  __shared__ double sW[kThreads / 64][kAxKC][NT * 16 + 1];
-  __shared__ double sh[8];
-  // after its k loop, wave w reuses its own W stage for its partial block
-  auto sR = [&](int q, int rr, int col) -> double& { return sW[q][rr][col]; };
+__global__ __launch_bounds__(ax_kw_threads(NT)) void k_ax_kw(const TA* __restrict__ A, const double* __restrict__ W,
+                                                        TY* __restrict__ Y, int64_t m, int n, int c,
+                                                        double* __restrict__ sumsqA, double* __restrict__ sumsqY,
+                                                        double* __restrict__ rerr) {
+  constexpr int NTH = ax_kw_threads(NT);
+  constexpr int NW = NTH / 64;
+  __shared__ double sR[NW][16][NT * 16 + 1];
+  __shared__ double sh[NW];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row = (int64_t)blockIdx.x * 16 + li;
   const bool rok = row < m;
-  const int kchunks = (n + kAxKC - 1) / kAxKC;
+  const int nslices = (n + kAxKwSlice - 1) / kAxKwSlice;
   double ssa = 0.0;
   d4 acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int kc = w; kc < kchunks; kc += kThreads / 64) {
-    const int k0 = kc * kAxKC;
-    const int kl = min(kAxKC, n - k0);
-    for (int e = lane; e < kAxKC * NT * 16; e += 64) {
-      const int kk = e / (NT * 16), cc = e % (NT * 16);
-      sW[w][kk][cc] = (kk < kl && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+  for (int sl = w; sl < nslices; sl += NW) {
+    const int kb = sl * kAxKwSlice + 8 * g;   // k of this lane's k-slot at step s8: kb + s8
+    double a[8], b[8][NT];
+    const TA* p = (LY == ROW) ? A + row * n + kb : A + row + (int64_t)kb * m;
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+      const int k = kb + s8;
+      a[s8] = (rok && k < n) ? (double)p[(LY == ROW) ? (int64_t)s8 : (int64_t)s8 * m] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int col = 16 * q + li;
+        b[s8][q] = (k < n && col < c) ? W[(int64_t)k * c + col] : 0.0;
+      }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double a[kAxKC / 4];
-    ax_load_chunk<TA, LY>(A, m, n, row, rok, k0, n, a);
 #pragma unroll
-    for (int u = 0; u < kAxKC / 4; ++u) ssa = fma(a[u], a[u], ssa);
+    for (int s8 = 0; s8 < 8; ++s8) {
+      ssa = fma(a[s8], a[s8], ssa);
 #pragma unroll
-    for (int ss = 0; ss < kAxKC / 32; ++ss) {
-      const int kb = 32 * ss + 8 * g;
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-        for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[ss * 8 + s8], sW[w][kb + s8][16 * q + li], acc[q]);
+      for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[s8], b[s8][q], acc[q]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 #pragma unroll
   for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sR(w, g + 4 * v, 16 * q + li) = acc[q][v];
+    for (int v = 0; v < 4; ++v) sR[w][g + 4 * v][16 * q + li] = acc[q][v];
   __syncthreads();
   double ssy = 0.0, sse = 0.0;
-  for (int e = t; e < 16 * c; e += kThreads) {
+  for (int e = t; e < 16 * c; e += NTH) {
     int rr, col;
     if (LY == ROW) { rr = e / c; col = e % c; } else { rr = e % 16; col = e / 16; }
     const int64_t yr = (int64_t)blockIdx.x * 16 + rr;
     if (yr >= m) continue;
     double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < kThreads / 64; ++q) sum += sR(q, rr, col);
+    for (int q = 0; q < NW; ++q) sum += sR[q][rr][col];
     const TY y = (TY)sum;
     const double yd = (double)y;
     ssy = fma(yd, yd, ssy);
@@ -403,17 +408,27 @@ __global__ __launch_bounds__(kThreads) void k_ax_kw(const TA* __restrict__ A, co
     sse = fma(er, er, sse);
     Y[at(LY, yr, col, m, c)] = y;
   }
+  // block sums (fixed order over the waves)
+  auto bsum = [&](double v) {
+    v = group_sum64(v);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s2 = 0.0;
+    for (int q = 0; q < NW; ++q) s2 += sh[q];
+    return s2;
+  };
   if (sumsqA) {
-    const double s = block_sum(ssa, sh);
-    if (t == 0) sumsqA[blockIdx.x] = s;
+    const double s2 = bsum(ssa);
+    if (t == 0) sumsqA[blockIdx.x] = s2;
   }
   if (sumsqY) {
-    const double s = block_sum(ssy, sh);
-    if (t == 0) sumsqY[blockIdx.x] = s;
+    const double s2 = bsum(ssy);
+    if (t == 0) sumsqY[blockIdx.x] = s2;
   }
   if (rerr) {
-    const double s = block_sum(sse, sh);
-    if (t == 0) rerr[blockIdx.x] = s;
+    const double s2 = bsum(sse);
+    if (t == 0) rerr[blockIdx.x] = s2;
   }
 }
 
@@ -1113,13 +1128,13 @@ static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n,
   }
   if (ax_short(m, n)) {
     if (c <= 16)
-      TT_LAUNCH((k_ax_kw<TA, TY, 1, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 1, LY>), grid, dim3(ax_kw_threads(1)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else if (c <= 32)
-      TT_LAUNCH((k_ax_kw<TA, TY, 2, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 2, LY>), grid, dim3(ax_kw_threads(2)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else if (c <= 48)
-      TT_LAUNCH((k_ax_kw<TA, TY, 3, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 3, LY>), grid, dim3(ax_kw_threads(3)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else
-      TT_LAUNCH((k_ax_kw<TA, TY, 4, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+      TT_LAUNCH((k_ax_kw<TA, TY, 4, LY>), grid, dim3(ax_kw_threads(4)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     return;
   }
   if (c <= 16)
