@@ -527,13 +527,28 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
   double* Kc = K;
   double* Kn = K2;
   int sweeps = 0;
+  static_assert(NT >= (kCMax / 2) * (kCMax / 2), "one 2 x 2 block per thread");
+  const bool blk = t < h * h;            // this thread's block (P, Q), fixed for the whole solve
+  const int P = blk ? t % h : 0, Q = blk ? t / h : 0;
   for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
-    sweeps = sweep + 1;
+    // converged when no pair would be rotated: exactly the sweep that would
+    // follow applies no rotation, so it is not run
     if (t == 0) *flag = 0;
     __syncthreads();
+    for (int e = t; e < L * L; e += NT) {
+      const int i = e % L, j = e / L;
+      if (i < j) {
+        const double apq = Kc[i + j * kLd];
+        if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(Kc[i + i * kLd] * Kc[j + j * kLd])) *flag = 1;
+      }
+    }
+    __syncthreads();
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+    sweeps = sweep + 1;
     for (int round = 0; round < Le - 1; ++round) {
-      for (int e = t; e < h * h; e += NT) {
-        const int P = e % h, Q = e / h;
+      if (blk) {
         int aP, bP, aQ, bQ;
         rr_pair(P, round, Le, &aP, &bP);
         rr_pair(Q, round, Le, &aQ, &bQ);
@@ -558,14 +573,11 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
         Z[aP + bQ * kLd] = sQ * zaa + cQ * zab;
         Z[bP + aQ * kLd] = cQ * zba - sQ * zbb;
         Z[bP + bQ * kLd] = sQ * zba + cQ * zbb;
-        if (rot && P == Q) *flag = 1;   // pair P rotated (evaluated once per pair here)
+        (void)rot;
       }
       __syncthreads();
       double* tmp = Kc; Kc = Kn; Kn = tmp;
     }
-    const int any = *flag;
-    __syncthreads();
-    if (!any) break;
   }
   // descending order, ties by index
   if (t < L) {
