@@ -63,7 +63,10 @@ typedef struct {
   uint64_t seed;            /* seed of the Gaussian test matrices */
   int32_t max_rank;         /* eps mode: rank cap per step (0 = TT_MAX_ELL) */
   int32_t exact_delta;      /* 1: measure every step error ||C - C_r||_F by an extra
-                               pass over C; 0: from ||C||^2 - ||carry||^2 */
+                               pass over C; 0: from ||C||^2 - ||carry||^2, an estimate
+                               that loses digits by cancellation when a step error is
+                               below ~1e-7 ||C|| (err_bound is then an estimate too;
+                               with 1 it is a bound) */
   const double* weights;    /* host, d-1 entries with sum w_k^2 = 1, or NULL for the
                                default (1/sqrt(d-1); 1/(d-1) for Alg. 4) */
   int32_t profile;          /* bit mask of kernel classes (bit c = class c,
