@@ -22,6 +22,10 @@ if ROOT not in sys.path:
 
 METRIC = "TT-URV GB/s swept + roofline %, mixed vs FP64 GPU at 1e-6 rel. error"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of a kernel class, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
+# workload scaled by the copy-probe factors (profiles/c2_order5_32_fp64_tturv_r2l.md); set to None
+# whenever the class's kernels change after the counters were taken
+MEASURED_TRAFFIC = {"tall_atb": 75.23e6}
 FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
@@ -245,6 +249,7 @@ def main():
         achieved = flops_per / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof["traffic"] = MEASURED_TRAFFIC.get(dom_name) if W is WORKLOADS["order5_32_fp64"] else None
     roof["kernel"] = dom_name
     roof["launches_per_step"] = kstat["launches"] / args.steps
     roof["avg_launch_ms"] = round(avg_ms, 5)
