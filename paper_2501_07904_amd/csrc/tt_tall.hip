@@ -443,10 +443,17 @@ __global__ __launch_bounds__(ax_kw_threads(NT)) void k_ax_kw(const TA* __restric
 // column blocks).  Only the blocks I <= J are multiplied (both operands of a
 // Gram block come from the same registers); the lower blocks are written by
 // symmetry.  The four waves' partial blocks are summed in LDS in wave order.
-template <typename TA, int NB, int LY>
+// Each lane takes a run of RPL consecutive rows (RPL = 32 bytes of each
+// column: 8 FP32 or 4 FP64 values) as vector loads when the storage is
+// column-major and aligned (VEC), so that one load instruction covers 4 x 32
+// contiguous bytes of 16 columns; MFMA step s then uses row RPL g + s for
+// k-slot g, and a wave advances 4 RPL rows per iteration.
+template <typename TA, int NB, int LY, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_gram_narrow(const TA* __restrict__ A, int64_t m, int n,
                                                           int64_t rows_per_chunk, double* __restrict__ partials) {
   constexpr int NP = NB * (NB + 1) / 2;
+  constexpr int RPL = 32 / (int)sizeof(TA);
+  constexpr int RW = 4 * RPL;   // rows per wave iteration
   __shared__ double sR[kThreads / 64][NP][16][17];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -455,36 +462,53 @@ __global__ __launch_bounds__(kThreads) void k_gram_narrow(const TA* __restrict__
   d4 acc[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  auto load = [&](int64_t i0, double (*a)[4]) {
+  typedef TA vec_t __attribute__((ext_vector_type(4)));
+  auto load = [&](int64_t i0, TA (*a)[RPL]) {
+    const int64_t ib = i0 + RPL * g;   // first row of this lane's run
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int64_t i = i0 + 4 * s4 + g;
-      const bool rok = i < r1;
+    for (int b = 0; b < NB; ++b) {
+      const int j = 16 * b + li;
+      const bool jok = j < n;
+      if (VEC && LY == COL) {
+        const TA* p = A + ib + (int64_t)j * m;
+        if (jok && ib + RPL <= r1) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + li;
-        a[b][s4] = (rok && j < n) ? (double)A[LY == ROW ? i * n + j : i + (int64_t)j * m] : 0.0;
+          for (int h = 0; h < RPL / 4; ++h) {
+            const vec_t v = *reinterpret_cast<const vec_t*>(p + 4 * h);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[b][4 * h + e] = v[e];
+          }
+        } else {
+#pragma unroll
+          for (int s4 = 0; s4 < RPL; ++s4) a[b][s4] = (jok && ib + s4 < r1) ? p[s4] : (TA)0;
+        }
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < RPL; ++s4) {
+          const int64_t i = ib + s4;
+          a[b][s4] = (jok && i < r1) ? A[LY == ROW ? i * n + j : i + (int64_t)j * m] : (TA)0;
+        }
       }
     }
   };
-  double a[NB][4], an[NB][4];
-  int64_t i0 = r0 + 16 * w;
+  TA a[NB][RPL], an[NB][RPL];
+  int64_t i0 = r0 + RW * w;
   if (i0 < r1) load(i0, a);
-  for (; i0 < r1; i0 += 16 * (kThreads / 64)) {
-    const int64_t i1 = i0 + 16 * (kThreads / 64);
+  for (; i0 < r1; i0 += RW * (kThreads / 64)) {
+    const int64_t i1 = i0 + RW * (kThreads / 64);
     if (i1 < r1) load(i1, an);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
+    for (int s4 = 0; s4 < RPL; ++s4) {
       int q = 0;
 #pragma unroll
       for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = bi; bj < NB; ++bj, ++q) acc[q] = mfma_f64(a[bi][s4], a[bj][s4], acc[q]);
+        for (int bj = bi; bj < NB; ++bj, ++q) acc[q] = mfma_f64((double)a[bi][s4], (double)a[bj][s4], acc[q]);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) a[b][s4] = an[b][s4];
+      for (int s4 = 0; s4 < RPL; ++s4) a[b][s4] = an[b][s4];
   }
 #pragma unroll
   for (int q = 0; q < NP; ++q)
@@ -937,6 +961,109 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
     }
 }
 
+// Column-major, aligned A (VEC form of the narrow A*W): lane li owns the run of
+// rows 4li .. 4li+3 of a 64-row block and loads it with one vector load per
+// column; row block b of the four MFMA row blocks holds rows 4li + b.  The
+// result goes through a wave-private LDS tile, so Y is written in full lines.
+template <typename TA, typename TY, int NT, int NK>
+__global__ __launch_bounds__(kThreads) void k_ax_narrow_v(const TA* __restrict__ A, const double* __restrict__ W,
+                                                          TY* __restrict__ Y, int64_t m, int n, int c,
+                                                          double* __restrict__ sumsqA, double* __restrict__ sumsqY,
+                                                          double* __restrict__ rerr) {
+  constexpr int RB = 4;
+  __shared__ double sT[kThreads / 64][16 * RB][NT * 16 + 1];
+  __shared__ double sh[8];
+  typedef TA vec_t __attribute__((ext_vector_type(4)));
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  double wr[NK][NT];
+#pragma unroll
+  for (int s4 = 0; s4 < NK; ++s4)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int k = 4 * s4 + g, col = 16 * q + li;
+      wr[s4][q] = (k < n && col < c) ? W[(int64_t)k * c + col] : 0.0;
+    }
+  double ssa = 0.0, ssy = 0.0, sse = 0.0;
+  const int64_t nblk = (m + 16 * RB - 1) / (16 * RB);
+  const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
+  auto load = [&](int64_t b, vec_t* a) {
+    const int64_t row = b * 16 * RB + RB * li;
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      const int k = 4 * s4 + g;
+      if (k < n && row + RB <= m) {
+        a[s4] = *reinterpret_cast<const vec_t*>(A + row + (int64_t)k * m);
+      } else {
+#pragma unroll
+        for (int e = 0; e < RB; ++e) a[s4][e] = (k < n && row + e < m) ? A[row + e + (int64_t)k * m] : (TA)0;
+      }
+    }
+  };
+  vec_t a[NK], an[NK];
+  int64_t b = (int64_t)blockIdx.x * (kThreads / 64) + w;
+  if (b < nblk) load(b, a);
+  for (; b < nblk; b += stride) {
+    if (b + stride < nblk) load(b + stride, an);
+    d4 acc[RB][NT];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[rb][q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) {
+      if (4 * s4 >= n) break;   // k-steps past the last column only add zeros
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const double x = (double)a[s4][rb];
+        ssa = fma(x, x, ssa);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[rb][q] = mfma_f64(x, wr[s4][q], acc[rb][q]);
+      }
+    }
+    // block rb, result row g + 4v is local row RB (g + 4v) + rb
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sT[w][RB * (g + 4 * v) + rb][16 * q + li] = acc[rb][q][v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < 16 * RB * c; e += 64) {
+      const int rr = e % (16 * RB), col = e / (16 * RB);
+      const int64_t yr = b * 16 * RB + rr;
+      if (yr < m) {
+        const double sv = sT[w][rr][col];
+        const TY y = (TY)sv;
+        const double yd = (double)y;
+        ssy = fma(yd, yd, ssy);
+        const double er = sv - yd;
+        sse = fma(er, er, sse);
+        Y[yr + (int64_t)col * m] = y;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) a[s4] = an[s4];
+  }
+  if (sumsqA) {
+    const double s = block_sum(ssa, sh);
+    if (t == 0) sumsqA[blockIdx.x] = s;
+  }
+  if (sumsqY) {
+    const double s = block_sum(ssy, sh);
+    if (t == 0) sumsqY[blockIdx.x] = s;
+  }
+  if (rerr) {
+    const double s = block_sum(sse, sh);
+    if (t == 0) rerr[blockIdx.x] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // resid[chunk] = sum over rows of ||A(i,:) - Cr(i,:) V1^T||^2 (direct step
 // error); V1 (n x r) is stored k-major like the right operand of k_ax.
@@ -1041,14 +1168,21 @@ template <typename TA>
 static hipError_t launch_gram_narrow(const TA* A, int64_t m, int n, int layout, int64_t rpc, double* partials,
                                      int nchunks, hipStream_t st) {
   const int nb = (n + 15) / 16;
-#define TT_GRN(NBV)                                                                                          \
-  do {                                                                                                       \
-    if (layout == ROW)                                                                                       \
-      TT_LAUNCH((k_gram_narrow<TA, NBV, ROW>), dim3(nchunks), dim3(kThreads), 0, st, A, m, n, rpc, partials); \
-    else                                                                                                     \
-      TT_LAUNCH((k_gram_narrow<TA, NBV, COL>), dim3(nchunks), dim3(kThreads), 0, st, A, m, n, rpc, partials); \
+  // vector loads need 16-byte aligned column starts and run starts (rows per chunk a multiple of the run)
+  constexpr int RPL = 32 / (int)sizeof(TA);
+  const bool vec = layout == COL && ((uintptr_t)A % 16) == 0 && (m * (int64_t)sizeof(TA)) % 16 == 0 &&
+                   rpc % RPL == 0;
+#define TT_GRN(NBV, LYV, VECV)                                                                                   \
+  TT_LAUNCH((k_gram_narrow<TA, NBV, LYV, VECV>), dim3(nchunks), dim3(kThreads), 0, st, A, m, n, rpc, partials)
+#define TT_GRN_NB(LYV, VECV)                                                                                     \
+  do {                                                                                                          \
+    if (nb == 1) TT_GRN(1, LYV, VECV); else if (nb == 2) TT_GRN(2, LYV, VECV);                                  \
+    else if (nb == 3) TT_GRN(3, LYV, VECV); else TT_GRN(4, LYV, VECV);                                          \
   } while (0)
-  if (nb == 1) TT_GRN(1); else if (nb == 2) TT_GRN(2); else if (nb == 3) TT_GRN(3); else TT_GRN(4);
+  if (layout == ROW) TT_GRN_NB(ROW, false);
+  else if (vec) TT_GRN_NB(COL, true);
+  else TT_GRN_NB(COL, false);
+#undef TT_GRN_NB
 #undef TT_GRN
   return hipGetLastError();
 }
@@ -1062,7 +1196,8 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
     // FP64 operands: matrix-core kernel (Gram: Y == A with c == n <= 64)
     const bool gram = (A == Y);
     if (gram && (c != n || n > kAtbJT)) return hipErrorInvalidValue;
-    if (gram) return launch_gram_narrow<double>((const double*)A, m, n, layout, rpc, partials, nchunks, st);
+    if (gram)   // row chunks rounded to whole 32-row runs (empty trailing chunks give zero partials)
+      return launch_gram_narrow<double>((const double*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
     if (c <= 16)
       TT_LAUNCH((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
                          layout, rpc, partials);
@@ -1077,7 +1212,7 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
                          layout, rpc, partials);
   }
   else if (a_f32 && y_f32 && A == Y && c == n && n <= kAtbJT)
-    return launch_gram_narrow<float>((const float*)A, m, n, layout, rpc, partials, nchunks, st);
+    return launch_gram_narrow<float>((const float*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
   else if (a_f32 && y_f32)
     TT_LAUNCH((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
                        (const float*)Y, m, n, c, layout, rpc, partials);
@@ -1104,6 +1239,8 @@ constexpr int kNarrowGroups = 2048;   // workgroups of the narrow kernel (grid-s
 
 int ax_chunks(int64_t m, int n, int c) {
   if (ax_narrow(n, c)) {
+    // narrow kernels: 4 waves per group, 16-row blocks (64-row blocks in the vector form; the
+    // same group count keeps the sum-of-squares partials independent of the form)
     const int64_t groups = ((m + 15) / 16 + 3) / 4;
     return (int)(groups < kNarrowGroups ? groups : kNarrowGroups);
   }
@@ -1118,6 +1255,15 @@ static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n,
   dim3 grid(nchunks), block(kThreads);
   if (ax_narrow(n, c)) {
     const int nk = ax_nk(n);
+    const bool vec = LY == COL && ((uintptr_t)A % (4 * sizeof(TA))) == 0 && (m * (int64_t)sizeof(TA)) % (4 * sizeof(TA)) == 0 &&
+                     nk <= 16 && ((c + 15) / 16) <= 2;
+    if (vec) {
+#define TT_AXV(NTV, NKV) TT_LAUNCH((k_ax_narrow_v<TA, TY, NTV, NKV>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
+      if (c <= 16) { if (nk <= 4) TT_AXV(1, 4); else if (nk <= 8) TT_AXV(1, 8); else TT_AXV(1, 16); }
+      else { if (nk <= 4) TT_AXV(2, 4); else if (nk <= 8) TT_AXV(2, 8); else TT_AXV(2, 16); }
+#undef TT_AXV
+      return;
+    }
 #define TT_AXN(NTV, NKV) TT_LAUNCH((k_ax_narrow<TA, TY, NTV, NKV, LY>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
     if (c <= 16) { if (nk <= 4) TT_AXN(1, 4); else if (nk <= 8) TT_AXN(1, 8); else TT_AXN(1, 16); }
     else if (c <= 32) { if (nk <= 4) TT_AXN(2, 4); else if (nk <= 8) TT_AXN(2, 8); else TT_AXN(2, 16); }
