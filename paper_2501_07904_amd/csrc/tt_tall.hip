@@ -961,40 +961,46 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
     }
 }
 
-// Column-major, aligned A (VEC form of the narrow A*W): lane li owns the run of
-// rows 4li .. 4li+3 of a 64-row block and loads it with one vector load per
-// column; row block b of the four MFMA row blocks holds rows 4li + b.  The
-// result goes through a wave-private LDS tile, so Y is written in full lines.
-template <typename TA, typename TY, int NT, int NK>
+// Column-major, aligned A (vector form of the narrow A*W): lane li of a wave
+// owns the run of RB consecutive rows RB*li .. RB*li+RB-1 of a 16*RB-row block
+// and loads it with one vector load per column; MFMA row block rb holds rows
+// RB*li + rb.  W (n x c, at most 64 x 64) sits in LDS for the whole launch, so
+// the waves run their blocks independently (no barrier after the set-up), each
+// prefetching its next block while the current one runs on the matrix cores.
+// Result row rho of block rb is block row RB*rho + rb: a lane holds RB
+// consecutive rows of one column of Y and writes them with one vector store.
+template <typename TA, typename TY, int NT, int NK, int RB>
 __global__ __launch_bounds__(kThreads) void k_ax_narrow_v(const TA* __restrict__ A, const double* __restrict__ W,
                                                           TY* __restrict__ Y, int64_t m, int n, int c,
                                                           double* __restrict__ sumsqA, double* __restrict__ sumsqY,
                                                           double* __restrict__ rerr) {
-  constexpr int RB = 4;
-  __shared__ double sT[kThreads / 64][16 * RB][NT * 16 + 1];
+  __shared__ double sW[4 * NK][NT * 16 + 1];
   __shared__ double sh[8];
-  typedef TA vec_t __attribute__((ext_vector_type(4)));
+  typedef TA vec_t __attribute__((ext_vector_type(RB)));
+  typedef TY yvec_t __attribute__((ext_vector_type(RB)));
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
-  double wr[NK][NT];
-#pragma unroll
-  for (int s4 = 0; s4 < NK; ++s4)
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int k = 4 * s4 + g, col = 16 * q + li;
-      wr[s4][q] = (k < n && col < c) ? W[(int64_t)k * c + col] : 0.0;
-    }
+  for (int e = t; e < 4 * NK * NT * 16; e += kThreads) {
+    const int k = e / (NT * 16), col = e % (NT * 16);
+    sW[k][col] = (k < n && col < c) ? W[(int64_t)k * c + col] : 0.0;
+  }
+  __syncthreads();
   double ssa = 0.0, ssy = 0.0, sse = 0.0;
   const int64_t nblk = (m + 16 * RB - 1) / (16 * RB);
   const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
   auto load = [&](int64_t b, vec_t* a) {
     const int64_t row = b * 16 * RB + RB * li;
+    if (row + RB <= m) {
+      const TA* p = A + row + (int64_t)g * m;
 #pragma unroll
-    for (int s4 = 0; s4 < NK; ++s4) {
-      const int k = 4 * s4 + g;
-      if (k < n && row + RB <= m) {
-        a[s4] = *reinterpret_cast<const vec_t*>(A + row + (int64_t)k * m);
-      } else {
+      for (int s4 = 0; s4 < NK; ++s4) {
+        if (4 * s4 + g < n) a[s4] = *reinterpret_cast<const vec_t*>(p + (int64_t)(4 * s4) * m);
+        else a[s4] = vec_t{};
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < NK; ++s4) {
+        const int k = 4 * s4 + g;
 #pragma unroll
         for (int e = 0; e < RB; ++e) a[s4][e] = (k < n && row + e < m) ? A[row + e + (int64_t)k * m] : (TA)0;
       }
@@ -1013,42 +1019,203 @@ __global__ __launch_bounds__(kThreads) void k_ax_narrow_v(const TA* __restrict__
 #pragma unroll
     for (int s4 = 0; s4 < NK; ++s4) {
       if (4 * s4 >= n) break;   // k-steps past the last column only add zeros
+      double wv[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) wv[q] = sW[4 * s4 + g][16 * q + li];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const double x = (double)a[s4][rb];
         ssa = fma(x, x, ssa);
 #pragma unroll
-        for (int q = 0; q < NT; ++q) acc[rb][q] = mfma_f64(x, wr[s4][q], acc[rb][q]);
+        for (int q = 0; q < NT; ++q) acc[rb][q] = mfma_f64(x, wv[q], acc[rb][q]);
       }
     }
-    // block rb, result row g + 4v is local row RB (g + 4v) + rb
+    // result register v holds MFMA row g + 4v, block row RB (g + 4v) + rb
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int col = 16 * q + li;
+      if (col >= c) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r0 = b * 16 * RB + RB * (g + 4 * v);
+        yvec_t yv;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const double sv = acc[rb][q][v];
+          const TY y = (TY)sv;
+          yv[rb] = y;
+          if (r0 + rb < m) {
+            const double yd = (double)y;
+            ssy = fma(yd, yd, ssy);
+            const double er = sv - yd;
+            sse = fma(er, er, sse);
+          }
+        }
+        if (r0 + RB <= m) {
+          *reinterpret_cast<yvec_t*>(Y + r0 + (int64_t)col * m) = yv;
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (r0 + rb < m) Y[r0 + rb + (int64_t)col * m] = yv[rb];
+        }
+      }
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < NK; ++s4) a[s4] = an[s4];
+  }
+  if (sumsqA) {
+    const double s = block_sum(ssa, sh);
+    if (t == 0) sumsqA[blockIdx.x] = s;
+  }
+  if (sumsqY) {
+    const double s = block_sum(ssy, sh);
+    if (t == 0) sumsqY[blockIdx.x] = s;
+  }
+  if (rerr) {
+    const double s = block_sum(sse, sh);
+    if (t == 0) rerr[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y = A W for column-major, aligned A of any width (vector form of k_ax).
+// Lane li of a wave owns the run of RB consecutive rows RB*li .. RB*li+RB-1
+// of the wave's 16*RB-row block and reads it with one vector load per column,
+// so each load instruction covers 4 columns with 16*RB*sizeof(TA) contiguous
+// bytes each; MFMA row block rb holds rows RB*li + rb.  The four waves own
+// consecutive blocks (a 64*RB-row tile) and share each KC-column chunk of W,
+// staged in LDS (double buffered, the
+// next chunk of A prefetched into registers while the current one runs on
+// the matrix cores).  Result row rho of block rb is tile row RB*rho + rb, so
+// a lane holds RB consecutive rows of one column of Y and writes them with one
+// vector store.  F32M: FP32 matrix cores (v_mfma_f32_16x16x4f32, A and W
+// rounded to FP32, FP32 accumulation); otherwise FP64 matrix cores.
+template <typename TA, typename TY, int NT, bool F32M, int RB, int KC>
+__global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A, const double* __restrict__ W,
+                                                       TY* __restrict__ Y, int64_t m, int n, int c,
+                                                       double* __restrict__ sumsqA, double* __restrict__ sumsqY,
+                                                       double* __restrict__ rerr) {
+  constexpr int TR = 4 * 16 * RB;            // rows per tile
+  constexpr int NS = KC / 4;             // k-steps per chunk
+  constexpr int NWS = (KC * NT * 16 + kThreads - 1) / kThreads;
+  typedef TA vec_t __attribute__((ext_vector_type(RB)));
+  typedef TY yvec_t __attribute__((ext_vector_type(RB)));
+  typedef typename std::conditional<F32M, float, double>::type TM;   // matrix-core operand type
+  typedef typename std::conditional<F32M, f4, d4>::type acc_t;
+  __shared__ TM sW[2][KC][NT * 16 + 1];
+  __shared__ double sh[8];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  double ssa = 0.0, ssy = 0.0, sse = 0.0;
+  const int64_t ntiles = (m + TR - 1) / TR;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * TR + 16 * RB * w + RB * li;   // first of this lane's RB rows
+    const bool full_rows = tile * TR + TR <= m;                // uniform over the workgroup
+    const TA* Al = A + row + (int64_t)g * m;                   // this lane's rows of column 4s + g
+    auto load_a = [&](int k0, vec_t* a) {
+      if (full_rows && k0 + KC <= n) {
+        const TA* p = Al + (int64_t)k0 * m;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = *reinterpret_cast<const vec_t*>(p + (int64_t)(4 * s) * m);
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int k = k0 + 4 * s + g;
+#pragma unroll
+          for (int e = 0; e < RB; ++e) a[s][e] = (k < n && row + e < m) ? A[row + e + (int64_t)k * m] : (TA)0;
+        }
+      }
+    };
+    auto load_w = [&](int k0, TM* dst) {
+#pragma unroll
+      for (int u = 0; u < NWS; ++u) {
+        const int e = t + kThreads * u;
+        const int kk = e / (NT * 16), cc = e % (NT * 16);
+        dst[u] = (e < KC * NT * 16 && k0 + kk < n && cc < c) ? (TM)W[(int64_t)(k0 + kk) * c + cc] : (TM)0;
+      }
+    };
+    auto store_w = [&](const TM* src, int buf) {
+#pragma unroll
+      for (int u = 0; u < NWS; ++u) {
+        const int e = t + kThreads * u;
+        if (e < KC * NT * 16) sW[buf][e / (NT * 16)][e % (NT * 16)] = src[u];
+      }
+    };
+    acc_t acc[RB][NT];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int q = 0; q < NT; ++q)
+      for (int q = 0; q < NT; ++q) acc[rb][q] = acc_t{0, 0, 0, 0};
+    vec_t a[NS], an[NS];
+    TM wn[NWS];
+    __syncthreads();   // the previous tile's reads of sW are done
+    load_w(0, wn);
+    load_a(0, a);
+    store_w(wn, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < n; k0 += KC) {
+      const bool more = k0 + KC < n;
+      if (more) {
+        load_w(k0 + KC, wn);
+        load_a(k0 + KC, an);
+      }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sT[w][RB * (g + 4 * v) + rb][16 * q + li] = acc[rb][q][v];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < 16 * RB * c; e += 64) {
-      const int rr = e % (16 * RB), col = e / (16 * RB);
-      const int64_t yr = b * 16 * RB + rr;
-      if (yr < m) {
-        const double sv = sT[w][rr][col];
-        const TY y = (TY)sv;
-        const double yd = (double)y;
-        ssy = fma(yd, yd, ssy);
-        const double er = sv - yd;
-        sse = fma(er, er, sse);
-        Y[yr + (int64_t)col * m] = y;
+      for (int s = 0; s < NS; ++s) {
+        TM b[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) b[q] = sW[buf][4 * s + g][16 * q + li];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const double xd = (double)a[s][rb];
+          ssa = fma(xd, xd, ssa);
+          const TM x = (TM)a[s][rb];
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            if constexpr (F32M) acc[rb][q] = mfma_f32(x, b[q], acc[rb][q]);
+            else acc[rb][q] = mfma_f64(x, b[q], acc[rb][q]);
+          }
+        }
+      }
+      if (more) {
+        store_w(wn, buf ^ 1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s] = an[s];
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+    // result register v of a lane holds MFMA row rho = g + 4v (FP64) or 4g + v (FP32)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int col = 16 * q + li;
+      if (col >= c) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rho = F32M ? 4 * g + v : g + 4 * v;
+        const int64_t r0 = tile * TR + 16 * RB * w + RB * rho;
+        yvec_t yv;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const double s = (double)acc[rb][q][v];
+          const TY y = (TY)s;
+          yv[rb] = y;
+          if (r0 + rb < m) {
+            const double yd = (double)y;
+            ssy = fma(yd, yd, ssy);
+            const double er = s - yd;
+            sse = fma(er, er, sse);
+          }
+        }
+        if (r0 + RB <= m) {
+          *reinterpret_cast<yvec_t*>(Y + r0 + (int64_t)col * m) = yv;
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (r0 + rb < m) Y[r0 + rb + (int64_t)col * m] = yv[rb];
+        }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int s4 = 0; s4 < NK; ++s4) a[s4] = an[s4];
   }
   if (sumsqA) {
     const double s = block_sum(ssa, sh);
@@ -1239,7 +1406,7 @@ constexpr int kNarrowGroups = 2048;   // workgroups of the narrow kernel (grid-s
 
 int ax_chunks(int64_t m, int n, int c) {
   if (ax_narrow(n, c)) {
-    // narrow kernels: 4 waves per group, 16-row blocks (64-row blocks in the vector form; the
+    // narrow kernels: 4 waves per group, 16-row blocks (16*RB-row blocks in the vector form; the
     // same group count keeps the sum-of-squares partials independent of the form)
     const int64_t groups = ((m + 15) / 16 + 3) / 4;
     return (int)(groups < kNarrowGroups ? groups : kNarrowGroups);
@@ -1249,18 +1416,34 @@ int ax_chunks(int64_t m, int n, int c) {
   return (int)(tiles < 8192 ? tiles : 8192);
 }
 
+// The vector form of A*W needs 16-byte aligned column runs of A (and of Y for
+// its RB-row stores).
+template <int RB, typename TA, typename TY>
+static bool ax_cv_ok(const TA* A, const TY* Y, int64_t m) {
+  return ((uintptr_t)A % (RB * sizeof(TA))) == 0 && m % RB == 0 && ((uintptr_t)Y % (RB * sizeof(TY))) == 0;
+}
+// Row runs (RB) and W chunk width (KC) of the vector A*W, as measured fastest
+// at 32768 x 512 (FP64, c = 24) and 640000 x 1280 (FP64 and FP32, c = 48):
+// FP64 data in runs of 2 rows, FP32 data in runs of 4 (2 where the FP64
+// accumulators of 4 rows would not fit the registers).
+template <typename TA, int NT, bool F32M>
+struct AxvCfg {
+  static constexpr int RB = sizeof(TA) == 8 ? 2 : (F32M || NT <= 3 ? 4 : 2);
+  static constexpr int KC = (sizeof(TA) == 8 && NT <= 2) || (sizeof(TA) == 4 && RB == 2) ? 32 : 16;
+};
+
 template <typename TA, typename TY, int LY>
 static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n, int c, int nchunks,
                           double* sumsqA, double* sumsqY, double* rerr, hipStream_t st) {
   dim3 grid(nchunks), block(kThreads);
   if (ax_narrow(n, c)) {
     const int nk = ax_nk(n);
-    const bool vec = LY == COL && ((uintptr_t)A % (4 * sizeof(TA))) == 0 && (m * (int64_t)sizeof(TA)) % (4 * sizeof(TA)) == 0 &&
-                     nk <= 16 && ((c + 15) / 16) <= 2;
-    if (vec) {
-#define TT_AXV(NTV, NKV) TT_LAUNCH((k_ax_narrow_v<TA, TY, NTV, NKV>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
-      if (c <= 16) { if (nk <= 4) TT_AXV(1, 4); else if (nk <= 8) TT_AXV(1, 8); else TT_AXV(1, 16); }
-      else { if (nk <= 4) TT_AXV(2, 4); else if (nk <= 8) TT_AXV(2, 8); else TT_AXV(2, 16); }
+    constexpr int RBV = 16 / (int)sizeof(TA);
+    if (LY == COL && ax_cv_ok<RBV>(A, Y, m) && ((c + 15) / 16) <= 2) {
+      const int nkv = (n + 3) / 4;
+#define TT_AXV(NTV, NKV) TT_LAUNCH((k_ax_narrow_v<TA, TY, NTV, NKV, RBV>), grid, block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
+      if (c <= 16) { if (nkv <= 4) TT_AXV(1, 4); else if (nkv <= 8) TT_AXV(1, 8); else if (nkv <= 12) TT_AXV(1, 12); else TT_AXV(1, 16); }
+      else { if (nkv <= 4) TT_AXV(2, 4); else if (nkv <= 8) TT_AXV(2, 8); else if (nkv <= 12) TT_AXV(2, 12); else TT_AXV(2, 16); }
 #undef TT_AXV
       return;
     }
@@ -1281,6 +1464,14 @@ static void ax_dispatch_l(const TA* A, const double* W, TY* Y, int64_t m, int n,
       TT_LAUNCH((k_ax_kw<TA, TY, 3, LY>), grid, dim3(ax_kw_threads(3)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
     else
       TT_LAUNCH((k_ax_kw<TA, TY, 4, LY>), grid, dim3(ax_kw_threads(4)), 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr);
+    return;
+  }
+  if (LY == COL && ax_cv_ok<2>(A, Y, m) && (sizeof(TA) == 8 || ax_cv_ok<4>(A, Y, m))) {
+#define TT_AXC(NTV)                                                                                       \
+  TT_LAUNCH((k_ax_cv<TA, TY, NTV, false, AxvCfg<TA, NTV, false>::RB, AxvCfg<TA, NTV, false>::KC>), grid, \
+            block, 0, st, A, W, Y, m, n, c, sumsqA, sumsqY, rerr)
+    if (c <= 16) TT_AXC(1); else if (c <= 32) TT_AXC(2); else if (c <= 48) TT_AXC(3); else TT_AXC(4);
+#undef TT_AXC
     return;
   }
   if (c <= 16)
@@ -1384,8 +1575,25 @@ hipError_t launch_ax_lp(const void* A, int a_f32, const double* W, float* Y, int
     if (nt == 1) TT_AXF(TAV, 1); else if (nt == 2) TT_AXF(TAV, 2);                                        \
     else if (nt == 3) TT_AXF(TAV, 3); else TT_AXF(TAV, 4);                                                \
   } while (0)
-  if (a_f32) { if (bf16) TT_AXL_NT(float, true); else TT_AXF_NT(float); }
-  else { if (bf16) TT_AXL_NT(double, true); else TT_AXF_NT(double); }
+#define TT_AXCV(TAV)                                                                                      \
+  do {                                                                                                    \
+    const int64_t cvt = (m + 64 * 4 - 1) / (64 * 4);                                                      \
+    dim3 g2((unsigned)(cvt < 8192 ? cvt : 8192));                                                         \
+    const TAV* Ap = (const TAV*)A;                                                                        \
+    const int nt = (c + 15) / 16;                                                                         \
+    if (nt == 1) TT_LAUNCH((k_ax_cv<TAV, float, 1, true, 4, AxvCfg<TAV, 1, true>::KC>), g2, block, 0, st, Ap, W, Y, m, n, c, nullptr, nullptr, nullptr); \
+    else if (nt == 2) TT_LAUNCH((k_ax_cv<TAV, float, 2, true, 4, AxvCfg<TAV, 2, true>::KC>), g2, block, 0, st, Ap, W, Y, m, n, c, nullptr, nullptr, nullptr); \
+    else if (nt == 3) TT_LAUNCH((k_ax_cv<TAV, float, 3, true, 4, AxvCfg<TAV, 3, true>::KC>), g2, block, 0, st, Ap, W, Y, m, n, c, nullptr, nullptr, nullptr); \
+    else TT_LAUNCH((k_ax_cv<TAV, float, 4, true, 4, AxvCfg<TAV, 4, true>::KC>), g2, block, 0, st, Ap, W, Y, m, n, c, nullptr, nullptr, nullptr); \
+  } while (0)
+  if (a_f32) {
+    if (bf16) TT_AXL_NT(float, true);
+    else if (layout == COL && ax_cv_ok<4>((const float*)A, Y, m)) TT_AXCV(float);
+    else TT_AXF_NT(float);
+  } else {
+    if (bf16) TT_AXL_NT(double, true); else TT_AXF_NT(double);
+  }
+#undef TT_AXCV
 #undef TT_AXF_NT
 #undef TT_AXF
 #undef TT_AXL_NT
