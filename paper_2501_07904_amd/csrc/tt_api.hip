@@ -247,6 +247,7 @@ struct Work {
   double* X;
   double* M;
   double* part;
+  int64_t part_len;   // doubles in part
   double* H;
   double* K;
   double* V1;
@@ -277,6 +278,8 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
     } else {
       z.Y = std::max(z.Y, s.m * (int64_t)c);
       z.X = std::max(z.X, (int64_t)s.n * c);
+      for (int cc = 1; cc <= c; ++cc)   // reused by the orthonormalisation of a tall n x cc iterate
+        z.part = std::max(z.part, orth_scratch(s.n, cc));
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, c) * s.n * c);
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, c, c) * c * c);
       if (P.alg4) {
@@ -309,6 +312,7 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.X = (double*)take(z.X * 8);
   W.M = (double*)take(z.X * 8);
   W.part = (double*)take(z.part * 8);
+  W.part_len = z.part;
   W.H = (double*)take((size_t)kCMax * kCMax * 8);
   W.K = (double*)take((size_t)kCMax * kCMax * 8);
   W.V1 = (double*)take(z.V1 * 8);
@@ -412,7 +416,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
         LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
                launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       }
-      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
     }
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
     // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank); in the
@@ -450,7 +454,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
              launch_atb2(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, 0, W.part, nch, st));
       LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
              launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
-      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
     }
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
            launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,

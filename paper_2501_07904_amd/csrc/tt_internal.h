@@ -104,8 +104,10 @@ hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st
 // Gaussian test matrix G (n x ell, k-major: G(i,j) at i*ell + j) of the step.
 hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st);
 // X = orth(M): explicit orthonormal factor of the Householder QR of M (n x c,
-// column-major); X is written k-major.
-hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st);
+// column-major; overwritten); X is written k-major.  Tall M is factorised as a
+// tree of block QRs in `scratch` (orth_scratch(n, c) doubles, may be 0).
+int64_t orth_scratch(int n, int c);
+hipError_t launch_orth(double* M, double* X, int n, int c, double* scratch, int64_t scratch_len, hipStream_t st);
 // Rayleigh-Ritz on span(X) (X k-major): K = (A X)^T (A X) (ell x ell) -> rank,
 // V1 = X Z_r, W = Z_r.
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st);

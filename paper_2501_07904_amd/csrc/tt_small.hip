@@ -95,95 +95,12 @@ __global__ void k_gen_sketch(double* G, SolveArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// Householder QR of X (n x c, column-major, leading dim ld), c <= 64, in
-// place: on return X holds the explicit orthonormal factor H_0 ... H_{c-1}
-// [I; 0].  A zero column gives an identity reflector, so the result stays
-// orthonormal for rank-deficient X.  Factorisation: per column one pass in
-// which a group of tpj threads per trailing column computes both the norm of
-// the pivot column and its own dot product, then updates its column (one
-// barrier per column).  The reflector v_k = [1; scal_k X[k+1:, k]] is kept
-// unscaled below the diagonal.  Q is then formed in place backwards, as
-// LAPACK's dorg2r does.
-__device__ __forceinline__ int group_width(int ncol) {
-  int tpj = 64;
-  while (tpj * ncol > kThreads && tpj > 1) tpj >>= 1;
-  return tpj;
-}
-
-__device__ __forceinline__ void householder_inplace(double* X, int64_t ld, int n, int c, double* tau, double* scal) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < c; ++k) {
-    const int ncol = c - k;
-    const int tpj = group_width(ncol);
-    const int g = t / tpj, lane = t % tpj;
-    const bool on = g < ncol;
-    const int j = k + g;
-    double sig = 0.0, gj = 0.0;
-    if (on) {
-#pragma unroll 4
-      for (int i = k + 1 + lane; i < n; i += tpj) {
-        const double xk = X[i + k * ld];
-        sig = fma(xk, xk, sig);
-        gj = fma(xk, X[i + j * ld], gj);
-      }
-    }
-    sig = group_sum(sig, tpj);
-    gj = group_sum(gj, tpj);
-    if (on) {
-      const double alpha = X[k + k * ld];
-      double tk = 0.0, sc = 0.0;
-      if (sig > 0.0) {
-        const double mu = sqrt(fma(alpha, alpha, sig));
-        const double beta = alpha <= 0.0 ? mu : -mu;
-        tk = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
-      }
-      if (g == 0) {
-        if (lane == 0) { tau[k] = tk; scal[k] = sc; }
-      } else if (tk != 0.0) {
-        const double xkj = X[k + j * ld];
-        const double f = tk * fma(sc, gj, xkj);  // tau * v^T x_j
-        if (lane == 0) X[k + j * ld] = xkj - f;
-        const double fs = f * sc;
-        for (int i = k + 1 + lane; i < n; i += tpj) X[i + j * ld] = fma(-fs, X[i + k * ld], X[i + j * ld]);
-      }
-    }
-    __syncthreads();
-  }
-  for (int k = c - 1; k >= 0; --k) {
-    const double tk = tau[k], sc = scal[k];
-    const int ncol = c - k - 1;
-    if (ncol > 0) {
-      const int tpj = group_width(ncol);
-      const int g = t / tpj, lane = t % tpj;
-      const bool on = g < ncol;
-      const int j = k + 1 + g;
-      double dsum = 0.0;
-      if (on && tk != 0.0)
-        for (int i = k + 1 + lane; i < n; i += tpj) dsum = fma(X[i + k * ld], X[i + j * ld], dsum);
-      dsum = group_sum(dsum, tpj);
-      if (on) {
-        // row k of column j is zero before H_k (it held an entry of R)
-        const double f = tk * sc * dsum;
-        if (lane == 0) X[k + j * ld] = -f;
-        if (tk != 0.0) {
-          const double fs = f * sc;
-          for (int i = k + 1 + lane; i < n; i += tpj) X[i + j * ld] = fma(-fs, X[i + k * ld], X[i + j * ld]);
-        }
-      }
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += kThreads)
-      X[i + k * ld] = (i < k) ? 0.0 : (i == k ? 1.0 - tk : -tk * sc * X[i + k * ld]);
-    __syncthreads();
-  }
-}
-
-// --------------------------------------------------------------------------
-// Register-resident Householder QR with the same result as householder_inplace
-// (explicit Q of X, n x c), for n <= R * tpj.  Thread group g (tpj threads,
-// tpj = kThreads / c rounded up to a power of two) owns column g and keeps its
-// rows i = lane + tpj*r (r < R) in registers.  Column k's Householder vector
+// Householder QR of X (n x c, c <= 64) with the explicit orthonormal factor
+// Q = H_0 ... H_{c-1} [I; 0] formed backwards (as LAPACK's dorg2r does); a
+// column already zero below the diagonal gives the identity reflector, so Q
+// stays orthonormal for rank-deficient X.  Register-resident, for n <= R * tpj:
+// thread group g (tpj threads, tpj = kThreads / c rounded up to a power of
+// two) owns column g and keeps its rows i = lane + tpj*r (r < R) in registers.  Column k's Householder vector
 // is published by its group through a double-buffered LDS vector, so both the
 // factorisation and the backward formation of Q take one barrier per column.
 // Input X(i, j) at X[i*xi + j*xj]; output Q(i, j) at Q[i*qi + j*qj] (may alias X).
@@ -194,9 +111,12 @@ __host__ __device__ __forceinline__ int reg_group_width(int c) {
   return tpj < 64 ? tpj : 64;
 }
 
+// Rout (optional): the c x c triangular factor R(i, j) at Rout[i*ri + j*rj],
+// zero below the diagonal, with M = Q R.
 template <int R, int TPJ>
 __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int64_t xj, double* Q, int64_t qi,
-                                                int64_t qj, int n, int c, double* vbuf) {
+                                                int64_t qj, int n, int c, double* vbuf, double* Rout = nullptr,
+                                                int64_t ri = 0, int64_t rj = 0) {
   // rows are padded to NP = R * TPJ with zeros, so the loops below need no row
   // guards; TPJ (= reg_group_width(c)) is a compile-time constant so that the
   // LDS offsets of a thread's rows are immediates.  Step k of the
@@ -213,7 +133,7 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
     x[r] = (own && i < n) ? X[i * xi + g * xj] : 0.0;
   }
   double* taus = vbuf + 2 * NP;
-  double my_tau = 0.0;
+  double my_tau = 0.0, my_diag = 0.0;
   // ---- factorisation
   for (int k = 0; k < c; ++k) {
     if (k > 0 && own && g >= k) {
@@ -242,11 +162,13 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
       sig = group_sum(sig, TPJ);
       alpha = group_sum(alpha, TPJ);   // one lane holds row k, the others add zero
       double tk = 0.0, sc = 0.0;
+      my_diag = alpha;   // R(k, k): alpha when column k is already zero below row k, else beta
       if (sig > 0.0) {
         const double mu = sqrt(fma(alpha, alpha, sig));
         const double beta = alpha <= 0.0 ? mu : -mu;
         tk = (beta - alpha) / beta;
         sc = 1.0 / (alpha - beta);
+        my_diag = beta;
       }
       my_tau = tk;
       double* v = vbuf + (k & 1) * NP + lane;
@@ -260,6 +182,14 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
       if (lane == 0) taus[k] = tk;
     }
     __syncthreads();
+  }
+  if (Rout && own) {
+    // column g: rows above the diagonal hold R, row g keeps alpha (R(g, g) is my_diag)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + TPJ * r;
+      if (i < c) Rout[i * ri + g * rj] = (i < g) ? x[r] : (i == g ? my_diag : 0.0);
+    }
   }
   // ---- Q = H_0 ... H_{c-1} [I; 0], backwards: group k publishes v_k, the
   // groups g > k apply H_k to their columns, group k forms H_k e_k
@@ -307,118 +237,6 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
   __syncthreads();
 }
 
-// Same algorithm and thread mapping with the columns kept in LDS (W, column g
-// at W + g*NP) instead of registers: each thread touches only its own rows of
-// its own column, so the accesses are conflict-free and independent; used
-// when R rows per thread would not fit the register budget of 1024 threads.
-template <int R, int TPJ>
-__device__ __forceinline__ void householder_lds(const double* X, int64_t xi, int64_t xj, double* Q, int64_t qi,
-                                                int64_t qj, int n, int c, double* W, double* vbuf) {
-  const int t = threadIdx.x;
-  constexpr int tpj = TPJ;
-  constexpr int NP = R * TPJ;
-  const int g = t / tpj, lane = t % tpj;
-  const bool own = g < c;
-  double* x = W + (int64_t)g * NP + lane;   // row lane + tpj*r at x[tpj*r]
-  if (own) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = lane + tpj * r;
-      x[tpj * r] = (i < n) ? X[i * xi + g * xj] : 0.0;
-    }
-  }
-  double* taus = vbuf + 2 * NP;
-  double my_tau = 0.0;
-  for (int k = 0; k < c; ++k) {
-    double* v = vbuf + (k & 1) * NP + lane;
-    if (g == k) {
-      double sig = 0.0, alpha = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
-        const double xr = x[tpj * r];
-        sig = fma(i > k ? xr : 0.0, xr, sig);
-        alpha += (i == k) ? xr : 0.0;
-      }
-      sig = group_sum(sig, tpj);
-      alpha = group_sum(alpha, tpj);
-      double tk = 0.0, sc = 0.0;
-      if (sig > 0.0) {
-        const double mu = sqrt(fma(alpha, alpha, sig));
-        const double beta = alpha <= 0.0 ? mu : -mu;
-        tk = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
-      }
-      my_tau = tk;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
-        const double xr = x[tpj * r];
-        const double vi = (i < k) ? 0.0 : (i == k ? 1.0 : sc * xr);
-        v[tpj * r] = vi;
-        x[tpj * r] = (i > k) ? vi : xr;
-      }
-      if (lane == 0) taus[k] = tk;
-    }
-    __syncthreads();
-    if (own && g > k) {
-      const double tk = taus[k];
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; r += 2) {
-        d0 = fma(v[tpj * r], x[tpj * r], d0);
-        if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
-      }
-      double dot = d0 + d1;
-      dot = group_sum(dot, tpj);
-      const double f = tk * dot;
-#pragma unroll
-      for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
-    }
-  }
-  __syncthreads();
-  for (int k = c - 1; k >= 0; --k) {
-    double* v = vbuf + (k & 1) * NP + lane;
-    if (g == k) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
-        v[tpj * r] = (i < k) ? 0.0 : (i == k ? 1.0 : x[tpj * r]);
-      }
-      if (lane == 0) taus[k] = my_tau;
-    }
-    __syncthreads();
-    if (own && g > k) {
-      const double tk = taus[k];
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; r += 2) {
-        d0 = fma(v[tpj * r], x[tpj * r], d0);
-        if (r + 1 < R) d1 = fma(v[tpj * (r + 1)], x[tpj * (r + 1)], d1);
-      }
-      double dot = d0 + d1;
-      dot = group_sum(dot, tpj);
-      const double f = tk * dot;
-#pragma unroll
-      for (int r = 0; r < R; ++r) x[tpj * r] = fma(-f, v[tpj * r], x[tpj * r]);
-    } else if (g == k) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = lane + tpj * r;
-        x[tpj * r] = (i < k) ? 0.0 : (i == k ? 1.0 - my_tau : -my_tau * x[tpj * r]);
-      }
-    }
-  }
-  __syncthreads();
-  if (own) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = lane + tpj * r;
-      if (i < n) Q[i * qi + g * qj] = x[tpj * r];
-    }
-  }
-  __syncthreads();
-}
 
 // Rows per thread the register path needs for an n x c block (0: too large).
 __device__ __host__ __forceinline__ int reg_rows(int n, int c) {
@@ -762,38 +580,13 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
 }
 
 // --------------------------------------------------------------------------
-// X = orth(M) for n x c blocks; LDS-resident when it fits, else in place in
-// global memory (M is overwritten by the reflectors).
-constexpr int kOrthLdsDoubles = 19456;
-constexpr int kRegMaxN = 64 * 16;   // largest padded n of the register path (tpj <= 64, R <= 16)   // 152 KB: n x c blocks up to this size stay in LDS
-
-__global__ __launch_bounds__(kThreads) void k_orth(double* M, double* X, int n, int c) {
-  __shared__ double buf[kOrthLdsDoubles];
-  __shared__ double tau[kCMax], scal[kCMax];
-  const int t = threadIdx.x;
-  if ((int64_t)n * c <= kOrthLdsDoubles) {
-    for (int e = t; e < n * c; e += kThreads) buf[e] = M[e];
-    __syncthreads();
-    householder_inplace(buf, n, n, c, tau, scal);
-    for (int e = t; e < n * c; e += kThreads) X[e] = buf[(e / c) + (int64_t)n * (e % c)];
-  } else {
-    // large blocks: factor in place in M (global), then write X k-major
-    householder_inplace(M, n, n, c, tau, scal);
-    for (int64_t e = t; e < (int64_t)n * c; e += kThreads) X[e] = M[(e / c) + (int64_t)n * (e % c)];
-  }
-}
-
+// X = orth(M) for n x c blocks (M column-major, X k-major).
 // Register-resident variant for n <= R * tpj (one kernel per R so that each
 // allocates only the registers it needs).
 template <int R, int TPJ>
 __global__ __launch_bounds__(kThreads) void k_orth_reg(const double* M, double* X, int n, int c) {
   __shared__ double vbuf[2 * R * TPJ + kCMax];
-  if constexpr (R <= 16) {
-    householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf);
-  } else {
-    __shared__ double wcols[R * kThreads];   // (kThreads / TPJ) columns of R * TPJ rows
-    householder_lds<R, TPJ>(M, 1, n, X, c, 1, n, c, wcols, vbuf);
-  }
+  householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf);
 }
 
 template <int R>
@@ -992,14 +785,90 @@ hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_orth(double* M, double* X, int n, int c, hipStream_t st) {
-  if (n < 1 || c < 1 || c > kCMax || c > n) return hipErrorInvalidValue;
-  switch (reg_rows(n, c)) {
-    case 4: launch_orth_reg<4>(M, X, n, c, st); break;
-    case 8: launch_orth_reg<8>(M, X, n, c, st); break;
-    case 16: launch_orth_reg<16>(M, X, n, c, st); break;
-    default: TT_LAUNCH(k_orth, dim3(1), dim3(kThreads), 0, st, M, X, n, c); break;
+// Taller blocks: a tree of register QRs (TSQR).  The n rows are split into P
+// balanced leaf blocks of at most tsqr_block_rows(c) rows (each at least half
+// that, so never fewer than c); leaf b factors M_b = Q_b R_b in its own
+// workgroup, Q_b overwriting its rows of M and R_b going to rows b*c .. b*c+c-1
+// of the stacked (P c) x c matrix S.  Then S = Q_S R (recursively, by the same
+// routine), and X = diag(Q_b) Q_S: row i of leaf b is Q_b(i, :) Q_S(b c : b c + c, :).
+// X spans the column space of M and has orthonormal columns like the one-block
+// factorisation (the two may differ in the signs of the columns).
+static int tsqr_block_rows(int c) { return 16 * reg_group_width(c); }
+
+__host__ __device__ __forceinline__ void tsqr_block(int n, int P, int b, int* r0, int* rows) {
+  const int q = n / P, e = n % P;   // the first e blocks take one more row
+  *r0 = b * q + (b < e ? b : e);
+  *rows = q + (b < e ? 1 : 0);
+}
+
+template <int R, int TPJ>
+__global__ __launch_bounds__(kThreads) void k_tsqr_leaf(double* M, int n, int c, int P, double* S) {
+  __shared__ double vbuf[2 * R * TPJ + kCMax];
+  int r0, rows;
+  tsqr_block(n, P, blockIdx.x, &r0, &rows);
+  householder_reg<R, TPJ>(M + r0, 1, n, M + r0, 1, n, rows, c, vbuf, S + (int64_t)blockIdx.x * c, 1,
+                          (int64_t)P * c);
+}
+
+constexpr int kCombineThreads = 256;
+__global__ __launch_bounds__(kCombineThreads) void k_tsqr_combine(const double* __restrict__ M, int n, int c, int P,
+                                                                  const double* __restrict__ QS, double* __restrict__ X) {
+  __shared__ double sq[kCMax * kCMax];
+  int r0, rows;
+  tsqr_block(n, P, blockIdx.x, &r0, &rows);
+  // rows b*c .. b*c+c-1 of Q_S (k-major) are one contiguous c x c block
+  for (int e = threadIdx.x; e < c * c; e += kCombineThreads) sq[e] = QS[(int64_t)blockIdx.x * c * c + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * c; e += kCombineThreads) {
+    const int i = e / c, j = e % c;
+    double s = 0.0;
+    for (int l = 0; l < c; ++l) s = fma(M[(r0 + i) + (int64_t)l * n], sq[l * c + j], s);
+    X[(int64_t)(r0 + i) * c + j] = s;
   }
+}
+
+template <int R>
+static void launch_tsqr_leaf(double* M, int n, int c, int P, double* S, hipStream_t st) {
+  const int tpj = reg_group_width(c);
+  if (tpj == 16) TT_LAUNCH((k_tsqr_leaf<R, 16>), dim3(P), dim3(kThreads), 0, st, M, n, c, P, S);
+  else if (tpj == 32) TT_LAUNCH((k_tsqr_leaf<R, 32>), dim3(P), dim3(kThreads), 0, st, M, n, c, P, S);
+  else TT_LAUNCH((k_tsqr_leaf<R, 64>), dim3(P), dim3(kThreads), 0, st, M, n, c, P, S);
+}
+
+int64_t orth_scratch(int n, int c) {
+  if (c < 1 || c > kCMax || n <= tsqr_block_rows(c)) return 0;
+  const int P = (n + tsqr_block_rows(c) - 1) / tsqr_block_rows(c);
+  const int n2 = P * c;
+  return 2 * (int64_t)n2 * c + orth_scratch(n2, c);
+}
+
+hipError_t launch_orth(double* M, double* X, int n, int c, double* scratch, int64_t scratch_len, hipStream_t st) {
+  if (n < 1 || c < 1 || c > kCMax || c > n) return hipErrorInvalidValue;
+  const int nbmax = tsqr_block_rows(c);
+  if (n <= nbmax) {
+    switch (reg_rows(n, c)) {
+      case 4: launch_orth_reg<4>(M, X, n, c, st); break;
+      case 8: launch_orth_reg<8>(M, X, n, c, st); break;
+      default: launch_orth_reg<16>(M, X, n, c, st); break;
+    }
+    return hipGetLastError();
+  }
+  if (!scratch || scratch_len < orth_scratch(n, c)) return hipErrorInvalidValue;
+  const int P = (n + nbmax - 1) / nbmax;
+  const int n2 = P * c;
+  double* S = scratch;
+  double* QS = scratch + (int64_t)n2 * c;
+  const int rmax = (n + P - 1) / P;   // rows of the largest leaf block
+  switch (reg_rows(rmax, c)) {
+    case 4: launch_tsqr_leaf<4>(M, n, c, P, S, st); break;
+    case 8: launch_tsqr_leaf<8>(M, n, c, P, S, st); break;
+    default: launch_tsqr_leaf<16>(M, n, c, P, S, st); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_orth(S, QS, n2, c, QS + (int64_t)n2 * c, scratch_len - 2 * (int64_t)n2 * c, st);
+  if (e != hipSuccess) return e;
+  TT_LAUNCH(k_tsqr_combine, dim3(P), dim3(kCombineThreads), 0, st, M, n, c, P, QS, X);
   return hipGetLastError();
 }
 

@@ -136,6 +136,25 @@ def test_ragged_shapes(sweep, variant):
     np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
 
 
+@pytest.mark.parametrize("dims,ranks,p", [
+    ([200, 30, 40], [8, 36], 8),      # ell = 16, n = 1080 > 1024 rows: two leaf blocks
+    ([200, 30, 20], [16, 18], 8),     # ell = 24, n = 540 > 512
+    ([300, 30, 20], [24, 18], 16),    # ell = 40, n = 540 > 256: three leaf blocks
+    ([100, 30, 60], [24, 56], 16),    # ell = 40, n = 1680: seven leaf blocks whose stacked R is split again
+])
+@pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
+def test_tall_iterate_tree_qr(dims, ranks, p, sweep, variant):
+    """Core-side iterates taller than one register-resident QR block take the
+    tree (TSQR) orthonormalisation: same cores as the oracle's Householder QR."""
+    if sweep == "L2R":
+        dims, ranks = dims[::-1], ranks[::-1]
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, 106)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=ranks, q=1, p=p, exact_delta=True)
+    assert rep["ranks"] == orep["ranks"]
+    _compare(cores, oc, sweep)
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+
+
 @pytest.mark.parametrize("sweep,variant", COMBOS)
 def test_truncation_below_true_rank(sweep, variant):
     """Ranks below the generating ranks: real truncation with well-separated spectra."""
