@@ -116,7 +116,7 @@ __host__ __device__ __forceinline__ int reg_group_width(int c) {
 template <int R, int TPJ>
 __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int64_t xj, double* Q, int64_t qi,
                                                 int64_t qj, int n, int c, double* vbuf, double* Rout = nullptr,
-                                                int64_t ri = 0, int64_t rj = 0) {
+                                                int64_t ri = 0, int64_t rj = 0, double* vall = nullptr) {
   // rows are padded to NP = R * TPJ with zeros, so the loops below need no row
   // guards; TPJ (= reg_group_width(c)) is a compile-time constant so that the
   // LDS offsets of a thread's rows are immediates.  Step k of the
@@ -191,9 +191,47 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
       if (i < c) Rout[i * ri + g * rj] = (i < g) ? x[r] : (i == g ? my_diag : 0.0);
     }
   }
-  // ---- Q = H_0 ... H_{c-1} [I; 0], backwards: group k publishes v_k, the
-  // groups g > k apply H_k to their columns, group k forms H_k e_k
-  for (int k = c - 1; k >= 0; --k) {
+  // ---- Q = H_0 ... H_{c-1} [I; 0]; column g is H_0 ... H_g e_g, since
+  // H_k e_g = e_g for k > g
+  if (vall) {
+    // all reflectors are known: publish them together (vall holds NP x c),
+    // then every group forms its own column, H_g e_g followed by H_{g-1}, ...,
+    // H_0, with no further barrier (the same operations in the same order as
+    // the step-wise loop below)
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + TPJ * r;
+        vall[g * NP + i] = (i < g) ? 0.0 : (i == g ? 1.0 : x[r]);
+      }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + TPJ * r;
+        x[r] = (i < g) ? 0.0 : (i == g ? 1.0 - my_tau : -my_tau * x[r]);
+      }
+      for (int k = g - 1; k >= 0; --k) {
+        const double* v = vall + k * NP + lane;
+        const double tk = taus[k];
+        double vr[R];
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          vr[r] = v[TPJ * r];
+          if (r & 1) d1 = fma(vr[r], x[r], d1);
+          else d0 = fma(vr[r], x[r], d0);
+        }
+        const double f = tk * group_sum(d0 + d1, TPJ);
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
+      }
+    }
+  }
+  // step-wise: group k publishes v_k, the groups g > k apply H_k to their
+  // columns, group k forms H_k e_k
+  for (int k = c - 1; k >= 0 && !vall; --k) {
     if (g == k) {
       double* v = vbuf + (k & 1) * NP + lane;
 #pragma unroll
@@ -583,10 +621,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
 // X = orth(M) for n x c blocks (M column-major, X k-major).
 // Register-resident variant for n <= R * tpj (one kernel per R so that each
 // allocates only the registers it needs).
+// (vall: the c reflectors of R * TPJ rows, c <= kThreads / TPJ)
 template <int R, int TPJ>
 __global__ __launch_bounds__(kThreads) void k_orth_reg(const double* M, double* X, int n, int c) {
   __shared__ double vbuf[2 * R * TPJ + kCMax];
-  householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf);
+  __shared__ double vall[R * kThreads];
+  householder_reg<R, TPJ>(M, 1, n, X, c, 1, n, c, vbuf, nullptr, 0, 0, vall);
 }
 
 template <int R>
@@ -804,10 +844,11 @@ __host__ __device__ __forceinline__ void tsqr_block(int n, int P, int b, int* r0
 template <int R, int TPJ>
 __global__ __launch_bounds__(kThreads) void k_tsqr_leaf(double* M, int n, int c, int P, double* S) {
   __shared__ double vbuf[2 * R * TPJ + kCMax];
+  __shared__ double vall[R * kThreads];
   int r0, rows;
   tsqr_block(n, P, blockIdx.x, &r0, &rows);
   householder_reg<R, TPJ>(M + r0, 1, n, M + r0, 1, n, rows, c, vbuf, S + (int64_t)blockIdx.x * c, 1,
-                          (int64_t)P * c);
+                          (int64_t)P * c, vall);
 }
 
 constexpr int kCombineThreads = 256;

@@ -1167,8 +1167,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A,
         for (int q = 0; q < NT; ++q) b[q] = sW[buf][4 * s + g][16 * q + li];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const double xd = (double)a[s][rb];
-          ssa = fma(xd, xd, ssa);
+          if constexpr (!F32M) {   // the FP32 form is launched without sums
+            const double xd = (double)a[s][rb];
+            ssa = fma(xd, xd, ssa);
+          }
           const TM x = (TM)a[s][rb];
 #pragma unroll
           for (int q = 0; q < NT; ++q) {
