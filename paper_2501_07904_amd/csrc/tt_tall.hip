@@ -1301,21 +1301,25 @@ __global__ __launch_bounds__(kThreads) void k_reduce_scalar(const double* __rest
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partials, int nchunks,
-                                                     int64_t size, double* __restrict__ out,
-                                                     double* __restrict__ out2) {
-  // 16 consecutive entries x 16 chunk slices; slices are summed in a fixed order
-  __shared__ double red[16][17];
+// 16 consecutive entries x SL chunk slices per workgroup (slice sl sums chunks
+// sl, sl + SL, ...); the slices are then summed in a fixed order: SL = 16
+// for few chunks, 64 when there are many chunks of a small matrix (a Gram
+// pass's partials), so that each thread's chain of dependent loads stays short.
+template <int SL>
+__global__ __launch_bounds__(16 * SL) void k_reduce(const double* __restrict__ partials, int nchunks,
+                                                    int64_t size, double* __restrict__ out,
+                                                    double* __restrict__ out2) {
+  __shared__ double red[SL][17];
   const int el = threadIdx.x & 15, sl = threadIdx.x >> 4;
   const int64_t e = (int64_t)blockIdx.x * 16 + el;
   double s = 0.0;
   if (e < size)
-    for (int ch = sl; ch < nchunks; ch += 16) s += partials[(int64_t)ch * size + e];
+    for (int ch = sl; ch < nchunks; ch += SL) s += partials[(int64_t)ch * size + e];
   red[sl][el] = s;
   __syncthreads();
   if (sl == 0 && e < size) {
     double tot = 0.0;
-    for (int k = 0; k < 16; ++k) tot += red[k][el];
+    for (int k = 0; k < SL; ++k) tot += red[k][el];
     out[e] = tot;
     if (out2) out2[e] = tot;
   }
@@ -1537,8 +1541,10 @@ hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, doub
     return hipGetLastError();
   }
   const int64_t blocks = (size + 15) / 16;
-  TT_LAUNCH(k_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, st, partials, nchunks,
-                     size, out, out2);
+  if (nchunks >= 256)
+    TT_LAUNCH(k_reduce<64>, dim3((unsigned)blocks), dim3(16 * 64), 0, st, partials, nchunks, size, out, out2);
+  else
+    TT_LAUNCH(k_reduce<16>, dim3((unsigned)blocks), dim3(16 * 16), 0, st, partials, nchunks, size, out, out2);
   return hipGetLastError();
 }
 
