@@ -141,6 +141,7 @@ def test_ragged_shapes(sweep, variant):
     ([200, 30, 20], [16, 18], 8),     # ell = 24, n = 540 > 512
     ([300, 30, 20], [24, 18], 16),    # ell = 40, n = 540 > 256: three leaf blocks
     ([100, 30, 60], [24, 56], 16),    # ell = 40, n = 1680: seven leaf blocks whose stacked R is split again
+    ([300, 30, 20], [56, 18], 8),     # ell = 64, the widest iterate, n = 540
 ])
 @pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
 def test_tall_iterate_tree_qr(dims, ranks, p, sweep, variant):
@@ -378,6 +379,30 @@ def test_mixed_fixed_rank_bound_and_agreement(sweep, variant, prec):
     else:
         # BF16 power products: a coarser sketch, still within a few percent of the FP64 error
         assert err <= 1.05 * np.linalg.norm(rec64 - a32)
+
+
+@pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
+def test_mixed_tall_iterate(sweep, variant):
+    """The mixed form where the sketched step takes the wide streaming kernels
+    (m = 8192 rows, n = 540 core-side columns, ell = 40: FP32 matrix-core A*X
+    and A^T Y, the FP64-accumulating Rayleigh-Ritz pass, the tree QR): same
+    ranks as the FP64 form, the stated bound holds, and the result stays
+    within FP32 storage accuracy of the FP64 form."""
+    dims, ranks = [8192, 30, 20], [24, 18]
+    if sweep == "L2R":
+        dims, ranks = dims[::-1], ranks[::-1]
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-4, 121)
+    A = _dev(a.astype(np.float32))
+    a32 = a.astype(np.float32).astype(np.float64)
+    c64, r64 = T.tt_utv_decompose(A, dims, ranks=ranks, sweep=sweep, variant=variant, q=1, oversample=16,
+                                  exact_delta=True)
+    cmx, rmx = T.tt_utv_decompose(A, dims, ranks=ranks, sweep=sweep, variant=variant, q=1, oversample=16,
+                                  exact_delta=True, prec="mixed")
+    assert rmx["ranks"] == r64["ranks"]
+    rec64 = T.tt_reconstruct(c64).cpu().numpy()
+    recmx = T.tt_reconstruct(cmx).cpu().numpy()
+    assert np.linalg.norm(recmx - a32) <= rmx["err_bound"] * (1 + 1e-9)
+    assert np.linalg.norm(recmx - rec64) <= 1e-5 * np.linalg.norm(a32)
 
 
 def test_mixed_eps_1e6_function_tensor():
