@@ -35,88 +35,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// partials[chunk] = A[rows of chunk, j0:j0+64]^T * Y[rows of chunk, :]
-// grid: (nchunks, ceil(n/64)); each thread owns a 4x4 block of the 64 x c
-// output and a subset of the rows of every 32-row tile staged in LDS.
+// Row tiles and column blocks that fix the chunking of the A^T Y passes
+// (atb_chunks): 32-row tiles, 64-column blocks.
 constexpr int kAtbTR = 32;
 constexpr int kAtbJT = 64;
-
-template <typename TA, typename TY>
-__global__ __launch_bounds__(kThreads) void k_atb(const TA* __restrict__ A, const TY* __restrict__ Y,
-                                                  int64_t m, int n, int c, int layout,
-                                                  int64_t rows_per_chunk,
-                                                  double* __restrict__ partials) {
-  // tiles and the final reduction scratch share the same LDS
-  __shared__ double lds[2 * kAtbTR * (kAtbJT + 1) > kThreads * 16 ? 2 * kAtbTR * (kAtbJT + 1) : kThreads * 16];
-  double (*sA)[kAtbJT + 1] = reinterpret_cast<double (*)[kAtbJT + 1]>(lds);
-  double (*sY)[kCMax + 1] = reinterpret_cast<double (*)[kCMax + 1]>(lds + kAtbTR * (kAtbJT + 1));
-  double* red = lds;
-  const bool gram = ((const void*)A == (const void*)Y);   // Y = A: the tile of A serves both sides
-  const int t = threadIdx.x;
-  const int64_t chunk = blockIdx.x;
-  const int j0 = blockIdx.y * kAtbJT;
-  const int jt = min(kAtbJT, n - j0);
-  const int nbj = (jt + 3) >> 2, nbc = (c + 3) >> 2, nblk = nbj * nbc;
-  const int RG = kThreads / nblk;  // nblk <= 256, so RG >= 1
-  const int blk = t % nblk, rg = t / nblk;
-  const bool active = rg < RG;
-  const int bj = (blk / nbc) * 4, bc = (blk % nbc) * 4;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-
-  const int64_t r0 = chunk * rows_per_chunk;
-  const int64_t r1 = min(m, r0 + rows_per_chunk);
-  for (int64_t rb = r0; rb < r1; rb += kAtbTR) {
-    const int tr = (int)min((int64_t)kAtbTR, r1 - rb);
-    // stage A[rb:rb+tr, j0:j0+jt] and Y[rb:rb+tr, 0:c]; zero-fill the padding
-    for (int e = t; e < kAtbTR * kAtbJT; e += kThreads) {
-      int i, j;
-      if (layout == ROW) { i = e / kAtbJT; j = e % kAtbJT; } else { i = e % kAtbTR; j = e / kAtbTR; }
-      sA[i][j] = (i < tr && j < jt) ? ldv(A, at(layout, rb + i, j0 + j, m, n)) : 0.0;
-    }
-    if (!gram) {
-      for (int e = t; e < kAtbTR * kCMax; e += kThreads) {
-        int i, j;
-        if (layout == ROW) { i = e / kCMax; j = e % kCMax; } else { i = e % kAtbTR; j = e / kAtbTR; }
-        sY[i][j] = (i < tr && j < c) ? ldv(Y, at(layout, rb + i, j, m, c)) : 0.0;
-      }
-    }
-    __syncthreads();
-    if (active) {
-      for (int i = rg; i < tr; i += RG) {
-        double a[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = sA[i][bj + u];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) y[v] = gram ? sA[i][bc + v] : sY[i][bc + v];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], y[v], acc[u][v]);
-      }
-    }
-    __syncthreads();
-  }
-  // fixed-order reduction over the row groups
-  if (active) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) red[(rg * nblk + blk) * 16 + u * 4 + v] = acc[u][v];
-  }
-  __syncthreads();
-  double* out = partials + chunk * (int64_t)n * c;
-  for (int e = t; e < jt * c; e += kThreads) {
-    const int j = e % jt, cc = e / jt;
-    const int b = (j >> 2) * nbc + (cc >> 2), u = j & 3, v = cc & 3;
-    double s = 0.0;
-    for (int g = 0; g < RG; ++g) s += red[(g * nblk + b) * 16 + u * 4 + v];
-    out[(j0 + j) + (int64_t)n * cc] = s;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Y = A W on the FP64 matrix cores.  W (n x c) is k-major (row k = c
@@ -137,74 +59,6 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 
 constexpr int kAxKC = 64;
 constexpr int kAxSplitTiles = 128;   // A*W splits its k range when A has fewer 64-row tiles
-
-// ---------------------------------------------------------------------------
-// partials[chunk] = A[rows of chunk, j0:j0+64]^T Y[rows of chunk, :] for FP64
-// operands on the matrix cores.  Row tiles of 32 rows of A (64 columns) and Y
-// (all c columns, zero-padded to 16*NT) are staged in LDS with coalesced loads
-// (COL: each column segment is contiguous; ROW: each row segment is); wave w
-// then owns output rows j0+16w .. j0+16w+15 and computes their 16 x 16*NT block
-// with v_mfma_f64_16x16x4, the k-slots running over the rows of the tile
-// (operand A: lane l holds A(i0 + l/16, j0 + 16w + l%16); operand B: lane l
-// holds Y(i0 + l/16, 16t + l%16)).  With Y == A (Gram) the tile of A serves
-// both sides.
-constexpr int kAtbMR = 32;
-
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_atb_mfma(const double* __restrict__ A, const double* __restrict__ Y,
-                                                       int64_t m, int n, int c, int layout,
-                                                       int64_t rows_per_chunk, double* __restrict__ partials) {
-  __shared__ double sA[kAtbMR][kAtbJT + 1];
-  __shared__ double sY[kAtbMR][NT * 16 + 1];
-  const bool gram = (A == Y);
-  const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int g = lane >> 4, li = lane & 15;
-  const int64_t chunk = blockIdx.x;
-  const int j0 = blockIdx.y * kAtbJT;
-  const int jt = min(kAtbJT, n - j0);
-  const int64_t r0 = chunk * rows_per_chunk;
-  const int64_t r1 = min(m, r0 + rows_per_chunk);
-  d4 acc[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t rb = r0; rb < r1; rb += kAtbMR) {
-    const int tr = (int)min((int64_t)kAtbMR, r1 - rb);
-    __syncthreads();
-    for (int e = t; e < kAtbMR * kAtbJT; e += kThreads) {
-      int i, j;
-      if (layout == ROW) { i = e / kAtbJT; j = e % kAtbJT; } else { i = e % kAtbMR; j = e / kAtbMR; }
-      sA[i][j] = (i < tr && j < jt) ? A[at(layout, rb + i, j0 + j, m, n)] : 0.0;
-    }
-    if (!gram) {
-      for (int e = t; e < kAtbMR * NT * 16; e += kThreads) {
-        int i, j;
-        if (layout == ROW) { i = e / (NT * 16); j = e % (NT * 16); } else { i = e % kAtbMR; j = e / kAtbMR; }
-        sY[i][j] = (i < tr && j < c) ? Y[at(layout, rb + i, j, m, c)] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kAtbMR / 4; ++ks) {
-      const int i = 4 * ks + g;
-      const double a = sA[i][16 * w + li];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const double b = gram ? sA[i][16 * q + li] : sY[i][16 * q + li];
-        acc[q] = mfma_f64(a, b, acc[q]);
-      }
-    }
-  }
-  double* out = partials + chunk * (int64_t)n * c;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = 16 * w + g + 4 * v, cc = 16 * q + li;
-      if (j < jt && cc < c) out[(j0 + j) + (int64_t)n * cc] = acc[q][v];
-    }
-  }
-}
 
 // Loads of one kAxKC-column chunk of A for the MFMA operand of this lane:
 // a[ss*8 + s8] = A(row, k0 + 32 ss + 8 g + s8), zero outside the matrix; ssa
@@ -1364,38 +1218,13 @@ hipError_t launch_atb(const void* A, int a_f32, const void* Y, int y_f32, int64_
                       int layout, double* partials, int nchunks, hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
   const int64_t rpc = (m + nchunks - 1) / nchunks;
-  dim3 grid(nchunks, (n + kAtbJT - 1) / kAtbJT);
-  if (!a_f32 && !y_f32) {
-    // FP64 operands: matrix-core kernel (Gram: Y == A with c == n <= 64)
-    const bool gram = (A == Y);
-    if (gram && (c != n || n > kAtbJT)) return hipErrorInvalidValue;
-    if (gram)   // row chunks rounded to whole 32-row runs (empty trailing chunks give zero partials)
-      return launch_gram_narrow<double>((const double*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
-    if (c <= 16)
-      TT_LAUNCH((k_atb_mfma<1>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
-                         layout, rpc, partials);
-    else if (c <= 32)
-      TT_LAUNCH((k_atb_mfma<2>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
-                         layout, rpc, partials);
-    else if (c <= 48)
-      TT_LAUNCH((k_atb_mfma<3>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
-                         layout, rpc, partials);
-    else
-      TT_LAUNCH((k_atb_mfma<4>), grid, dim3(kThreads), 0, st, (const double*)A, (const double*)Y, m, n, c,
-                         layout, rpc, partials);
+  // Gram passes (Y == A, c == n <= 64): both operands from the same loads; row
+  // chunks rounded to whole 32-row runs (empty trailing chunks give zero partials)
+  if (A == Y && a_f32 == y_f32 && c == n && n <= kAtbJT) {
+    if (a_f32) return launch_gram_narrow<float>((const float*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
+    return launch_gram_narrow<double>((const double*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
   }
-  else if (a_f32 && y_f32 && A == Y && c == n && n <= kAtbJT)
-    return launch_gram_narrow<float>((const float*)A, m, n, layout, (rpc + 31) / 32 * 32, partials, nchunks, st);
-  else if (a_f32 && y_f32)
-    TT_LAUNCH((k_atb<float, float>), grid, dim3(kThreads), 0, st, (const float*)A,
-                       (const float*)Y, m, n, c, layout, rpc, partials);
-  else if (a_f32)
-    TT_LAUNCH((k_atb<float, double>), grid, dim3(kThreads), 0, st, (const float*)A,
-                       (const double*)Y, m, n, c, layout, rpc, partials);
-  else
-    TT_LAUNCH((k_atb<double, float>), grid, dim3(kThreads), 0, st, (const double*)A,
-                       (const float*)Y, m, n, c, layout, rpc, partials);
-  return hipGetLastError();
+  return launch_atb2(A, a_f32, Y, y_f32, m, n, c, layout, 0, partials, nchunks, st);
 }
 
 // Short A: the k range is split over the waves of a workgroup of 16 rows.
