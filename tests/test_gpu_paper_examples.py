@@ -1,0 +1,60 @@
+"""The paper's Example 2 at its own size on the GPU (Sec. 4.1, Table "Beps").
+
+B(i1..i4) = sin(sqrt(sum_k ((i_k - 1)/(I - 1))^2)), I = 160: a 5.2 GB FP64
+tensor, built on the device.  For each prescribed relative error of the
+table, TT-ULV left-to-right must return the TT-SVD ranks the table prints,
+and TT-URV right-to-left the same ranks in the order its sweep meets the
+bonds (B is symmetric in its four indices, so a right-to-left sweep sees
+bond 3 first); the error stays below eps and below the reported bound."""
+import os
+
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2501_07904_amd")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "table_beps_ttsvd_ranks.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append((float(line.split()[0]), [int(x) for x in line.split()[1:]]))
+    return rows
+
+
+@pytest.fixture(scope="module")
+def tensor_b():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    n = 160
+    x = torch.arange(n, dtype=torch.float64, device="cuda") / (n - 1)
+    x2 = x * x
+    # C-contiguous (i4, i3, i2, i1): i1 fastest, the library's flat order
+    s = x2.view(n, 1, 1, 1) + x2.view(1, n, 1, 1) + x2.view(1, 1, n, 1) + x2.view(1, 1, 1, n)
+    b = torch.sin(torch.sqrt(s)).reshape(-1)
+    del s
+    yield b
+    del b
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("sweep,variant", [("L2R", "ULV"), ("R2L", "URV")])
+def test_example2_table_beps_ranks(tensor_b, sweep, variant):
+    dims = [160] * 4
+    norm_b = float(torch.linalg.vector_norm(tensor_b))
+    for eps, svd_ranks in _table_rows():
+        cores, rep = T.tt_utv_decompose(tensor_b, dims, eps=eps, sweep=sweep, variant=variant, q=1, oversample=8,
+                                        exact_delta=True)
+        want = svd_ranks if sweep == "L2R" else svd_ranks[::-1]
+        assert rep["ranks"] == [1] + want + [1], (eps, rep["ranks"])
+        rec = T.tt_reconstruct(cores)
+        err = float(torch.linalg.vector_norm(rec - tensor_b))
+        del rec
+        assert err <= eps * norm_b
+        assert err <= rep["err_bound"] * (1 + 1e-6)
