@@ -509,3 +509,125 @@ def completion_step(cores, idx, vals):
     den = float(jg @ jg)
     alpha = float(e @ jg) / den if den > 0 else 0.0
     return [c - alpha * gk for c, gk in zip(cores, g)], f, alpha
+
+
+# --------------------------------------------------------------------------
+# Riemannian gradient descent for completion (Sec. 4.3, "MRI data
+# completion"): the gradient of f on the manifold of trains of fixed ranks
+# (the Euclidean gradient projected onto the tangent space at the current
+# train), a step along it with the exact minimiser of f on that line, and a
+# fixed-rank TT-UTV of the stepped tensor as the retraction.
+def _left_unfold(g):
+    r0, n, r1 = g.shape
+    return g.reshape(r0 * n, r1, order="F")
+
+
+def left_orthogonalize(cores):
+    """The same train with cores 1..d-1 left-orthogonal (Def. 2.2): QR of
+    each left unfolding, left to right, the triangular factor pushed into
+    the next core.  Ranks must satisfy r_k <= r_{k-1} I_k."""
+    out = [np.array(c, dtype=np.float64) for c in cores]
+    for k in range(len(out) - 1):
+        r0, n, r1 = out[k].shape
+        assert r1 <= r0 * n, "rank above what the left unfolding allows"
+        Q, R = np.linalg.qr(_left_unfold(out[k]))
+        out[k] = Q.reshape(r0, n, r1, order="F")
+        out[k + 1] = np.einsum("ab,bjc->ajc", R, out[k + 1])
+    return out
+
+
+def right_orthogonalize(cores):
+    """The same train with cores 2..d right-orthogonal (Def. 2.2): QR of the
+    transposed right unfoldings, right to left."""
+    out = [np.array(c, dtype=np.float64) for c in cores]
+    for k in range(len(out) - 1, 0, -1):
+        r0, n, r1 = out[k].shape
+        assert r0 <= n * r1, "rank above what the right unfolding allows"
+        Q, R = np.linalg.qr(out[k].reshape(r0, n * r1, order="F").T)     # G^T = Q R, G = R^T Q^T
+        out[k] = Q.T.reshape(r0, n, r1, order="F")
+        out[k - 1] = np.einsum("ajb,cb->ajc", out[k - 1], R)
+    return out
+
+
+def tt_sample_grad_mixed(left_cores, right_cores, idx, w):
+    """dL/dC_k of L = sum_s w_s (L_1..L_{k-1} C_k R_{k+1}..R_d)[idx_s] for every
+    k: the gradient of the sampled entries at the mixed-canonical point k,
+    with the left interface products from left_cores and the right ones
+    from right_cores (two forms of one train)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    d = len(left_cores)
+    N = idx.shape[0]
+    left = [np.ones((N, 1))]
+    for k in range(d - 1):
+        left.append(np.einsum("na,anb->nb", left[-1], left_cores[k][:, idx[:, k], :]))
+    right = [np.ones((N, 1))]
+    for k in range(d - 1, 0, -1):
+        right.append(np.einsum("anb,nb->na", right_cores[k][:, idx[:, k], :], right[-1]))
+    right = right[::-1]
+    grads = []
+    for k in range(d):
+        g = np.zeros_like(left_cores[k])
+        contrib = w[:, None, None] * left[k][:, :, None] * right[k][:, None, :]
+        np.add.at(g, (slice(None), idx[:, k], slice(None)), np.transpose(contrib, (1, 0, 2)))
+        grads.append(g)
+    return grads
+
+
+def riemannian_gradient(cores, idx, z):
+    """Projection onto the tangent space at the train X of the (sampled)
+    Euclidean gradient Z = sum_s z_s e_{idx_s}.  With left- and
+    right-orthogonal forms U, V of X, the tangent vector is
+    xi = sum_k U_1..U_{k-1} dC_k V_{k+1}..V_d, where dC_k = (I - U_k U_k^T) G_k
+    on the left unfoldings for k < d, dC_d = G_d, and G_k is the gradient of
+    <Z, .> at the mixed-canonical point k.  Returns (U, V, dC)."""
+    U = left_orthogonalize(cores)
+    V = right_orthogonalize(cores)
+    G = tt_sample_grad_mixed(U, V, idx, z)
+    dC = []
+    for k in range(len(cores) - 1):
+        u, g = _left_unfold(U[k]), _left_unfold(G[k])
+        dC.append((g - u @ (u.T @ g)).reshape(G[k].shape, order="F"))
+    dC.append(G[-1])
+    return U, V, dC
+
+
+def tangent_train(U, V, dC, t=1.0, base=False):
+    """Cores (interior ranks 2 r_k) of t*xi, or of X + t*xi with base=True,
+    where xi = sum_k U_<k dC_k V_>k and X = U_1 ... U_d: first core
+    [t dC_1, U_1], interior cores [[V_k, 0], [t dC_k, U_k]], last core
+    [[V_d], [t dC_d (+ U_d)]]."""
+    d = len(U)
+    W = []
+    for k in range(d):
+        if k == 0:
+            W.append(np.concatenate([t * dC[0], U[0]], axis=2))
+        elif k < d - 1:
+            r0, n, r1 = U[k].shape
+            blk = np.zeros((2 * r0, n, 2 * r1))
+            blk[:r0, :, :r1] = V[k]
+            blk[r0:, :, :r1] = t * dC[k]
+            blk[r0:, :, r1:] = U[k]
+            W.append(blk)
+        else:
+            last = t * dC[k] + (U[k] if base else 0.0)
+            W.append(np.concatenate([V[k], last], axis=0))
+    return W
+
+
+def rgrad_step(cores, idx, vals, ranks, q=1, p=8, seed=0):
+    """One Riemannian gradient step for f = 1/2 sum_s (X[idx_s] - m_s)^2:
+    z = X[idx] - m, xi = the Riemannian gradient, alpha = <P xi, z> / ||P xi||^2
+    (P: sampling at idx) the exact minimiser of f(X - alpha xi), then the
+    retraction: TT-ULV left to right at the fixed ranks of the full tensor
+    X - alpha xi.  Returns (new cores, f before the step, alpha)."""
+    z = tt_sample(cores, idx) - np.asarray(vals, dtype=np.float64)
+    f = 0.5 * float(z @ z)
+    U, V, dC = riemannian_gradient(cores, idx, z)
+    pxi = tt_sample(tangent_train(U, V, dC), idx)
+    den = float(pxi @ pxi)
+    alpha = float(pxi @ z) / den if den > 0 else 0.0
+    xhat = tt_reconstruct(tangent_train(U, V, dC, t=-alpha, base=True))
+    dims = [int(c.shape[1]) for c in cores]
+    new, _ = tt_utv(xhat, dims, ranks=list(ranks), sweep="L2R", variant="ULV", q=q, p=p, seed=seed)
+    return new, f, alpha
