@@ -181,6 +181,18 @@ int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks,
                        const double* const* cores, const int64_t* idx, int64_t N,
                        const double* gout, double* const* gcores, void* stream);
 
+/* The same gradient taken at the mixed-canonical points of one train, the
+ * ingredient of its Riemannian gradient (Sec. 4.3, RGrad for completion):
+ * gcores[k] = dL/dC_k of L = sum_s gout[s] * (L_1..L_{k-1} C_k R_{k+1}..R_d)[idx_s],
+ * where L_j = left_cores[j] (left-orthogonal form) and R_j = right_cores[j]
+ * (right-orthogonal form of the same train, same ranks); with left_cores ==
+ * right_cores it is tt_sample_backward.  Same layouts, checks and stream
+ * behaviour as tt_sample_backward. */
+int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks,
+                             const double* const* left_cores, const double* const* right_cores,
+                             const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
+                             void* stream);
+
 const char* tt_last_error(void);
 
 #ifdef __cplusplus

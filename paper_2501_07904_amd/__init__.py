@@ -21,7 +21,7 @@ SWEEPS = {"L2R": 0, "R2L": 1}
 VARIANTS = {"ULV": 0, "URV": 1, "SVD": 2}
 DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose",
-           "tt_reconstruct_workspace", "tt_reconstruct", "tt_sample", "tt_sample_backward",
+           "tt_reconstruct_workspace", "tt_reconstruct", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed",
            "tt_last_error", "tt_kernel_class_name"]
 
 
@@ -85,8 +85,10 @@ def load_library(path=LIB_PATH):
     lib.tt_sample.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp, vp]
     lib.tt_sample_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp,
                                        ctypes.POINTER(vp), vp]
+    lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                             ctypes.c_int64, vp, ctypes.POINTER(vp), vp]
     for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_reconstruct_workspace",
-                 "tt_reconstruct", "tt_sample", "tt_sample_backward"):
+                 "tt_reconstruct", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -263,6 +265,25 @@ def tt_sample_backward(cores, idx, gout, stream=None):
     gflat = [torch.empty_like(b) for b in bufs]
     _check(lib.tt_sample_backward(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()),
                                   N, ctypes.c_void_p(gout.data_ptr()), _ptrs(gflat), _stream(stream)))
+    return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
+
+
+def tt_sample_backward_mixed(left_cores, right_cores, idx, gout, stream=None):
+    """Core gradients of sum_s gout[s] * A_TT[idx_s] at the mixed-canonical
+    points: the interfaces left of core k from left_cores, right of it from
+    right_cores (two forms of one train with equal ranks)."""
+    lib = load_library()
+    dims, ranks = _train_shape(left_cores)
+    if _train_shape(right_cores) != (dims, ranks):
+        raise ValueError("left and right cores must describe trains of the same shape and ranks")
+    idx = idx.contiguous().to(torch.int64)
+    gout = gout.contiguous().to(torch.float64)
+    N = idx.shape[0]
+    lb, rb = _core_buffers(left_cores), _core_buffers(right_cores)
+    gflat = [torch.empty_like(b) for b in lb]
+    _check(lib.tt_sample_backward_mixed(len(dims), _i64(dims), _i64(ranks), _ptrs(lb), _ptrs(rb),
+                                        ctypes.c_void_p(idx.data_ptr()), N, ctypes.c_void_p(gout.data_ptr()),
+                                        _ptrs(gflat), _stream(stream)))
     return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
 
 

@@ -1,5 +1,18 @@
 """Masked tensor completion on TT cores, started from a TT-UTV decomposition.
 
+Two iterations are provided.  `completion_step`: gradient descent on the
+cores (below).  `rgrad_step`: Riemannian gradient descent on the manifold of
+trains of fixed ranks with TT-UTV as the retraction (Sec. 4.3): the sampled
+Euclidean gradient is projected onto the tangent space at the current train
+(core gradients at the mixed-canonical points from the tt_sample_backward_mixed
+kernel, then a projection of each left unfolding), the step
+X - alpha xi uses the exact minimiser alpha of f on that line, and the
+retraction is a fixed-rank TT-ULV (left to right) of the full stepped tensor,
+which also gives the left-orthogonal form for the next step; the
+right-orthogonal form is a fixed-rank TT-URV (right to left) of the full
+current tensor, which represents it exactly.
+
+
 The observed entries M[idx_s] (s = 1..N) of an order-d tensor are fitted by
 gradient descent on the cores of f = 1/2 sum_s (A_TT[idx_s] - M[idx_s])^2.
 Sampled values and core gradients come from the library's tt_sample and
@@ -12,7 +25,7 @@ fraction) (a spectral initialisation).
 """
 import torch
 
-from . import tt_sample, tt_sample_backward, tt_utv_decompose
+from . import tt_reconstruct, tt_sample, tt_sample_backward, tt_sample_backward_mixed, tt_utv_decompose
 
 
 def flat_index(idx, dims):
@@ -58,5 +71,85 @@ def complete(dims, idx, vals, ranks, steps, cores=None, seed=0):
     hist = []
     for _ in range(steps):
         cores, f, _ = completion_step(cores, idx, vals)
+        hist.append(f)
+    return cores, hist
+
+
+def _left_unfold(g):
+    """Left unfolding (r0 I) x r1 of a logical (r0, I, r1) core, r0 index fastest."""
+    r0, n, r1 = g.shape
+    return g.permute(1, 0, 2).reshape(n * r0, r1)
+
+
+def _fold_left(m, r0, n, r1):
+    return m.reshape(n, r0, r1).permute(1, 0, 2)
+
+
+def _tangent_train(U, V, dC, t, base):
+    """Cores of t*xi (base False) or X + t*xi (base True), xi = sum_k U_<k dC_k V_>k,
+    X = U_1..U_d: first core [t dC_1, U_1], interior [[V_k, 0], [t dC_k, U_k]],
+    last [[V_d], [t dC_d (+ U_d)]]."""
+    d = len(U)
+    W = []
+    for k in range(d):
+        if k == 0:
+            W.append(torch.cat([t * dC[0], U[0]], dim=2))
+        elif k < d - 1:
+            r0, n, r1 = U[k].shape
+            blk = torch.zeros((2 * r0, n, 2 * r1), dtype=torch.float64, device=U[k].device)
+            blk[:r0, :, :r1] = V[k]
+            blk[r0:, :, :r1] = t * dC[k]
+            blk[r0:, :, r1:] = U[k]
+            W.append(blk)
+        else:
+            last = t * dC[k] + U[k] if base else t * dC[k]
+            W.append(torch.cat([V[k], last], dim=0))
+    return W
+
+
+def rgrad_step(cores, idx, vals, q=1, oversample=8, seed=0, left_orthogonal=False):
+    """One Riemannian gradient step (TT-UTV retraction) for
+    f = 1/2 sum_s (X[idx_s] - m_s)^2 at the train `cores`.  With
+    left_orthogonal the cores are already the left-orthogonal form (as
+    returned by this function).  Returns (new left-orthogonal cores, f before
+    the step, alpha)."""
+    dims = [int(g.shape[1]) for g in cores]
+    ranks = [int(g.shape[2]) for g in cores[:-1]]
+    kw = dict(q=q, oversample=oversample, seed=seed)
+    full = tt_reconstruct(cores)
+    if left_orthogonal:
+        U = [g.to(torch.float64) for g in cores]
+    else:
+        U, _ = tt_utv_decompose(full, dims, ranks=ranks, sweep="L2R", variant="ULV", **kw)
+        U = [g.clone() for g in U]
+    V, _ = tt_utv_decompose(full, dims, ranks=ranks, sweep="R2L", variant="URV", **kw)
+    V = [g.clone() for g in V]
+    del full
+    z = tt_sample(U, idx) - vals.to(torch.float64)
+    f = 0.5 * float(torch.dot(z, z))
+    G = tt_sample_backward_mixed(U, V, idx, z)
+    dC = []
+    for k in range(len(dims) - 1):
+        u, g = _left_unfold(U[k]), _left_unfold(G[k])
+        dC.append(_fold_left(g - u @ (u.T @ g), *U[k].shape))
+    dC.append(G[-1])
+    pxi = tt_sample(_tangent_train(U, V, dC, 1.0, False), idx)
+    den = float(torch.dot(pxi, pxi))
+    alpha = float(torch.dot(pxi, z)) / den if den > 0 else 0.0
+    xhat = tt_reconstruct(_tangent_train(U, V, dC, -alpha, True))
+    new, _ = tt_utv_decompose(xhat, dims, ranks=ranks, sweep="L2R", variant="ULV", **kw)
+    return [g.clone() for g in new], f, alpha
+
+
+def complete_rgrad(dims, idx, vals, ranks, steps, cores=None, seed=0):
+    """Spectral initialisation (unless cores are given) and `steps` Riemannian
+    gradient steps; returns (left-orthogonal cores, list of f per step)."""
+    if cores is None:
+        cores, _ = spectral_init(dims, idx, vals, ranks, seed=seed)
+    hist = []
+    left = False
+    for _ in range(steps):
+        cores, f, _ = rgrad_step(cores, idx, vals, seed=seed, left_orthogonal=left)
+        left = True
         hist.append(f)
     return cores, hist

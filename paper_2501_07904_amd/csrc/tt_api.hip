@@ -789,16 +789,33 @@ int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const double* co
   return TT_OK;
 }
 
-int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
-                       const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
-                       void* stream) {
+static int sample_bwd_checks(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                             const int64_t* idx, int64_t N, const double* gout, double* const* gcores) {
   if (d < 2 || d > TT_MAX_D || !dims || !ranks || !cores || !gcores) return fail(TT_EINVAL, "bad train description");
   for (int k = 0; k <= d; ++k)
     if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
   if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
   if (N < 0) return fail(TT_EINVAL, "N < 0");
   if (N > 0 && (!idx || !gout)) return fail(TT_EINVAL, "idx/gout is NULL");
-  HIP_OK(launch_sample_bwd(d, dims, ranks, cores, idx, N, gout, gcores, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                       const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
+                       void* stream) {
+  const int rc = sample_bwd_checks(d, dims, ranks, cores, idx, N, gout, gcores);
+  if (rc != TT_OK) return rc;
+  HIP_OK(launch_sample_bwd(d, dims, ranks, cores, nullptr, idx, N, gout, gcores, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks, const double* const* left_cores,
+                             const double* const* right_cores, const int64_t* idx, int64_t N, const double* gout,
+                             double* const* gcores, void* stream) {
+  const int rc = sample_bwd_checks(d, dims, ranks, left_cores, idx, N, gout, gcores);
+  if (rc != TT_OK) return rc;
+  if (!right_cores) return fail(TT_EINVAL, "right_cores is NULL");
+  HIP_OK(launch_sample_bwd(d, dims, ranks, left_cores, right_cores, idx, N, gout, gcores, (hipStream_t)stream));
   return TT_OK;
 }
 

@@ -127,8 +127,10 @@ hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f
 hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
                          const double* const* cores, const int64_t* idx, int64_t N, double* out,
                          hipStream_t st);
+// right_cores: NULL for the gradient of the train itself; else the right
+// interface products come from right_cores (a second form of the same train).
 hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
-                             const double* const* cores, const int64_t* idx, int64_t N,
-                             const double* gout, double* const* gcores, hipStream_t st);
+                             const double* const* cores, const double* const* right_cores, const int64_t* idx,
+                             int64_t N, const double* gout, double* const* gcores, hipStream_t st);
 
 }  // namespace ttutv

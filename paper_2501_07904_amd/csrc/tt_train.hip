@@ -102,7 +102,10 @@ __global__ __launch_bounds__(kThreads) void k_sample(TrainDesc D, const int64_t*
 // One wave per sample: the right interface products rho_c (c = d-1..0) are
 // recomputed into LDS, then a left-to-right pass forms lambda_c and scatters
 // gout_s * lambda_c[a] * rho_c[b] into dG_c[a, i_c, b].
-__global__ __launch_bounds__(kThreads) void k_sample_bwd(TrainDesc D, const int64_t* __restrict__ idx,
+// Left interface products from the cores of D, right ones from those of DR
+// (the same train for the plain gradient; the left- and right-orthogonal
+// forms of one train for the gradient at the mixed-canonical points).
+__global__ __launch_bounds__(kThreads) void k_sample_bwd(TrainDesc D, TrainDesc DR, const int64_t* __restrict__ idx,
                                                          int64_t N, const double* __restrict__ gout,
                                                          GradDesc G) {
   __shared__ double rho[kThreads / 64][TT_MAX_D_INTERNAL][64];
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_sample_bwd(TrainDesc D, const int6
       double nr = 0.0;
       for (int b = 0; b < rb; ++b) {
         const double rbv = __shfl(r, b, 64);
-        if (lane < ra) nr = fma(core_at(D, c + 1, lane, i, b), rbv, nr);
+        if (lane < ra) nr = fma(core_at(DR, c + 1, lane, i, b), rbv, nr);
       }
       r = nr;
       rho[wl][c][lane] = r;
@@ -208,18 +211,19 @@ hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
 }
 
 hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
-                             const double* const* cores, const int64_t* idx, int64_t N,
-                             const double* gout, double* const* gcores, hipStream_t st) {
-  TrainDesc D;
+                             const double* const* cores, const double* const* right_cores, const int64_t* idx,
+                             int64_t N, const double* gout, double* const* gcores, hipStream_t st) {
+  TrainDesc D, DR;
   GradDesc G;
   if (!fill_desc(D, d, dims, ranks, cores)) return hipErrorInvalidValue;
+  if (!fill_desc(DR, d, dims, ranks, right_cores ? right_cores : cores)) return hipErrorInvalidValue;
   for (int k = 0; k < d; ++k) G.cores[k] = gcores[k];
   for (int k = 0; k < d; ++k) {
     const int64_t sz = ranks[k] * dims[k] * ranks[k + 1];
     TT_LAUNCH(k_fill_zero, dim3((unsigned)((sz + 255) / 256)), dim3(256), 0, st, gcores[k], sz);
   }
   if (N > 0)
-    TT_LAUNCH(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, idx, N, gout, G);
+    TT_LAUNCH(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, DR, idx, N, gout, G);
   return hipGetLastError();
 }
 
