@@ -544,11 +544,13 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
         T[i + j * kLd] = s;
       }
       __syncthreads();
-      // n <= 64: at most 4 rows per thread
+      // n <= 64: at most 4 rows per thread; sK (free until K is formed) holds
+      // the reflectors for the barrier-free formation of Q
+      static_assert(kCMax * kLd >= 4 * kThreads, "sK holds 4 * kThreads doubles");
       switch (reg_group_width(L)) {
-        case 16: householder_reg<4, 16>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
-        case 32: householder_reg<4, 32>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
-        default: householder_reg<4, 64>(T, 1, kLd, T, 1, kLd, n, L, vbuf); break;
+        case 16: householder_reg<4, 16>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
+        case 32: householder_reg<4, 32>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
+        default: householder_reg<4, 64>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
       }
       double* tmp = X; X = T; T = tmp;
     }
