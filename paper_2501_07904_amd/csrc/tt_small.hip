@@ -289,71 +289,95 @@ __device__ __host__ __forceinline__ int reg_rows(int n, int c) {
 // --------------------------------------------------------------------------
 // Symmetric eigen-decomposition of K (L x L in LDS, ld kLd) by cyclic Jacobi
 // with the round-robin parallel ordering: each round rotates L/2 disjoint
-// pairs, and K <- J^T K J is applied as independent 2 x 2 block updates
-// (two barriers per round).  Pairs whose off-diagonal entry is below the
-// rounding floor are skipped; the iteration stops after a sweep without a
-// rotation.  On return lam[0..L) holds the eigenvalues in descending order
-// and perm[a] the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
-__device__ __forceinline__ void rr_pair(int p, int round, int Le, int* a, int* b) {
-  // round < Le-1 and p < Le/2, so each sum is below 2(Le-1): one conditional subtraction
-  const int m = Le - 1;
-  int x, y;
-  if (p == 0) {
-    x = 0;
-    y = 1 + round;
+// pairs, and K <- J^T K J is applied as independent 2 x 2 block updates (one
+// barrier per round).  Pairs whose off-diagonal entry is below the rounding
+// floor are skipped; the iteration stops after a sweep without a rotation.
+// On return lam[0..L) holds the eigenvalues in descending order and perm[a]
+// the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
+//
+// Pair p of round r (0 <= r < m = Le - 1, Le = L rounded up to even) holds
+// the indices x = 0, y = 1 + r for p = 0 and x = 1 + (p + r) mod m,
+// y = 1 + (m - p + r) mod m otherwise.  From one round to the next an index
+// moves by at most one pair position: the x member of pair p + 1 becomes the
+// x member of pair p, the y member of pair p - 1 the y member of pair p, and
+// the ends turn around (pair 0's y comes from pair 1's x, pair 1's y from
+// pair 0's y, the last pair's x from its own y).
+__device__ __forceinline__ void pair_labels(int p, int r, int m, int* x, int* y) {
+  // r < m and p <= m / 2, so each sum is below 2m: one conditional subtraction
+  int u = p + r;
+  if (u >= m) u -= m;
+  int v = m - p + r;
+  if (v >= m) v -= m;
+  *x = p == 0 ? 0 : 1 + u;
+  *y = p == 0 ? 1 + r : 1 + v;
+}
+
+// Position (pair, member) in the previous round of member s of pair p.
+__device__ __forceinline__ void pair_source(int p, int s, int h, int* po, int* so) {
+  if (h == 1) { *po = p; *so = s; return; }
+  if (p == 0) { *po = s; *so = 0; return; }
+  if (s == 0) {
+    if (p < h - 1) { *po = p + 1; *so = 0; }
+    else { *po = h - 1; *so = 1; }
   } else {
-    int u = p + round;
-    if (u >= m) u -= m;
-    int v = m - p + round;
-    if (v >= m) v -= m;
-    x = 1 + u;
-    y = 1 + v;
+    if (p == 1) { *po = 0; *so = 1; }
+    else { *po = p - 1; *so = 1; }
   }
-  *a = min(x, y);
-  *b = max(x, y);
 }
 
 // Rotation (cs, sn) of a pair with diagonal entries app, aqq and coupling
 // apq, zeroing apq; the identity when apq is below the rounding floor.
-// Branch-free, so that a thread evaluates its two pairs with overlapping
-// latency: tan(theta) t = 2 apq / (d + sign(d) sqrt(d^2 + 4 apq^2)),
-// d = aqq - app, |t| <= 1, from operands scaled to max(|d|, |2 apq|) ~ 1 (t is
-// scale invariant); reciprocal and reciprocal square roots by the hardware
-// estimate plus two Newton steps.  cs = 1/sqrt(1 + t^2) to working accuracy
-// keeps the rotation orthogonal; t itself need only be close to the exact
-// angle.  Every thread that evaluates a pair does so from the same operands
-// with the same operations, so all copies agree bitwise.
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+// With d = aqq - app and w = 2 apq scaled by the same power of two to
+// max(|d|, |w|) in [1/2, 1) (exact; the angle is scale invariant) and
+// h = sqrt(d^2 + w^2), D = |d| + h:  tan(theta) = sign(d) w / D (the root of
+// magnitude at most 1), so cs = D / sqrt(D^2 + w^2) and
+// sn = sign(d) w / sqrt(D^2 + w^2), with no division.  Both square roots come
+// from the hardware reciprocal-square-root estimate refined by two coupled
+// (Goldschmidt) steps that carry sqrt(x) and 1/(2 sqrt(x)) together; cs and
+// sn share the same 1/sqrt, so the rotation is orthogonal to working
+// accuracy.  Every thread that evaluates a pair does so from the same
+// operands with the same operations, so all copies agree bitwise.
+__device__ __forceinline__ void sqrt_rsq(double x, double* sq, double* rs) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, hf = 0.5 * y;
+  double r = fma(-g, hf, 0.5);
+  g = fma(g, r, g);
+  hf = fma(hf, r, hf);
+  r = fma(-g, hf, 0.5);
+  *sq = fma(g, r, g);
+  *rs = 2.0 * fma(hf, r, hf);
 }
 
-__device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, double abs_floor, double* cs,
+__device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double abs_floor, double* cs,
                                            double* sn) {
   const bool on = fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(app * aqq);
   const double dd = aqq - app, tw = 2.0 * apq;
-  const double sc = __builtin_amdgcn_rcp(on ? fmax(fabs(dd), fabs(tw)) : 1.0);
-  const double d1 = dd * sc, t1 = tw * sc;
-  const double d2 = fma(d1, d1, t1 * t1);   // in [1, 2] when on
-  const double rr = d2 * rsq_nr(d2);
-  const double den = d1 >= 0.0 ? d1 + rr : d1 - rr;   // |den| >= 1
-  double q = __builtin_amdgcn_rcp(den);
-  q = fma(q, fma(-den, q, 1.0), q);
-  q = fma(q, fma(-den, q, 1.0), q);
-  const double tt = t1 * q;
-  const double c = rsq_nr(fma(tt, tt, 1.0));
-  *cs = on ? c : 1.0;
-  *sn = on ? tt * c : 0.0;
-  return on;
+  int ex;
+  (void)frexp(fmax(fabs(dd), fabs(tw)), &ex);
+  const double d1 = ldexp(dd, -ex), w1 = ldexp(tw, -ex);
+  const double w2 = w1 * w1;
+  double hq, unused;
+  sqrt_rsq(fma(d1, d1, w2), &hq, &unused);
+  const double den = fabs(d1) + hq;   // in [1/2, 1 + sqrt(2))
+  double rn, y;
+  sqrt_rsq(fma(den, den, w2), &rn, &y);
+  (void)rn;
+  (void)unused;
+  *cs = on ? den * y : 1.0;
+  *sn = on ? (d1 >= 0.0 ? w1 : -w1) * y : 0.0;
 }
 
-// K is L x L in LDS (ld kLd); K2 is scratch of the same size: the rounds
-// alternate between the two, so that every thread reads the entries of the
-// previous round while others write the next.  A round is one barrier: the
-// thread of block (P, Q) evaluates the rotations of pairs P and Q itself,
-// writes the 2 x 2 block of J^T K J and applies the rotation of Q to the
-// 2 x 2 block (rows of P, columns of Q) of Z.
+// K is L x L in LDS (ld kLd); K2 is scratch of the same size.  During the
+// iteration K is held by pair position rather than by index: entry (i, j),
+// with i member si of pair Pi and j member sj of pair Pj in the current round,
+// sits in plane si + 2 sj at Pi + h Pj (four planes of h x h, h = Le / 2).
+// The thread of block (P, Q) writes its four entries at P + h Q and, the next
+// round, reads them from where the pair movement above put them: offsets
+// fixed for the whole solve, and the lanes of a wave touch nearly consecutive
+// words of each plane (an index-addressed layout has 4- to 8-way LDS bank
+// conflicts on the same accesses).  The rounds alternate between K2 and K.
+// Z stays index-addressed; the thread of block (P, Q) rotates rows 2P, 2P + 1
+// of the columns of pair Q.
 template <int NT>
 __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int L, double* lam, int* perm,
                                           double* sh, int* flag) {
@@ -361,16 +385,24 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
   // the pair holding the padding index then always gets the identity rotation
   const int t = threadIdx.x;
   const int Le = L + (L & 1);
-  const int h = Le / 2;
+  const int h = Le / 2, m = Le - 1, hh = h * h;
   for (int e = t; e < Le * Le; e += NT) {
     const int i = e % Le, j = e / Le;
     Z[i + j * kLd] = (i == j && i < L) ? 1.0 : 0.0;
-    if (i >= L || j >= L) K[i + j * kLd] = 0.0;
   }
   double dpart = 0.0;
   for (int i = t; i < L; i += NT) dpart = fmax(dpart, fabs(K[i + i * kLd]));
   for (int o = 32; o > 0; o >>= 1) dpart = fmax(dpart, __shfl_xor(dpart, o, 64));
   if ((t & 63) == 0) sh[t >> 6] = dpart;
+  // perm serves as the index -> position table (2 pair + member) of the layout
+  // written by the last round of a sweep (round m - 1), which is also the
+  // layout the first round reads
+  if (t < h) {
+    int x, y;
+    pair_labels(t, m - 1 > 0 ? m - 1 : 0, m, &x, &y);
+    perm[x] = 2 * t;
+    perm[y] = 2 * t + 1;
+  }
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < NT / 64; ++i) dmax = fmax(dmax, sh[i]);
@@ -379,74 +411,108 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
   // floors were measured to cost eigenvector accuracy of small, well
   // separated eigenvalues)
   const double abs_floor = 1e-300 + 1e-15 * dmax;
+  for (int e = t; e < Le * Le; e += NT) {
+    const int i = e % Le, j = e / Le;
+    const int pi = perm[i], pj = perm[j];
+    K2[((pi & 1) + 2 * (pj & 1)) * hh + (pi >> 1) + h * (pj >> 1)] = (i < L && j < L) ? K[i + j * kLd] : 0.0;
+  }
   __syncthreads();
-  double* Kc = K;
-  double* Kn = K2;
+  double* Kc = K2;
+  double* Kn = K;
   int sweeps = 0;
   static_assert(NT >= (kCMax / 2) * (kCMax / 2), "one 2 x 2 block per thread");
-  const bool blk = t < h * h;            // this thread's block (P, Q), fixed for the whole solve
-  const int P = blk ? t % h : 0, Q = blk ? t / h : 0;
+  // lane t evaluates the rotation of pair P = t mod h (every lane of a wave
+  // that holds a block, so that each wave has all h rotations: 64 >= h) and
+  // takes the rotation of its column pair Q from a lane of its own wave
+  const bool blk = t < hh;            // this thread's block (P, Q), fixed for the whole solve
+  const bool rot_lane = t < ((hh + 63) & ~63);
+  const int P = t % h, Q = blk ? t / h : 0;
+  const int wbase = t & ~63;
+  const int srcQ = wbase + (Q - wbase % h + h) % h;
+  int Pa, sa, Pb, sb, Qa, ta, Qb, tb;
+  pair_source(P, 0, h, &Pa, &sa);
+  pair_source(P, 1, h, &Pb, &sb);
+  pair_source(Q, 0, h, &Qa, &ta);
+  pair_source(Q, 1, h, &Qb, &tb);
+  const int o_pa = 3 * sa * hh + Pa * (1 + h), o_pb = 3 * sb * hh + Pb * (1 + h);
+  const int o_pab = (sa + 2 * sb) * hh + Pa + h * Pb;
+  const int o_aa = (sa + 2 * ta) * hh + Pa + h * Qa, o_ab = (sa + 2 * tb) * hh + Pa + h * Qb;
+  const int o_ba = (sb + 2 * ta) * hh + Pb + h * Qa, o_bb = (sb + 2 * tb) * hh + Pb + h * Qb;
+  const int own = P + h * Q;
   for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
     // converged when no pair would be rotated: exactly the sweep that would
     // follow applies no rotation, so it is not run
     if (t == 0) *flag = 0;
     __syncthreads();
-    for (int e = t; e < L * L; e += NT) {
-      const int i = e % L, j = e / L;
-      if (i < j) {
-        const double apq = Kc[i + j * kLd];
-        if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(Kc[i + i * kLd] * Kc[j + j * kLd])) *flag = 1;
-      }
+    for (int e = t; e < 4 * hh; e += NT) {
+      const int pl = e / hh, idx = e - pl * hh;
+      const int Pi = idx % h, Pj = idx / h;
+      if (Pi == Pj && (pl == 0 || pl == 3)) continue;   // a diagonal entry
+      const double apq = Kc[e];
+      const double di = Kc[3 * (pl & 1) * hh + Pi * (1 + h)], dj = Kc[3 * (pl >> 1) * hh + Pj * (1 + h)];
+      if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(di * dj)) *flag = 1;
     }
     __syncthreads();
     const int any = *flag;
     __syncthreads();
     if (!any) break;
     sweeps = sweep + 1;
-    for (int round = 0; round < Le - 1; ++round) {
-      if (blk) {
-        int aP, bP, aQ, bQ;
-        rr_pair(P, round, Le, &aP, &bP);
-        rr_pair(Q, round, Le, &aQ, &bQ);
+    for (int round = 0; round < m; ++round) {
+      if (rot_lane) {
         // every operand of the thread first (one LDS round trip), then the math
-        const double pa = Kc[aP + aP * kLd], pb = Kc[bP + bP * kLd], pab = Kc[aP + bP * kLd];
-        const double qa = Kc[aQ + aQ * kLd], qb = Kc[bQ + bQ * kLd], qab = Kc[aQ + bQ * kLd];
-        const double kaa = Kc[aP + aQ * kLd], kab = Kc[aP + bQ * kLd];
-        const double kba = Kc[bP + aQ * kLd], kbb = Kc[bP + bQ * kLd];
-        const double zaa = Z[aP + aQ * kLd], zab = Z[aP + bQ * kLd];
-        const double zba = Z[bP + aQ * kLd], zbb = Z[bP + bQ * kLd];
-        double cP, sP, cQ, sQ;
-        const bool rot = jacobi_rot(pa, pb, pab, abs_floor, &cP, &sP);
-        jacobi_rot(qa, qb, qab, abs_floor, &cQ, &sQ);
-        const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
-        const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
-        Kn[aP + aQ * kLd] = cP * raa - sP * rba;
-        Kn[aP + bQ * kLd] = cP * rab - sP * rbb;
-        Kn[bP + aQ * kLd] = sP * raa + cP * rba;
-        Kn[bP + bQ * kLd] = sP * rab + cP * rbb;
-        // Z <- Z J on rows {aP, bP} and columns {aQ, bQ}
-        Z[aP + aQ * kLd] = cQ * zaa - sQ * zab;
-        Z[aP + bQ * kLd] = sQ * zaa + cQ * zab;
-        Z[bP + aQ * kLd] = cQ * zba - sQ * zbb;
-        Z[bP + bQ * kLd] = sQ * zba + cQ * zbb;
-        (void)rot;
+        const double pa = Kc[o_pa], pb = Kc[o_pb], pab = Kc[o_pab];
+        double kaa = 0.0, kab = 0.0, kba = 0.0, kbb = 0.0, z0a = 0.0, z0b = 0.0, z1a = 0.0, z1b = 0.0;
+        int xQ, yQ;
+        pair_labels(Q, round, m, &xQ, &yQ);
+        double* z0 = Z + 2 * P + xQ * kLd;
+        double* z1 = Z + 2 * P + yQ * kLd;
+        if (blk) {
+          kaa = Kc[o_aa]; kab = Kc[o_ab]; kba = Kc[o_ba]; kbb = Kc[o_bb];
+          z0a = z0[0]; z0b = z0[1]; z1a = z1[0]; z1b = z1[1];
+        }
+        double cP, sP;
+        jacobi_rot(pa, pb, pab, abs_floor, &cP, &sP);
+        const double cQ = __shfl(cP, srcQ, 64), sQ = __shfl(sP, srcQ, 64);
+        if (blk) {
+          const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
+          const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
+          Kn[own] = cP * raa - sP * rba;              // (x_P, x_Q)
+          Kn[hh + own] = sP * raa + cP * rba;         // (y_P, x_Q)
+          Kn[2 * hh + own] = cP * rab - sP * rbb;     // (x_P, y_Q)
+          Kn[3 * hh + own] = sP * rab + cP * rbb;     // (y_P, y_Q)
+          // Z <- Z J on rows 2P, 2P + 1 and the columns of pair Q
+          z0[0] = cQ * z0a - sQ * z1a;
+          z0[1] = cQ * z0b - sQ * z1b;
+          z1[0] = sQ * z0a + cQ * z1a;
+          z1[1] = sQ * z0b + cQ * z1b;
+        }
       }
       __syncthreads();
       double* tmp = Kc; Kc = Kn; Kn = tmp;
     }
   }
-  // descending order, ties by index
+  // descending order, ties by index; the diagonal is read through the
+  // position table before perm is overwritten
+  double v = 0.0;
   if (t < L) {
-    const double v = Kc[t + t * kLd];
-    int rank = 0;
-    for (int j = 0; j < L; ++j) {
-      const double w = Kc[j + j * kLd];
-      rank += (w > v) || (w == v && j < t);
-    }
-    perm[rank] = t;
+    const int pi = perm[t];
+    v = Kc[3 * (pi & 1) * hh + (pi >> 1) * (1 + h)];
   }
   __syncthreads();
-  if (t < L) lam[t] = Kc[perm[t] + perm[t] * kLd];
+  if (t < L) lam[t] = v;
+  __syncthreads();
+  int rank = 0;
+  if (t < L) {
+    for (int j = 0; j < L; ++j) {
+      const double w = lam[j];
+      rank += (w > v) || (w == v && j < t);
+    }
+  }
+  __syncthreads();
+  if (t < L) {
+    perm[rank] = t;
+    lam[rank] = v;
+  }
   __syncthreads();
   return sweeps;
 }
