@@ -46,6 +46,53 @@ __device__ __forceinline__ double group_sum(double v, int tpj) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// sqrt(x) and 1/sqrt(x) for x > 0: the hardware reciprocal-square-root
+// estimate refined by two coupled (Goldschmidt) steps carrying sqrt(x) and
+// 1/(2 sqrt(x)) together (each step squares the relative error).
+__device__ __forceinline__ void sqrt_rsq(double x, double* sq, double* rs) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, hf = 0.5 * y;
+  double r = fma(-g, hf, 0.5);
+  g = fma(g, r, g);
+  hf = fma(hf, r, hf);
+  r = fma(-g, hf, 0.5);
+  *sq = fma(g, r, g);
+  *rs = 2.0 * fma(hf, r, hf);
+}
+
+// Two group sums at once, their DPP steps interleaved (one reduction's latency).
+__device__ __forceinline__ void group_sum2(double* a, double* b, int tpj) {
+  double u = *a, v = *b;
+  u += dpp_mov<0xB1>(u);
+  v += dpp_mov<0xB1>(v);
+  u += dpp_mov<0x4E>(u);
+  v += dpp_mov<0x4E>(v);
+  u += dpp_mov<0x141>(u);
+  v += dpp_mov<0x141>(v);
+  u += dpp_mov<0x140>(u);
+  v += dpp_mov<0x140>(v);
+  if (tpj == 16) { *a = u; *b = v; return; }
+  const double u0 = readlane_d(u, 0), u1 = readlane_d(u, 16), u2 = readlane_d(u, 32), u3 = readlane_d(u, 48);
+  const double v0 = readlane_d(v, 0), v1 = readlane_d(v, 16), v2 = readlane_d(v, 32), v3 = readlane_d(v, 48);
+  if (tpj == 32) {
+    const bool hi = threadIdx.x & 32;
+    *a = hi ? u2 + u3 : u0 + u1;
+    *b = hi ? v2 + v3 : v0 + v1;
+    return;
+  }
+  *a = (u0 + u1) + (u2 + u3);
+  *b = (v0 + v1) + (v2 + v3);
+}
+
+// x . v over a thread's R rows: four partial sums (R is a multiple of 4).
+template <int R>
+__device__ __forceinline__ double dot_rows(const double* x, const double* v) {
+  double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < R; ++r) d[r & 3] = fma(v[r], x[r], d[r & 3]);
+  return (d[0] + d[1]) + (d[2] + d[3]);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = group_sum(v, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -140,34 +187,38 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
       const double* v = vbuf + ((k - 1) & 1) * NP + lane;
       const double tk = taus[k - 1];
       double vr[R];
-      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        vr[r] = v[TPJ * r];
-        if (r & 1) d1 = fma(vr[r], x[r], d1);
-        else d0 = fma(vr[r], x[r], d0);
-      }
-      const double f = tk * group_sum(d0 + d1, TPJ);
+      for (int r = 0; r < R; ++r) vr[r] = v[TPJ * r];
+      const double f = tk * group_sum(dot_rows<R>(x, vr), TPJ);
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
     }
     if (g == k) {
-      double sig = 0.0, alpha = 0.0;
+      double sg4[4] = {0.0, 0.0, 0.0, 0.0}, alpha = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = lane + TPJ * r;
-        sig = fma(i > k ? x[r] : 0.0, x[r], sig);
+        sg4[r & 3] = fma(i > k ? x[r] : 0.0, x[r], sg4[r & 3]);
         alpha = (i == k) ? x[r] : alpha;
       }
-      sig = group_sum(sig, TPJ);
-      alpha = group_sum(alpha, TPJ);   // one lane holds row k, the others add zero
+      double sig = (sg4[0] + sg4[1]) + (sg4[2] + sg4[3]);
+      group_sum2(&sig, &alpha, TPJ);   // one lane holds row k, the others add zero to alpha
       double tk = 0.0, sc = 0.0;
       my_diag = alpha;   // R(k, k): alpha when column k is already zero below row k, else beta
       if (sig > 0.0) {
-        const double mu = sqrt(fma(alpha, alpha, sig));
-        const double beta = alpha <= 0.0 ? mu : -mu;
-        tk = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
+        // mu = sqrt(alpha^2 + sig) and 1/mu together; beta = -sign(alpha) mu,
+        // tau = (beta - alpha) / beta, and the scale 1 / (alpha - beta), where
+        // |alpha - beta| = |alpha| + mu lies in [mu, 2 mu]: a reciprocal
+        // estimate refined by two Newton steps
+        double mu, rmu;
+        sqrt_rsq(fma(alpha, alpha, sig), &mu, &rmu);
+        const bool neg = alpha <= 0.0;
+        const double beta = neg ? mu : -mu;
+        tk = (beta - alpha) * (neg ? rmu : -rmu);
+        const double dn = alpha - beta;
+        double q = __builtin_amdgcn_rcp(dn);
+        q = fma(q, fma(-dn, q, 1.0), q);
+        sc = fma(q, fma(-dn, q, 1.0), q);
         my_diag = beta;
       }
       my_tau = tk;
@@ -216,14 +267,9 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
         const double* v = vall + k * NP + lane;
         const double tk = taus[k];
         double vr[R];
-        double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          vr[r] = v[TPJ * r];
-          if (r & 1) d1 = fma(vr[r], x[r], d1);
-          else d0 = fma(vr[r], x[r], d0);
-        }
-        const double f = tk * group_sum(d0 + d1, TPJ);
+        for (int r = 0; r < R; ++r) vr[r] = v[TPJ * r];
+        const double f = tk * group_sum(dot_rows<R>(x, vr), TPJ);
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
       }
@@ -246,14 +292,9 @@ __device__ __forceinline__ void householder_reg(const double* X, int64_t xi, int
       const double* v = vbuf + (k & 1) * NP + lane;
       const double tk = taus[k];
       double vr[R];
-      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        vr[r] = v[TPJ * r];
-        if (r & 1) d1 = fma(vr[r], x[r], d1);
-        else d0 = fma(vr[r], x[r], d0);
-      }
-      const double f = tk * group_sum(d0 + d1, TPJ);
+      for (int r = 0; r < R; ++r) vr[r] = v[TPJ * r];
+      const double f = tk * group_sum(dot_rows<R>(x, vr), TPJ);
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = fma(-f, vr[r], x[r]);
     } else if (g == k) {
@@ -337,16 +378,6 @@ __device__ __forceinline__ void pair_source(int p, int s, int h, int* po, int* s
 // sn share the same 1/sqrt, so the rotation is orthogonal to working
 // accuracy.  Every thread that evaluates a pair does so from the same
 // operands with the same operations, so all copies agree bitwise.
-__device__ __forceinline__ void sqrt_rsq(double x, double* sq, double* rs) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, hf = 0.5 * y;
-  double r = fma(-g, hf, 0.5);
-  g = fma(g, r, g);
-  hf = fma(hf, r, hf);
-  r = fma(-g, hf, 0.5);
-  *sq = fma(g, r, g);
-  *rs = 2.0 * fma(hf, r, hf);
-}
 
 __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double abs_floor, double* cs,
                                            double* sn) {
