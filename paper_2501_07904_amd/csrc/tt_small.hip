@@ -744,7 +744,7 @@ constexpr int kRRThreads = 1024;  // measured: 16 waves finish a Jacobi round fa
 
 __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restrict__ K,
                                                          const double* __restrict__ X, SolveArgs a) {
-  __shared__ double sK[kCMax * kLd];
+  __shared__ __align__(16) double sK[kCMax * kLd];
   __shared__ double sK2[kCMax * kLd];
   __shared__ double sZ[kCMax * kLd];
   __shared__ double lam[kCMax], sg[kCMax], sh[32];
@@ -768,12 +768,38 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
   }
   __syncthreads();
   const int r = sr;
-  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
-    const int i = (int)(e / r), c = (int)(e % r);
-    const int pc = perm[c];
-    double s = 0.0;
-    for (int k = 0; k < L; ++k) s = fma(X[(int64_t)i * L + k], sZ[k + pc * kLd], s);
-    a.V1[e] = s;   // k-major: V1[i * r + c]
+  // Z_r in eigenvalue order, k-major with an even row stride, in the (now
+  // free) K buffer; a task is one row of V1 = X Z_r and eight of its columns,
+  // the tasks of a wave share their columns (broadcast LDS reads) and each
+  // output sums over k in order
+  const int rp = (r + 1) & ~1;
+  double* Zr = sK;
+  for (int e = t; e < L * rp; e += kRRThreads) {
+    const int k = e / rp, c = e % rp;
+    Zr[e] = c < r ? sZ[k + perm[c] * kLd] : 0.0;
+  }
+  __syncthreads();
+  const int nch = (r + 7) >> 3;
+  for (int64_t task = t; task < (int64_t)n * nch; task += kRRThreads) {
+    const int ch = (int)(task / n), i = (int)(task - (int64_t)ch * n);
+    const int c0 = 8 * ch, cn = min(8, r - c0);
+    const double* xr = X + (int64_t)i * L;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < L; ++k) {
+      const double xk = xr[k];
+      const double2* z = reinterpret_cast<const double2*>(Zr + k * rp + c0);   // within sK: k * rp + c0 + 8 <= 64 * 64 + 8
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 zz = z[j];
+        acc[2 * j] = fma(xk, zz.x, acc[2 * j]);
+        acc[2 * j + 1] = fma(xk, zz.y, acc[2 * j + 1]);
+      }
+    }
+    double* out = a.V1 + (int64_t)i * r + c0;   // k-major: V1[i * r + c]
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < cn) out[j] = acc[j];
   }
   __threadfence_block();
   __syncthreads();
