@@ -583,10 +583,20 @@ __device__ __forceinline__ void canonical_signs(const double* V, int64_t si, int
   for (int a = w; a < r; a += NT / 64) {
     double best = -1.0, val = 0.0;
     int bi = 0x7fffffff;
-    for (int i = lane; i < n; i += 64) {
-      const double x = V[i * si + a * sa];
-      const double ax = fabs(x);
-      if (ax > best) { best = ax; bi = i; val = x; }
+    // rows in increasing order per lane, four loads in flight
+    for (int i0 = lane; i0 < n; i0 += 256) {
+      double xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        xv[u] = i < n ? V[i * si + a * sa] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        const double ax = fabs(xv[u]);
+        if (i < n && ax > best) { best = ax; bi = i; val = xv[u]; }
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       const double ob = __shfl_xor(best, o, 64);
@@ -804,13 +814,26 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
   __threadfence_block();
   __syncthreads();
   canonical_signs<kRRThreads>(a.V1, r, 1, n, r, sg);
-  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
-    const int i = (int)(e / r), c = (int)(e % r);
-    const double v = a.V1[e] * sg[c];
-    a.V1[e] = v;
-    if (a.core) {
-      if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
-      else a.core[c + (int64_t)r * i] = v;
+  const int64_t nr = (int64_t)n * r;
+  for (int64_t e0 = t; e0 < nr; e0 += 4 * kRRThreads) {
+    double vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kRRThreads;
+      vv[u] = e < nr ? a.V1[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kRRThreads;
+      if (e < nr) {
+        const int i = (int)(e / r), c = (int)(e % r);
+        const double v = vv[u] * sg[c];
+        a.V1[e] = v;
+        if (a.core) {
+          if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
+          else a.core[c + (int64_t)r * i] = v;
+        }
+      }
     }
   }
   for (int e = t; e < L * r; e += kRRThreads) {
@@ -908,13 +931,26 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restr
   __threadfence_block();
   __syncthreads();
   canonical_signs<kRRThreads>(a.V1, r, 1, n, r, sg);
-  for (int64_t e = t; e < (int64_t)n * r; e += kRRThreads) {
-    const int i = (int)(e / r), c = (int)(e % r);
-    const double v = a.V1[e] * sg[c];
-    a.V1[e] = v;
-    if (a.core) {
-      if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
-      else a.core[c + (int64_t)r * i] = v;
+  const int64_t nr = (int64_t)n * r;
+  for (int64_t e0 = t; e0 < nr; e0 += 4 * kRRThreads) {
+    double vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kRRThreads;
+      vv[u] = e < nr ? a.V1[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kRRThreads;
+      if (e < nr) {
+        const int i = (int)(e / r), c = (int)(e % r);
+        const double v = vv[u] * sg[c];
+        a.V1[e] = v;
+        if (a.core) {
+          if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
+          else a.core[c + (int64_t)r * i] = v;
+        }
+      }
     }
   }
   for (int e = t; e < L * r; e += kRRThreads) {
