@@ -452,14 +452,13 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
   double* Kn = K;
   int sweeps = 0;
   static_assert(NT >= (kCMax / 2) * (kCMax / 2), "one 2 x 2 block per thread");
-  // lane t evaluates the rotation of pair P = t mod h (every lane of a wave
-  // that holds a block, so that each wave has all h rotations: 64 >= h) and
-  // takes the rotation of its column pair Q from a lane of its own wave
+  // a round is two phases: thread p < h evaluates the rotation of pair p
+  // (lam holds the h rotations meanwhile) while every block thread loads its
+  // block and Z entries; after a barrier the block threads apply the
+  // rotations of their two pairs
   const bool blk = t < hh;            // this thread's block (P, Q), fixed for the whole solve
-  const bool rot_lane = t < ((hh + 63) & ~63);
   const int P = t % h, Q = blk ? t / h : 0;
-  const int wbase = t & ~63;
-  const int srcQ = wbase + (Q - wbase % h + h) % h;
+  double* rot = lam;
   int Pa, sa, Pb, sb, Qa, ta, Qb, tb;
   pair_source(P, 0, h, &Pa, &sa);
   pair_source(P, 1, h, &Pb, &sb);
@@ -489,34 +488,40 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
     if (!any) break;
     sweeps = sweep + 1;
     for (int round = 0; round < m; ++round) {
-      if (rot_lane) {
-        // every operand of the thread first (one LDS round trip), then the math
+      // phase 1: the rotations (threads t < h hold pair t as their row pair)
+      if (t < h) {
         const double pa = Kc[o_pa], pb = Kc[o_pb], pab = Kc[o_pab];
-        double kaa = 0.0, kab = 0.0, kba = 0.0, kbb = 0.0, z0a = 0.0, z0b = 0.0, z1a = 0.0, z1b = 0.0;
-        int xQ, yQ;
-        pair_labels(Q, round, m, &xQ, &yQ);
-        double* z0 = Z + 2 * P + xQ * kLd;
-        double* z1 = Z + 2 * P + yQ * kLd;
-        if (blk) {
-          kaa = Kc[o_aa]; kab = Kc[o_ab]; kba = Kc[o_ba]; kbb = Kc[o_bb];
-          z0a = z0[0]; z0b = z0[1]; z1a = z1[0]; z1b = z1[1];
-        }
         double cP, sP;
         jacobi_rot(pa, pb, pab, abs_floor, &cP, &sP);
-        const double cQ = __shfl(cP, srcQ, 64), sQ = __shfl(sP, srcQ, 64);
-        if (blk) {
-          const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
-          const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
-          Kn[own] = cP * raa - sP * rba;              // (x_P, x_Q)
-          Kn[hh + own] = sP * raa + cP * rba;         // (y_P, x_Q)
-          Kn[2 * hh + own] = cP * rab - sP * rbb;     // (x_P, y_Q)
-          Kn[3 * hh + own] = sP * rab + cP * rbb;     // (y_P, y_Q)
-          // Z <- Z J on rows 2P, 2P + 1 and the columns of pair Q
-          z0[0] = cQ * z0a - sQ * z1a;
-          z0[1] = cQ * z0b - sQ * z1b;
-          z1[0] = sQ * z0a + cQ * z1a;
-          z1[1] = sQ * z0b + cQ * z1b;
-        }
+        rot[2 * t] = cP;
+        rot[2 * t + 1] = sP;
+      }
+      double kaa = 0.0, kab = 0.0, kba = 0.0, kbb = 0.0, z0a = 0.0, z0b = 0.0, z1a = 0.0, z1b = 0.0;
+      double* z0 = Z;
+      double* z1 = Z;
+      if (blk) {
+        kaa = Kc[o_aa]; kab = Kc[o_ab]; kba = Kc[o_ba]; kbb = Kc[o_bb];
+        int xQ, yQ;
+        pair_labels(Q, round, m, &xQ, &yQ);
+        z0 = Z + 2 * P + xQ * kLd;
+        z1 = Z + 2 * P + yQ * kLd;
+        z0a = z0[0]; z0b = z0[1]; z1a = z1[0]; z1b = z1[1];
+      }
+      __syncthreads();
+      // phase 2: the block update
+      if (blk) {
+        const double cP = rot[2 * P], sP = rot[2 * P + 1], cQ = rot[2 * Q], sQ = rot[2 * Q + 1];
+        const double raa = cQ * kaa - sQ * kab, rab = sQ * kaa + cQ * kab;
+        const double rba = cQ * kba - sQ * kbb, rbb = sQ * kba + cQ * kbb;
+        Kn[own] = cP * raa - sP * rba;              // (x_P, x_Q)
+        Kn[hh + own] = sP * raa + cP * rba;         // (y_P, x_Q)
+        Kn[2 * hh + own] = cP * rab - sP * rbb;     // (x_P, y_Q)
+        Kn[3 * hh + own] = sP * rab + cP * rbb;     // (y_P, y_Q)
+        // Z <- Z J on rows 2P, 2P + 1 and the columns of pair Q
+        z0[0] = cQ * z0a - sQ * z1a;
+        z0[1] = cQ * z0b - sQ * z1b;
+        z1[0] = sQ * z0a + cQ * z1a;
+        z1[1] = sQ * z0b + cQ * z1b;
       }
       __syncthreads();
       double* tmp = Kc; Kc = Kn; Kn = tmp;
