@@ -251,7 +251,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     else:
         achieved = flops_per / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
     roof["traffic"] = MEASURED_TRAFFIC.get(dom_name) if W is WORKLOADS["order5_32_fp64"] else None
     roof["kernel"] = dom_name

@@ -74,6 +74,13 @@ typedef struct {
                                with HIP events on the caller's stream, filling
                                tt_report.kstat; 0 = no events */
   int32_t prec;             /* tt_prec: TT_PREC_FP64, TT_PREC_MIXED or TT_PREC_MIXED_BF16 */
+  int32_t fuse_ata;         /* 1: a power step over FP64 data stored column-major
+                               (right-to-left sweeps) with n <= 512, ell <= 32 and
+                               n ell <= 12288 forms A^T (A X) with one read of A
+                               (class "tall_ata"); 0 (default): two passes, A X then
+                               A^T Y, which measure faster at n = 512: the one-pass
+                               kernel can hold only 16-row tiles of A on chip, and
+                               128-byte column segments stream at about 2 TB/s */
 } tt_opts;
 
 /* TT_PREC_FP64: every carry, sketch and product in FP64.
@@ -91,7 +98,7 @@ typedef struct {
 typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1, TT_PREC_MIXED_BF16 = 2 } tt_prec;
 
 /* Kernel classes of the profile (tt_kernel_class_name gives their names). */
-#define TT_NKCLASS 7
+#define TT_NKCLASS 8
 #define TT_PROFILE_ALL ((1 << TT_NKCLASS) - 1)
 typedef struct {
   int64_t launches;
@@ -119,7 +126,8 @@ typedef struct {
 const char* tt_kernel_class_name(int c);
 
 /* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
- * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64. */
+ * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64,
+ * fuse_ata = 0. */
 void tt_default_opts(tt_opts* opts);
 
 /* Device bytes of workspace tt_utv_decompose needs for this problem.

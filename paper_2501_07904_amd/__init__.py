@@ -35,10 +35,10 @@ class tt_opts(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("max_rank", ctypes.c_int32), ("exact_delta", ctypes.c_int32),
                 ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32),
-                ("prec", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("fuse_ata", ctypes.c_int32)]
 
 
-TT_NKCLASS = 7
+TT_NKCLASS = 8
 TT_PROFILE_ALL = (1 << TT_NKCLASS) - 1
 
 
@@ -128,13 +128,14 @@ PRECS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 
 
 def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-              prec="fp64"):
+              prec="fp64", fuse_ata=False):
     o = tt_opts()
     load_library().tt_default_opts(ctypes.byref(o))
     o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
     # profile: False/0 = off, True = every kernel class, an int = bit mask of classes
     o.profile = TT_PROFILE_ALL if profile is True else int(profile)
     o.prec = PRECS[prec]
+    o.fuse_ata = int(bool(fuse_ata))
     keep = None
     if weights is not None:
         keep = (ctypes.c_double * len(weights))(*[float(w) for w in weights])
@@ -160,7 +161,7 @@ def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dty
 
 def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
                      max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
-                     profile=False, prec="fp64"):
+                     profile=False, prec="fp64", fuse_ata=False):
     """TT-UTV of the device tensor A (float64/float32, flat in ivec order, i1
     fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
     float64 view of a column-major device buffer."""
@@ -173,7 +174,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
     d = len(dims)
     if (ranks is None) == (eps is None):
         raise ValueError("give exactly one of ranks and eps")
-    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec)
+    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata)
     rk = None if ranks is None else _i64(_full_ranks(ranks, d))
     epsv = -1.0 if eps is None else float(eps)
     nbytes = ctypes.c_size_t(0)
@@ -310,7 +311,7 @@ class Decomposer:
 
     def __init__(self, dims, dtype=torch.float64, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                  oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-                 device="cuda", prec="fp64"):
+                 device="cuda", prec="fp64", fuse_ata=False):
         lib = load_library()
         self.lib = lib
         self.dims = [int(x) for x in dims]
@@ -319,7 +320,8 @@ class Decomposer:
             raise ValueError("give exactly one of ranks and eps")
         self.dtype = dtype
         self.profile = profile
-        self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec)
+        self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
+                                          fuse_ata)
         self._dims = _i64(self.dims)
         self._ranks = None if ranks is None else _i64(_full_ranks(ranks, d))
         self.eps = -1.0 if eps is None else float(eps)

@@ -33,8 +33,10 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // ---- optional per-launch timing with HIP events on the caller's stream ----
-enum KClass { KC_ATB = 0, KC_AX = 1, KC_GRAM_Y = 2, KC_CARRY = 3, KC_RESID = 4, KC_REDUCE = 5, KC_SMALL = 6 };
-const char* const kClassNames[TT_NKCLASS] = {"tall_atb", "tall_ax", "gram_y", "carry", "resid", "reduce", "small"};
+enum KClass { KC_ATB = 0, KC_AX = 1, KC_GRAM_Y = 2, KC_CARRY = 3, KC_RESID = 4, KC_REDUCE = 5, KC_SMALL = 6,
+              KC_ATA = 7 };
+const char* const kClassNames[TT_NKCLASS] = {"tall_atb", "tall_ax", "gram_y", "carry", "resid", "reduce", "small",
+                                             "tall_ata"};
 
 thread_local std::vector<hipEvent_t> g_events;
 }  // namespace
@@ -140,6 +142,7 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
   if (P.o.max_rank < 0) return fail(TT_EINVAL, "max_rank < 0");
   if (P.o.prec != TT_PREC_FP64 && P.o.prec != TT_PREC_MIXED && P.o.prec != TT_PREC_MIXED_BF16)
     return fail(TT_EINVAL, "bad prec %d", P.o.prec);
+  if (P.o.fuse_ata != 0 && P.o.fuse_ata != 1) return fail(TT_EINVAL, "fuse_ata = %d is not 0 or 1", P.o.fuse_ata);
   P.mixed = (P.o.prec != TT_PREC_FP64);
   P.bf16 = (P.o.prec == TT_PREC_MIXED_BF16) ? 1 : 0;
   P.sweep = sweep;
@@ -281,6 +284,8 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
       for (int cc = 1; cc <= c; ++cc)   // reused by the orthonormalisation of a tall n x cc iterate
         z.part = std::max(z.part, orth_scratch(s.n, cc));
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, c) * s.n * c);
+      if (P.o.fuse_ata && s.layout == COL && s.n <= 512)   // one-pass power products
+        z.part = std::max(z.part, (int64_t)fused_ata_blocks(s.m) * s.n * std::min(c, 32));
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, c, c) * c * c);
       if (P.alg4) {
         z.U = std::max(z.U, s.m * (int64_t)c);
@@ -404,6 +409,12 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
                  launch_atb2(io.A, io.a_f32, W.Y, 1, m, n, c, s.layout, io.a_f32, W.part, nch, st));
         LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
                launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+      } else if (P.o.fuse_ata && !(first && it == 0) && fused_ata_ok(io.a_f32, m, n, c, s.layout)) {
+        const int fb = fused_ata_blocks(m);
+        LAUNCH(PF, KC_ATA, mn * sa + (double)n * c * 8 + (double)fb * n * c * 8, 4.0 * mn * c,
+               launch_fused_ata((const double*)io.A, W.X, m, n, c, W.part, fb, st));
+        LAUNCH(PF, KC_REDUCE, (double)(fb + 1) * n * c * 8, (double)fb * n * c,
+               launch_reduce(W.part, fb, (int64_t)n * c, W.M, nullptr, st));
       } else {
         LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
                launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
@@ -441,6 +452,15 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     bool need_norm = first;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
     for (int it = 0; it < P.o.q; ++it) {
+      if (!P.mixed && !need_norm && P.o.fuse_ata && fused_ata_ok(io.a_f32, m, n, c, s.layout)) {
+        const int fb = fused_ata_blocks(m);
+        LAUNCH(PF, KC_ATA, mn * sa + (double)n * c * 8 + (double)fb * n * c * 8, 4.0 * mn * c,
+               launch_fused_ata((const double*)io.A, W.X, m, n, c, W.part, fb, st));
+        LAUNCH(PF, KC_REDUCE, (double)(fb + 1) * n * c * 8, (double)fb * n * c,
+               launch_reduce(W.part, fb, (int64_t)n * c, W.M, nullptr, st));
+        LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
+        continue;
+      }
       const double sy = P.mixed ? 4.0 : 8.0;
       LAUNCH(PF, KC_AX, mn * sa + mc * sy + (double)n * c * 8, 2.0 * mn * c,
              launch_ax(io.A, io.a_f32, W.X, W.Y, P.mixed, m, n, c, s.layout, ach,

@@ -71,6 +71,13 @@ hipError_t launch_atb_lp(const void* A, int a_f32, const float* Y, int64_t m, in
 // any n: 128 columns of A per workgroup, row tiles prefetched into registers;
 // FP64 matrix cores, or FP32 ones (f32_mma, FP32 data only).  atb2_chunks(m, n)
 // chunks (never more than atb_chunks).
+// Z = A^T (A X) in one pass over A (FP64, column-major A; see fused_ata_ok):
+// fused_ata_blocks(m) partials of n x c (the count the launch takes), reduced
+// with launch_reduce.
+bool fused_ata_ok(int a_f32, int64_t m, int n, int c, int layout);
+int fused_ata_blocks(int64_t m);
+hipError_t launch_fused_ata(const double* A, const double* X, int64_t m, int n, int c, double* partials, int nblocks,
+                            hipStream_t st);
 int atb2_chunks(int64_t m, int n);
 hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c, int layout,
                        int f32_mma, double* partials, int nchunks, hipStream_t st);

@@ -469,23 +469,34 @@ __device__ __forceinline__ int jacobi_eig(double* K, double* K2, double* Z, int 
   const int o_aa = (sa + 2 * ta) * hh + Pa + h * Qa, o_ab = (sa + 2 * tb) * hh + Pa + h * Qb;
   const int o_ba = (sb + 2 * ta) * hh + Pb + h * Qa, o_bb = (sb + 2 * tb) * hh + Pb + h * Qb;
   const int own = P + h * Q;
+  double prev_off2 = HUGE_VAL;
   for (int sweep = 0; sweep < 30 && L >= 2; ++sweep) {
     // converged when no pair would be rotated: exactly the sweep that would
     // follow applies no rotation, so it is not run
     if (t == 0) *flag = 0;
     __syncthreads();
+    double off = 0.0;
     for (int e = t; e < 4 * hh; e += NT) {
       const int pl = e / hh, idx = e - pl * hh;
       const int Pi = idx % h, Pj = idx / h;
       if (Pi == Pj && (pl == 0 || pl == 3)) continue;   // a diagonal entry
       const double apq = Kc[e];
+      off = fma(apq, apq, off);
       const double di = Kc[3 * (pl & 1) * hh + Pi * (1 + h)], dj = Kc[3 * (pl >> 1) * hh + Pj * (1 + h)];
       if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(di * dj)) *flag = 1;
     }
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o, 64);
+    if ((t & 63) == 0) sh[t >> 6] = off;
     __syncthreads();
     const int any = *flag;
+    double off2 = 0.0;
+    for (int i = 0; i < NT / 64; ++i) off2 += sh[i];
     __syncthreads();
-    if (!any) break;
+    // also stop once the off-diagonal mass no longer falls (by 4x per sweep
+    // after the first four): the entries left above the floor are then
+    // rounding noise of the large ones that further rotations only move around
+    if (!any || (sweep >= 4 && off2 > 0.25 * prev_off2)) break;
+    prev_off2 = off2;
     sweeps = sweep + 1;
     for (int round = 0; round < m; ++round) {
       // phase 1: the rotations (threads t < h hold pair t as their row pair)

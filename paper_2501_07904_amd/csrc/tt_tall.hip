@@ -815,6 +815,142 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
     }
 }
 
+// ---------------------------------------------------------------------------
+// One power product Z = A^T (A X) with each row tile of A read from HBM once
+// (FP64, column-major A, n <= 512, n c <= 12288).  A workgroup of 8 waves
+// walks 16-row tiles of its rows; wave w owns columns 64w .. 64w+63.
+//   phase 1: Y_t = A_t X over the wave's columns (operand A: lane l holds
+//            A(row l%16, column 64w + 4s + l/16) at k-step s; X, n x c
+//            k-major, sits in LDS for the whole launch), the eight partial
+//            16 x 16NT blocks summed in LDS in wave order (two barriers);
+//   phase 2: Z(w's columns, :) += A_t^T Y_t (operand A: lane l holds
+//            A(row 4s + l/16, column 64w + 16mt + l%16); the second reading
+//            of the tile hits the caches), accumulated in registers.
+// The next tile's phase-1 operand is loaded while the current one is
+// multiplied.  Block b takes tiles b, b + B, b + 2B, ... (B blocks), so that
+// at any moment the blocks read one contiguous band of rows of every column.
+// Each workgroup writes its n x c partial of Z.
+constexpr int kFaThreads = 512;
+constexpr int kFaCW = 64;
+constexpr int kFaTR = 16;
+constexpr int kFaMaxN = 8 * kFaCW;
+constexpr int kFaMaxNC = 12288;
+
+template <int NT>
+__global__ __launch_bounds__(kFaThreads) void k_fused_ata(const double* __restrict__ A, const double* __restrict__ X,
+                                                          int64_t m, int n, int c,
+                                                          double* __restrict__ partials) {
+  constexpr int WY = 16 * NT;
+  __shared__ double sX[kFaMaxNC];
+  __shared__ double sP[8 * kFaTR * WY];
+  __shared__ double sYt[kFaTR * WY];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int jw = kFaCW * w;
+  const int64_t r0 = (int64_t)blockIdx.x * kFaTR, stride = (int64_t)gridDim.x * kFaTR;
+  const int64_t r1 = m;
+  for (int e = t; e < n * c; e += kFaThreads) sX[e] = X[e];
+  double a1[16], a1n[16], a2[16];
+  // loads stay straight-line: an index outside A is clamped into it and the
+  // value replaced by zero afterwards
+  auto load1 = [&](int64_t rb, double* dst) {
+    const int64_t r = rb + li;
+    const int64_t rc = r < r1 ? r : r1 - 1;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int j = jw + 4 * s + g;
+      dst[s] = A[rc + m * (int64_t)(j < n ? j : n - 1)];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int j = jw + 4 * s + g;
+      dst[s] = (r < r1 && j < n) ? dst[s] : 0.0;
+    }
+  };
+  auto load2 = [&](int64_t rb) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t r = rb + 4 * s + g;
+        const int j = jw + 16 * mt + li;
+        a2[4 * mt + s] = A[(r < r1 ? r : r1 - 1) + m * (int64_t)(j < n ? j : n - 1)];
+      }
+  };
+  auto mask2 = [&](int64_t rb) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t r = rb + 4 * s + g;
+        const int j = jw + 16 * mt + li;
+        a2[4 * mt + s] = (r < r1 && j < n) ? a2[4 * mt + s] : 0.0;
+      }
+  };
+  d4 z[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) z[mt][q] = d4{0, 0, 0, 0};
+  if (r0 < r1) load1(r0, a1);
+  __syncthreads();   // X staged
+  for (int64_t rb = r0; rb < r1; rb += stride) {
+    load2(rb);
+    if (rb + stride < r1) load1(rb + stride, a1n);
+    // phase 1
+    d4 y[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) y[q] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int j = jw + 4 * s + g;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int col = 16 * q + li;
+        const double xv = (j < n && col < c) ? sX[j * c + col] : 0.0;
+        y[q] = mfma_f64(a1[s], xv, y[q]);
+      }
+    }
+    // result lane l register v: row l/16 + 4v, column 16q + l%16
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sP[(w * kFaTR + g + 4 * v) * WY + 16 * q + li] = y[q][v];
+    __syncthreads();
+    if (t < kFaTR * WY) {
+      double sum = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < 8; ++ww) sum += sP[ww * kFaTR * WY + t];
+      sYt[t] = sum;
+    }
+    __syncthreads();
+    // phase 2
+    mask2(rb);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double yv[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) yv[q] = sYt[(4 * s + g) * WY + 16 * q + li];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) z[mt][q] = mfma_f64(a2[4 * mt + s], yv[q], z[mt][q]);
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) a1[s] = a1n[s];
+  }
+  double* out = partials + (int64_t)blockIdx.x * n * c;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = jw + 16 * mt + g + 4 * v, cc = 16 * q + li;
+        if (jj < n && cc < c) out[jj + (int64_t)n * cc] = z[mt][q][v];
+      }
+}
+
 // Column-major, aligned A (vector form of the narrow A*W): lane li of a wave
 // owns the run of RB consecutive rows RB*li .. RB*li+RB-1 of a 16*RB-row block
 // and loads it with one vector load per column; MFMA row block rb holds rows
@@ -1474,6 +1610,27 @@ namespace ttutv {
 
 int atb2_chunks(int64_t m, int n) {
   return atb_chunks(m, n, 0);   // no more partials than the 64-column kernel (workspace bound)
+}
+
+bool fused_ata_ok(int a_f32, int64_t m, int n, int c, int layout) {
+  return !a_f32 && layout == COL && m >= 1 && n >= 1 && n <= kFaMaxN && c >= 1 && c <= 32 &&
+         (int64_t)n * c <= kFaMaxNC;
+}
+
+// one block per compute unit, at most one per row tile
+int fused_ata_blocks(int64_t m) {
+  const int64_t tiles = (m + kFaTR - 1) / kFaTR;
+  return (int)(tiles < 256 ? tiles : 256);
+}
+
+hipError_t launch_fused_ata(const double* A, const double* X, int64_t m, int n, int c, double* partials, int nblocks,
+                            hipStream_t st) {
+  if (!fused_ata_ok(0, m, n, c, COL) || nblocks != fused_ata_blocks(m)) return hipErrorInvalidValue;
+  if (c <= 16)
+    TT_LAUNCH((k_fused_ata<1>), dim3(nblocks), dim3(kFaThreads), 0, st, A, X, m, n, c, partials);
+  else
+    TT_LAUNCH((k_fused_ata<2>), dim3(nblocks), dim3(kFaThreads), 0, st, A, X, m, n, c, partials);
+  return hipGetLastError();
 }
 
 hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c, int layout,

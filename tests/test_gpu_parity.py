@@ -156,6 +156,23 @@ def test_tall_iterate_tree_qr(dims, ranks, p, sweep, variant):
     np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
 
 
+@pytest.mark.parametrize("dims,ranks,p", [
+    ([37, 11, 40], [6, 9], 8),       # step 2: m = 37 (a partial row tile), n = 99, ell = 14 (one column tile)
+    ([500, 12, 30], [20, 10], 8),    # m = 500, n = 120, ell = 28 (two column tiles)
+    ([300, 16, 32], [19, 28], 8),    # n = 448, ell = 27: n ell = 12096 near the staged-X limit
+])
+@pytest.mark.parametrize("variant", ["URV", "ULV"])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_one_pass_power_product(dims, ranks, p, variant, fuse):
+    """Right-to-left power steps with A^T (A X) formed in one pass over A
+    (fuse_ata) and in two (the default): both give the oracle's cores."""
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, 107)
+    cores, rep, oc, orep = _run(a, dims, "R2L", variant, ranks=ranks, q=2, p=p, exact_delta=True, fuse_ata=fuse)
+    assert rep["ranks"] == orep["ranks"]
+    _compare(cores, oc, "R2L")
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+
+
 @pytest.mark.parametrize("sweep,variant", COMBOS)
 def test_truncation_below_true_rank(sweep, variant):
     """Ranks below the generating ranks: real truncation with well-separated spectra."""
