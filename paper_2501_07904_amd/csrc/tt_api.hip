@@ -401,14 +401,16 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
         LAUNCH(PF, KC_AX, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
                launch_ax_lp(io.A, io.a_f32, W.X, (float*)W.Y, m, n, c, s.layout, P.bf16, st));
         const int nch = atb_lp_chunks(m, n);
+        double* dst = nch == 1 ? W.M : W.part;   // a single chunk is the sum itself
         if (P.bf16)
           LAUNCH(PF, KC_ATB, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
-                 launch_atb_lp(io.A, io.a_f32, (const float*)W.Y, m, n, c, s.layout, W.part, nch, 1, st));
+                 launch_atb_lp(io.A, io.a_f32, (const float*)W.Y, m, n, c, s.layout, dst, nch, 1, st));
         else
           LAUNCH(PF, KC_ATB, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
-                 launch_atb2(io.A, io.a_f32, W.Y, 1, m, n, c, s.layout, io.a_f32, W.part, nch, st));
-        LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
-               launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+                 launch_atb2(io.A, io.a_f32, W.Y, 1, m, n, c, s.layout, io.a_f32, dst, nch, st));
+        if (nch > 1)
+          LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+                 launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       } else if (P.o.fuse_ata && !(first && it == 0) && fused_ata_ok(io.a_f32, m, n, c, s.layout)) {
         const int fb = fused_ata_blocks(m);
         LAUNCH(PF, KC_ATA, mn * sa + (double)n * c * 8 + (double)fb * n * c * 8, 4.0 * mn * c,
@@ -421,11 +423,13 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
                          (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
         if (first && it == 0)
           LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
+        // a single chunk is the sum itself: written straight to M, no reduction
         const int nch = atb2_chunks(m, n);
         LAUNCH(PF, KC_ATB, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-               launch_atb2(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, 0, W.part, nch, st));
-        LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
-               launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
+               launch_atb2(io.A, io.a_f32, W.Y, 0, m, n, c, s.layout, 0, nch == 1 ? W.M : W.part, nch, st));
+        if (nch > 1)
+          LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
+                 launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       }
       LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
     }
@@ -439,9 +443,10 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     if (rr_norm) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
     const int kch = atb_chunks(m, c, c);
     LAUNCH(PF, KC_GRAM_Y, mc * 8 + (double)c * c * 8, 2.0 * mc * c,
-           launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, W.part, kch, st));
-    LAUNCH(PF, KC_REDUCE, (double)(kch + 1) * c * c * 8, (double)kch * c * c,
-           launch_reduce(W.part, kch, (int64_t)c * c, W.K, nullptr, st));
+           launch_atb(W.Y, 0, W.Y, 0, m, c, c, s.layout, kch == 1 ? W.K : W.part, kch, st));
+    if (kch > 1)
+      LAUNCH(PF, KC_REDUCE, (double)(kch + 1) * c * c * 8, (double)kch * c * c,
+             launch_reduce(W.part, kch, (int64_t)c * c, W.K, nullptr, st));
     if (first) a.normC2_src = W.normA2;
     LAUNCH(PF, KC_SMALL, 0, 0, launch_rr_solve(W.K, W.X, a, st));
   } else {
