@@ -68,6 +68,24 @@ def test_workspace_grows_with_the_problem(lib):
     assert _ws(lib, [8] * 8, None, eps=1e-6, sweep=1, variant=1, dtype=1)[1] >= _ws(lib, [8] * 8, [1] + [8] * 7 + [1], sweep=1, variant=1, dtype=1)[1]
 
 
+def test_one_pass_option_on_host(lib):
+    """fuse_ata: off by default, 0 or 1 only, and when on the workspace holds
+    one n x ell partial per workgroup of the one-pass kernel (256 for the
+    32768 x 512 unfolding of 32^5, ell = 24)."""
+    o = T.make_opts()[0]
+    assert o.fuse_ata == 0
+    off = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1, opts=o)[1]
+    o1 = T.make_opts(fuse_ata=True)[0]
+    rc, on = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1, opts=o1)
+    # the partials grow from the two-pass kernel's 128 row chunks to 256 workgroups
+    assert rc == T.TT_OK and on - off == (256 - 128) * 512 * 24 * 8
+    o1.fuse_ata = 2
+    assert _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1, opts=o1)[0] == T.TT_EINVAL
+    assert "fuse_ata" in lib.tt_last_error().decode()
+    names = [lib.tt_kernel_class_name(c).decode() for c in range(T.TT_NKCLASS)]
+    assert names[-1] == "tall_ata" and lib.tt_kernel_class_name(T.TT_NKCLASS) is None
+
+
 def test_decompose_rejects_on_host(lib):
     d = 4
     dims = T._i64([16] * 4)
