@@ -330,9 +330,10 @@ __device__ __host__ __forceinline__ int reg_rows(int n, int c) {
 // --------------------------------------------------------------------------
 // Symmetric eigen-decomposition of K (L x L in LDS, ld kLd) by cyclic Jacobi
 // with the round-robin parallel ordering: each round rotates L/2 disjoint
-// pairs, and K <- J^T K J is applied as independent 2 x 2 block updates (one
-// barrier per round).  Pairs whose off-diagonal entry is below the rounding
-// floor are skipped; the iteration stops after a sweep without a rotation.
+// pairs, and K <- J^T K J is applied as independent 2 x 2 block updates.
+// Pairs whose off-diagonal entry is below the rounding floor are skipped; the
+// iteration stops before a sweep that would rotate nothing, or once sweeps no
+// longer reduce the off-diagonal mass.
 // On return lam[0..L) holds the eigenvalues in descending order and perm[a]
 // the column of Z (L x L, ld kLd) holding the eigenvector of lam[a].
 //
