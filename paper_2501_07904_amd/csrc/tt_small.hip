@@ -671,11 +671,19 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
       // n <= 64: at most 4 rows per thread; sK (free until K is formed) holds
       // the reflectors for the barrier-free formation of Q
       static_assert(kCMax * kLd >= 4 * kThreads, "sK holds 4 * kThreads doubles");
-      switch (reg_group_width(L)) {
-        case 16: householder_reg<4, 16>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
-        case 32: householder_reg<4, 32>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
-        default: householder_reg<4, 64>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK); break;
+      // rows per thread: just enough for n (every padded row costs LDS reads
+      // of the reflectors in each step)
+      const int tpj = reg_group_width(L);
+      const int rn = (n + tpj - 1) / tpj;
+#define TT_GHH(RV, TV) householder_reg<RV, TV>(T, 1, kLd, T, 1, kLd, n, L, vbuf, nullptr, 0, 0, sK)
+      if (tpj == 16) {
+        if (rn <= 1) TT_GHH(1, 16); else if (rn <= 2) TT_GHH(2, 16); else TT_GHH(4, 16);
+      } else if (tpj == 32) {
+        if (rn <= 1) TT_GHH(1, 32); else TT_GHH(2, 32);
+      } else {
+        TT_GHH(1, 64);
       }
+#undef TT_GHH
       double* tmp = X; X = T; T = tmp;
     }
   }
