@@ -266,6 +266,20 @@ def test_c2_full_size_order5_32():
         assert rep2["err_bound"] == pytest.approx(orep["err_bound"], rel=1e-2)
 
 
+def test_jacobi_stops_at_the_rounding_floor():
+    """32^5 with the one-pass power products, whose rounding once kept the
+    threshold-only Jacobi rule rotating noise to its 30-sweep cap on the third
+    unfolding: the solver now stops when sweeps no longer shrink the
+    off-diagonal mass, with the oracle's cores."""
+    dims = [32] * 5
+    a, _ = ttgen.gaussian_tt_tensor(dims, [16] * 4, 1e-6, 0)
+    cores, rep = T.tt_utv_decompose(_dev(a), dims, ranks=[16] * 4, sweep="R2L", variant="URV", q=2,
+                                    oversample=8, seed=1, fuse_ata=True)
+    assert max(rep["sweeps"]) <= 12, rep["sweeps"]
+    oc, _ = oracle.tt_utv(a, dims, ranks=[16] * 4, sweep="R2L", variant="URV", q=2, p=8, seed=1)
+    _compare(cores, oc, "R2L")
+
+
 # --------------------------------------------------------------------- prescribed accuracy
 @pytest.mark.parametrize("sweep,variant", ALL)
 def test_eps_mode_function_tensor(sweep, variant):
