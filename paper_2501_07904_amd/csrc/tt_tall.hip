@@ -297,16 +297,16 @@ __global__ __launch_bounds__(ax_kw_threads(NT)) void k_ax_kw(const TA* __restric
 // column blocks).  Only the blocks I <= J are multiplied (both operands of a
 // Gram block come from the same registers); the lower blocks are written by
 // symmetry.  The four waves' partial blocks are summed in LDS in wave order.
-// Each lane takes a run of RPL consecutive rows (RPL = 32 bytes of each
-// column: 8 FP32 or 4 FP64 values) as vector loads when the storage is
-// column-major and aligned (VEC), so that one load instruction covers 4 x 32
-// contiguous bytes of 16 columns; MFMA step s then uses row RPL g + s for
-// k-slot g, and a wave advances 4 RPL rows per iteration.
+// Each lane takes a run of RPL consecutive rows (RPL = 64 bytes of each
+// column: 16 FP32 or 8 FP64 values) as vector loads when the storage is
+// column-major and aligned (VEC), so that a wave's loads cover 4 x 64
+// contiguous bytes of each of 16 columns; MFMA step s then uses row RPL g + s
+// for k-slot g, and a wave advances 4 RPL rows per iteration.
 template <typename TA, int NB, int LY, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_gram_narrow(const TA* __restrict__ A, int64_t m, int n,
                                                           int64_t rows_per_chunk, double* __restrict__ partials) {
   constexpr int NP = NB * (NB + 1) / 2;
-  constexpr int RPL = 32 / (int)sizeof(TA);
+  constexpr int RPL = 64 / (int)sizeof(TA);
   constexpr int RW = 4 * RPL;   // rows per wave iteration
   __shared__ double sR[kThreads / 64][NP][16][17];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -1332,7 +1332,7 @@ static hipError_t launch_gram_narrow(const TA* A, int64_t m, int n, int layout, 
                                      int nchunks, hipStream_t st) {
   const int nb = (n + 15) / 16;
   // vector loads need 16-byte aligned column starts and run starts (rows per chunk a multiple of the run)
-  constexpr int RPL = 32 / (int)sizeof(TA);
+  constexpr int RPL = 64 / (int)sizeof(TA);
   const bool vec = layout == COL && ((uintptr_t)A % 16) == 0 && (m * (int64_t)sizeof(TA)) % 16 == 0 &&
                    rpc % RPL == 0;
 #define TT_GRN(NBV, LYV, VECV)                                                                                   \
