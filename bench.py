@@ -164,7 +164,7 @@ def main():
                          "traffic: its bytes read and written) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -43,7 +43,7 @@ extern "C" {
 #define TT_ERANK (-3)         /* eps not reachable within max_rank; cores and report still written */
 #define TT_ENONFINITE (-4)    /* input holds NaN or Inf (detected from ||A||_F) */
 #define TT_EHIP (-5)          /* a HIP runtime call failed */
-#define TT_EUNSUPPORTED (-6)  /* valid request outside this build's limits (e.g. ell > 64) */
+#define TT_EUNSUPPORTED (-6)  /* valid request outside the library's limits (e.g. ell > 64) */
 
 #define TT_MAX_D 32           /* largest tensor order */
 #define TT_MAX_ELL 64         /* largest sketch width ell (and therefore rank) */
