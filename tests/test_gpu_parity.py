@@ -136,6 +136,22 @@ def test_ragged_shapes(sweep, variant):
     np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
 
 
+@pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
+def test_partial_product_chunk_edges(sweep, variant):
+    """More row tiles than the 512 row chunks a partial-product pass uses, with
+    m not a multiple of a chunk's rows, so that the last chunks are short or
+    empty and must add zero: the first step's Gram pass over 25,110 (R2L,
+    column-major, vector loads) or 19,251 (L2R, row-major) rows, then power
+    products and the Gram of A X over 930 rows."""
+    dims = [30, 31, 27, 23]
+    ranks = [6, 10, 8]
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, 202)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=ranks, q=2, p=8, exact_delta=True)
+    assert rep["ranks"] == orep["ranks"]
+    _compare(cores, oc, sweep)
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+
+
 @pytest.mark.parametrize("dims,ranks,p", [
     ([200, 30, 40], [8, 36], 8),      # ell = 16, n = 1080 > 1024 rows: two leaf blocks
     ([200, 30, 20], [16, 18], 8),     # ell = 24, n = 540 > 512
