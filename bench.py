@@ -60,6 +60,58 @@ def stated_bound(T, dims, A, kw, dec):
     return rep
 
 
+def contractions(T, cores, reps=10):
+    """The train contractions on the device: reconstruction of the decomposed
+    32^5 train (268 MB of FP64 written, an HBM-write-bound pass), and sampling
+    and its backward on a (16,16,16,16,16,10) train of ranks 16 and 10 at the
+    3,145,728 entries of a 30% mask (the MRI-volume completion shape), each
+    timed with events over `reps` calls after one untimed call.  Returns the
+    JSON object for the bench line."""
+    import numpy as np
+    import torch
+
+    import ttgen
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    total = 1
+    for g in cores:
+        total *= int(g.shape[1])
+    ms = timed(lambda: T.tt_reconstruct(cores))
+    gbs = total * 8 / (ms * 1e-3) / 1e9
+    out["reconstruct"] = {"workload": "32^5 train, ranks 16, to a dense FP64 tensor (268 MB written)",
+                          "ms": round(ms, 4), "GB/s written": round(gbs, 1),
+                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"bench: reconstruct 32^5 FP64: {ms:.4f} ms, {gbs:.1f} GB/s written ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+
+    dims = [16, 16, 16, 16, 16, 10]
+    ranks = [1, 16, 16, 16, 16, 10, 1]
+    n_obs = 3145728
+    c4 = [torch.from_numpy(g).cuda() for g in ttgen.gaussian_cores(dims, ranks, 11)]
+    idx = torch.from_numpy(ttgen.random_indices(dims, n_obs, 12)).cuda()
+    gout = torch.ones(n_obs, dtype=torch.float64, device="cuda")
+    flops_fwd = 2.0 * sum(ranks[k] * ranks[k + 1] for k in range(len(dims)))   # the chain of mat-vecs
+    for name, fn, fl in (("sample", lambda: T.tt_sample(c4, idx), flops_fwd),
+                         ("sample_backward", lambda: T.tt_sample_backward(c4, idx, gout), 3.0 * flops_fwd)):
+        ms = timed(fn)
+        rate = n_obs / (ms * 1e-3)
+        out[name] = {"workload": "(16,16,16,16,16,10) train, ranks 16/10, 3,145,728 sampled entries",
+                     "ms": round(ms, 4), "Msamples/s": round(rate / 1e6, 2),
+                     "GFLOP/s": round(rate * fl / 1e9, 1)}
+        log(f"bench: {name} (16^5 x 10, 3.1M entries): {ms:.4f} ms, {rate / 1e6:.1f} M samples/s, {rate * fl / 1e9:.1f} GFLOP/s")
+    return out
+
+
 def mixed_vs_fp64(steps):
     """The two precision forms on the 1e-6 workload: 8^8 FP32 function tensor
     1/(1+x_1+...+x_8) on a uniform [0,1] grid, prescribed accuracy eps = 1e-6,
@@ -159,6 +211,8 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--no-c5", action="store_true", help="skip the 40^6 (16.4 GB) mixed-vs-FP64 comparison")
     ap.add_argument("--c5-steps", type=int, default=3)
+    ap.add_argument("--no-contractions", action="store_true",
+                    help="skip the timing of reconstruction, sampling and its backward")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the input tensor once (a kernel of known "
                          "traffic: its bytes read and written) to calibrate HBM counters")
@@ -267,6 +321,9 @@ def main():
     roof["step_t_roof_ms"] = round(t_roof, 5)
     roof["step_frac"] = round(t_roof / ms_per_step, 4)
 
+    del rec
+    contr = None if args.no_contractions else contractions(T, cores)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -298,7 +355,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "ranks": rep["ranks"], "rse": rse},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed,
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed, "contractions": contr,
     }
     print(json.dumps(out), flush=True)
 

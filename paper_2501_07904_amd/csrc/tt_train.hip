@@ -10,16 +10,19 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int TT_MAX_D_INTERNAL = 32;
 
-// C (M x N) = A (M x K) B (K x N), column-major, K <= 64.  64 x 64 output
-// tile per workgroup, 4 x 4 per thread; consecutive threads own consecutive
-// row quads so that the column-major writes coalesce.
-template <typename TC>
+// C (M x N) = A (M x K) B (K x N), column-major, K <= KB <= 64.  64 x 64
+// output tile per workgroup, 4 x 4 per thread; consecutive threads own
+// consecutive row quads so that the column-major writes coalesce.  The
+// staged operands take about 1 KB per k (a row of 65 doubles of each), so
+// KB = 16 lets eight workgroups share a CU where KB = 64 fits two: the output
+// write, which bounds the kernel, needs the workgroups in flight.
+template <typename TC, int KB>
 __global__ __launch_bounds__(kThreads) void k_gemm_smallk(const double* __restrict__ A,
                                                           const double* __restrict__ B,
                                                           TC* __restrict__ C, int64_t M, int64_t N,
                                                           int K) {
-  __shared__ double sA[kCMax][64 + 1];
-  __shared__ double sB[kCMax][64 + 1];
+  __shared__ double sA[KB][64 + 1];
+  __shared__ double sB[KB][64 + 1];
   const int t = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
   const int64_t j0 = (int64_t)blockIdx.y * 64;
@@ -50,6 +53,27 @@ __global__ __launch_bounds__(kThreads) void k_gemm_smallk(const double* __restri
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+  // a full tile whose columns start 16-byte aligned: each lane's four rows of
+  // a column (32 bytes of FP64, 16 of FP32) go out as 16-byte streaming stores,
+  // so a wave writes whole 512-byte (256-byte) column runs per instruction and
+  // the output does not displace the cached operands
+  constexpr int VW = 16 / (int)sizeof(TC);   // values per 16-byte store
+  const bool vec = mi == 64 && nj == 64 && (M % VW) == 0 && ((uintptr_t)C % 16) == 0;
+  if (vec) {
+    typedef TC vt __attribute__((ext_vector_type(VW)));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      TC* col = C + (i0 + ti) + M * (j0 + tj + v);
+#pragma unroll
+      for (int u0 = 0; u0 < 4; u0 += VW) {
+        vt x;
+#pragma unroll
+        for (int q = 0; q < VW; ++q) x[q] = (TC)acc[u0 + q][v];
+        __builtin_nontemporal_store(x, reinterpret_cast<vt*>(col + u0));
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -185,10 +209,14 @@ hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f
   const int64_t gx = (M + 63) / 64, gy = (N + 63) / 64;
   if (gy > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)gx, (unsigned)gy);
-  if (c_f32)
-    TT_LAUNCH((k_gemm_smallk<float>), grid, dim3(kThreads), 0, st, A, B, (float*)C, M, N, K);
-  else
-    TT_LAUNCH((k_gemm_smallk<double>), grid, dim3(kThreads), 0, st, A, B, (double*)C, M, N, K);
+#define TT_GSK(TCV, KBV) \
+  TT_LAUNCH((k_gemm_smallk<TCV, KBV>), grid, dim3(kThreads), 0, st, A, B, (TCV*)C, M, N, K)
+  if (c_f32) {
+    if (K <= 16) TT_GSK(float, 16); else if (K <= 32) TT_GSK(float, 32); else TT_GSK(float, 64);
+  } else {
+    if (K <= 16) TT_GSK(double, 16); else if (K <= 32) TT_GSK(double, 32); else TT_GSK(double, 64);
+  }
+#undef TT_GSK
   return hipGetLastError();
 }
 
