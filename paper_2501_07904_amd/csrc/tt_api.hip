@@ -256,11 +256,14 @@ struct Work {
   double* V1;
   double* W;
   double* normA2;
+  double* cpart;   // a carry's per-workgroup sums of squares, summed by the next step's solve
   StepRec* recs;
   size_t bytes;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kCarryParts = 8192;   // bound on the per-workgroup partials of one A*W pass
 
 struct Sizes {
   int64_t carry, Y, U, X, part, V1;
@@ -323,6 +326,7 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.V1 = (double*)take(z.V1 * 8);
   W.W = (double*)take((size_t)kCMax * kCMax * 8);
   W.normA2 = (double*)take(64);
+  W.cpart = (double*)take((size_t)kCarryParts * 8);
   W.recs = (StepRec*)take(sizeof(StepRec) * (size_t)d);
   W.bytes = off;
   return off;
@@ -349,7 +353,7 @@ struct StepIO {
 };
 
 int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
-             const StepRec* prev, const Work& W, hipStream_t st, Prof& PF, bool retry) {
+             StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF, bool retry) {
   SolveArgs a{};
   a.n = s.n;
   a.ell = ell;
@@ -371,6 +375,12 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   a.normA2 = W.normA2;
   a.first = first ? 1 : 0;
   a.normC2_src = first ? nullptr : &prev->carry2;
+  if (!first && prev_parts > 0) {
+    // the previous carry's sum of squares is still in partials: the solve reduces it
+    a.nc_parts = W.cpart;
+    a.nc_n = prev_parts;
+    a.nc_out = &prev->carry2;
+  }
   const int64_t m = s.m;
   const int n = s.n;
   StepRec* rec = W.recs + si;
@@ -515,24 +525,29 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   return TT_OK;
 }
 
+// defer_norm: leave ||carry||^2 as per-workgroup partials in W.cpart for the
+// next step's solve to reduce (*parts_out = their count, else 0).
 int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io, const Work& W,
-               StepRec* rec, hipStream_t st, Prof& PF) {
+               StepRec* rec, hipStream_t st, Prof& PF, bool defer_norm, int* parts_out) {
   const int64_t m = s.m;
   const int ach = step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r);
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double so = io.out_f32 ? 4.0 : 8.0;
   const double mr = (double)m * r;
   double* rerr = io.out_f32 ? W.part + 8192 : nullptr;
+  const bool defer = defer_norm && ach <= kCarryParts;
+  double* nparts = defer ? W.cpart : W.part;
+  *parts_out = defer ? ach : 0;
   if (step_gram(P, s)) {
     const double mn = (double)m * s.n;
     LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)s.n * r * 8, 2.0 * mn * r,
-           launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, W.part, rerr, st));
+           launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, nparts, rerr, st));
   } else {
     const double ml = (double)m * ell;
     LAUNCH(PF, KC_CARRY, ml * 8 + mr * so + (double)ell * r * 8, 2.0 * ml * r,
-           launch_ax(W.Y, 0, W.W, io.out, io.out_f32, m, ell, r, s.layout, ach, nullptr, W.part, rerr, st));
+           launch_ax(W.Y, 0, W.W, io.out, io.out_f32, m, ell, r, s.layout, ach, nullptr, nparts, rerr, st));
   }
-  LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, &rec->carry2, nullptr, st));
+  if (!defer) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, &rec->carry2, nullptr, st));
   if (rerr) LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(rerr, ach, 1, &rec->rho2, nullptr, st));
   if (P.o.exact_delta) {
     const int rch = resid_chunks(m);
@@ -624,6 +639,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   const void* curA = A;
   int a_f32 = (dtype == TT_F32);
   int prev_r = 0;
+  int prev_parts = 0;   // partials of the previous carry's ||.||^2 left for this step's solve
   bool all_sat = true;
   std::vector<StepRec> host(nsteps);
   for (int si = 0; si < nsteps; ++si) {
@@ -646,7 +662,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     int r;
     bool retry = false;
     while (true) {
-      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, W, st, PF, retry);
+      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, prev_parts, W, st, PF, retry);
       retry = true;
       if (rc) return rc;
       if (P.fixed) { r = std::min(s.r, ell); break; }
@@ -660,7 +676,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       }
       ell = std::min(2 * ell, lim);
     }
-    rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF);
+    // the last carry's norm is reduced at once (no later solve reads it)
+    rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF, !last, &prev_parts);
     if (rc) return rc;
     ells[si] = ell;
     rs[si] = r;

@@ -105,6 +105,13 @@ struct SolveArgs {
   const double* normC2_src;  // NULL: take trace(H) (Gram mode, first step)
   double* normA2;            // ||A||^2 (written on the first step, read for eps_k)
   int first;
+  // When set, ||C||^2 of this step is the previous carry's sum of squares still
+  // held as nc_n per-workgroup partials: the solve sums them (fixed order) and
+  // also stores the sum at nc_out (the previous step's record); normC2_src is
+  // then not read.
+  const double* nc_parts;
+  int nc_n;
+  double* nc_out;
 };
 // Gram mode (n <= kGramMax): H = A^T A (n x n column-major).
 hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st);

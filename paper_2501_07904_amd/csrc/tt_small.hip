@@ -103,6 +103,18 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// ||C||^2 of a step: the previous carry's partial sums of squares reduced by
+// the whole block (strided per thread, then block_sum: a fixed order), or the
+// stored value.  Every thread gets the result; thread 0 records the sum.
+__device__ __forceinline__ double step_norm2(const SolveArgs& a, double* sh) {
+  if (!a.nc_parts) return *a.normC2_src;
+  double v = 0.0;
+  for (int e = threadIdx.x; e < a.nc_n; e += kThreads) v += a.nc_parts[e];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) *a.nc_out = s;
+  return s;
+}
+
 // --------------------------------------------------------------------------
 // SplitMix64: the t-th output from state `seed` is the xor-shift-multiply
 // finaliser applied to seed + t * golden-ratio increment.
@@ -651,10 +663,11 @@ __global__ __launch_bounds__(kThreads) void k_gram_solve(const double* __restric
     for (int e = t; e < n * L; e += kThreads) X[(e % n) + (e / n) * kLd] = sketch_row_entry(a, e % n, e / n);
   }
   __syncthreads();
+  const double prev_nc2 = (a.nc_parts || a.normC2_src) ? step_norm2(a, sh) : 0.0;
   if (t == 0) {
     double tr = 0.0;
     for (int i = 0; i < n; ++i) tr += sH[i + i * kLd];
-    const double nc2 = a.normC2_src ? *a.normC2_src : tr;
+    const double nc2 = (a.nc_parts || a.normC2_src) ? prev_nc2 : tr;
     snormC2 = nc2;
     if (a.first) *a.normA2 = nc2;
   }
@@ -792,7 +805,10 @@ __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restric
     const int i = e % L, j = e / L;
     sK[i + j * kLd] = 0.5 * (K[i + (int64_t)L * j] + K[j + (int64_t)L * i]);
   }
-  if (t == 0) snormC2 = *a.normC2_src;
+  {
+    const double nc2 = step_norm2(a, sh);
+    if (t == 0) snormC2 = nc2;
+  }
   __syncthreads();
   const int sweeps = jacobi_eig<kRRThreads>(sK, sK2, sZ, L, lam, perm, sh, &flag);
   if (t == 0) {
@@ -931,7 +947,10 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restr
     const int i = e % L, j = e / L;
     sE[i + j * kLd] = 0.5 * (E[i + (int64_t)L * j] + E[j + (int64_t)L * i]);
   }
-  if (t == 0) snormC2 = *a.normC2_src;
+  {
+    const double nc2 = step_norm2(a, sh);
+    if (t == 0) snormC2 = nc2;
+  }
   __syncthreads();
   const int sweeps = jacobi_eig<kRRThreads>(sE, sK2, sW, L, lam, perm, sh, &flag);
   if (t == 0) {
