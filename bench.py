@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of a kernel class, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # workload scaled by the copy-probe factors (profiles/c2_order5_32_fp64_tturv_r2l.md); set to None
 # whenever the class's kernels change after the counters were taken
-MEASURED_TRAFFIC = {"tall_atb": 76.54e6, "tall_ax": 49.03e6}
+MEASURED_TRAFFIC = {"tall_atb": 76.49e6, "tall_ax": 49.03e6}
 FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
