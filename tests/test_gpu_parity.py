@@ -311,6 +311,24 @@ def test_eps_mode_function_tensor(sweep, variant):
         np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-3, atol=1e-3 * eps * orep["norm_A"])
 
 
+@pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
+def test_eps_mode_retries_and_step_norms(sweep, variant):
+    """Prescribed accuracy with a small oversampling, so that later steps widen
+    their sketch and run their solve again (the same widths as the oracle's);
+    each step's ||C|| is the previous carry's norm, summed from per-workgroup
+    partials inside the next solve, and the step errors come from
+    ||C||^2 - ||carry||^2: both against the oracle.  The noise makes the step
+    norms differ by ~1e-6 relative, so a norm taken from the wrong step fails."""
+    dims = [10, 12, 14, 12, 10]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 9, 12, 6], 3e-3, 303)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, eps=3e-2, q=1, p=2, seed=4)
+    assert rep["ranks"] == orep["ranks"] == [1, 3, 9, 12, 6, 1]
+    assert rep["ell"] == orep["ell"]   # the oracle widens in the same steps (ell 5 -> 10 in L2R step 2)
+    np.testing.assert_allclose(rep["normC"], orep["normC"], rtol=1e-12)
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
+    _compare_conditioned(cores, oc, orep["s"], sweep)
+
+
 def test_eps_mode_fp32_input_c3_shape():
     """8^8 FP32 function tensor at eps = 1e-6 through the plain FP64 path:
     the oracle sees the same FP32-rounded tensor in FP64."""
