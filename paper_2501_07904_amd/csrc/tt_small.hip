@@ -789,6 +789,7 @@ static void launch_orth_reg(double* M, double* X, int n, int c, hipStream_t st) 
 // K = Z diag(lam) Z^T, rank decision, V1 = X Z_r (core side), W = Z_r so that
 // the carry A V1 equals Y W.
 constexpr int kRRThreads = 1024;  // measured: 16 waves finish a Jacobi round faster than 4
+static_assert(kRRThreads == kThreads, "block_sum and step_norm2 assume kThreads threads per block");
 
 __global__ __launch_bounds__(kRRThreads) void k_rr_solve(const double* __restrict__ K,
                                                          const double* __restrict__ X, SolveArgs a) {
