@@ -41,7 +41,8 @@ extern "C" {
 #define TT_EINVAL (-1)        /* bad argument: dims, ranks, enum value, null pointer */
 #define TT_ENOSPC (-2)        /* workspace smaller than tt_utv_workspace reported */
 #define TT_ERANK (-3)         /* eps not reachable within max_rank; cores and report still written */
-#define TT_ENONFINITE (-4)    /* input holds NaN or Inf (detected from ||A||_F) */
+#define TT_ENONFINITE (-4)    /* input holds NaN or Inf (detected from ||A||_F after the
+                                 first pass over A; the sweep stops there) */
 #define TT_EHIP (-5)          /* a HIP runtime call failed */
 #define TT_EUNSUPPORTED (-6)  /* valid request outside the library's limits (e.g. ell > 64) */
 
@@ -88,9 +89,16 @@ typedef struct {
  * of every pass after the first); the power products run on FP32 matrix cores
  * (FP32 operands and accumulation); the final Rayleigh-Ritz pass reads A with
  * FP64 accumulation, and its Gram matrix, the factorisations and the rank rule
- * stay FP64.  Storing carry k in FP32 perturbs it by rho_k (measured exactly);
- * the report's err_bound is then sqrt(sum delta_k^2) + sum rho_k (sum delta_k
- * + sum rho_k for Alg. 4).
+ * stay FP64.  Steps whose core side n is at most 64 form A^T A in one FP64
+ * pass (it decides the rank and must be accurate to eps^2) and run no
+ * low-precision product: there the mixed form differs from TT_PREC_FP64 only
+ * in the FP32 storage of the carry.  Storing carry k in FP32 perturbs it by
+ * rho_k <= 2^-24 ||carry_k|| (measured exactly); the report's err_bound is then
+ * sqrt(sum delta_k^2) + sum rho_k (sum delta_k + sum rho_k for Alg. 4).  With
+ * a prescribed accuracy the rank rule aims at eps - (d-2) 2^-24 (the a-priori
+ * budget of the d-2 FP32 carries), so err_bound <= eps ||A||_F still holds;
+ * eps at or below that budget is rejected (TT_EINVAL), and a bound above
+ * eps ||A||_F clears rank_rule_met and returns TT_ERANK.
  * TT_PREC_MIXED_BF16: as TT_PREC_MIXED with the power products on BF16
  * operands (FP32 accumulation): the sketch resolves singular directions only
  * to about 4e-3 of the largest, which costs rank (or, under a rank cap, the
@@ -174,6 +182,25 @@ int tt_reconstruct_workspace(int d, const int64_t* dims, const int64_t* ranks, s
 int tt_reconstruct(int d, const int64_t* dims, const int64_t* ranks,
                    const double* const* cores, void* out, tt_dtype dtype,
                    void* work, size_t work_bytes, void* stream);
+
+/* Device bytes of workspace tt_reconstruct_backward needs for this train. */
+int tt_reconstruct_backward_workspace(int d, const int64_t* dims, const int64_t* ranks, size_t* bytes);
+
+/* Gradient of L = <gout, A_TT> with respect to every core, A_TT the dense
+ * tensor of Eq. (TT) (Sec. 2.1): dL/dG_k(a, i, b) = sum over the modes before
+ * and after k of Left_k(p, a) gout(p, i, q) Right_k(b, q), Left_k and Right_k
+ * the products of the cores before and after k.  gout: device, prod(dims)
+ * elements of `dtype` in ivec order (the upstream gradient of tt_reconstruct);
+ * gcores[k]: device, r_{k-1} I_k r_k doubles, overwritten with dL/dG_k in the
+ * core layout above; cores: FP64, every r_k <= 64.  The partial products of
+ * the train are recomputed from the cores (nothing is kept from a forward
+ * call): gout is read twice (gout Right^T and Left^T gout at one split of the
+ * train), then the chain rule runs back through the smaller partial products.
+ * Sums run in a fixed order (bitwise reproducible).  work: device workspace of
+ * tt_reconstruct_backward_workspace bytes.  Enqueues only. */
+int tt_reconstruct_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                            const void* gout, tt_dtype dtype, double* const* gcores, void* work,
+                            size_t work_bytes, void* stream);
 
 /* Entries of the train at N multi-indices, Eq. (TT).  idx: device, N x d
  * int64 row-major, 0-based, each i_k < I_k (not checked on the device: the

@@ -8,5 +8,5 @@ from .ttutv_oracle import (  # noqa: F401
     sketch_gaussian, splitmix64, tt_utv, tt_svd, tt_reconstruct, tt_sample,
     tt_sample_grad, step_tall_view, canonical_signs, completion_step,
     left_orthogonalize, right_orthogonalize, tt_sample_grad_mixed, riemannian_gradient, tangent_train,
-    rgrad_step,
+    rgrad_step, tt_reconstruct_grad,
 )

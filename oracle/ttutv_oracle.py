@@ -30,6 +30,8 @@ Function -> passage -> pin (see tests/test_oracle.py):
   tt_reconstruct     Eq. (TT)                                    closed-form rank-2 TT of a sum
   tt_sample          Eq. (TT) at given multi-indices             equals reconstruct at those entries
   tt_sample_grad     gradient of a weighted sum of sampled entries   central finite differences
+  tt_reconstruct_grad  gradient of <gout, A_TT> (dense gout)      central differences, Euler's identity,
+                                                                 equals tt_sample_grad for a sparse gout
 """
 import math
 
@@ -380,9 +382,26 @@ def _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank):
     return cores, rep
 
 
+def _svd(M):
+    """Thin SVD M = U diag(s) Vt by LAPACK.  For a strongly rectangular M it is
+    taken through a QR factorisation first (the R-SVD: M^T = Q R or M = Q R,
+    then the SVD of the small triangle R), which is exact up to rounding and
+    much faster than a direct bidiagonalisation of the long matrix."""
+    n, m = M.shape
+    if m >= 4 * n:
+        Q, R = np.linalg.qr(M.T, mode="reduced")          # M = R^T Q^T
+        Ur, s, Vrt = np.linalg.svd(R.T, full_matrices=False)
+        return Ur, s, Vrt @ Q.T
+    if n >= 4 * m:
+        Q, R = np.linalg.qr(M, mode="reduced")            # M = Q R
+        Ur, s, Vrt = np.linalg.svd(R, full_matrices=False)
+        return Q @ Ur, s, Vrt
+    return np.linalg.svd(M, full_matrices=False)
+
+
 def tt_svd(a, dims, ranks=None, eps=None, sweep="L2R", weights=None, max_rank=None):
     """TT-SVD (Oseledets 2011): the same sweeps with the exact truncated SVD of
-    every unfolding (numpy.linalg.svd); the rank rule is the one after Alg. 2."""
+    every unfolding (LAPACK, through _svd); the rank rule is the one after Alg. 2."""
     dims = [int(x) for x in dims]
     d = len(dims)
     a = _as_flat(a, dims)
@@ -398,14 +417,14 @@ def tt_svd(a, dims, ranks=None, eps=None, sweep="L2R", weights=None, max_rank=No
         if sweep == "L2R":
             n = r_carry * dims[k - 1]
             Cm = C.reshape(n, C.size // n, order="F")
-            U, s, Vt = np.linalg.svd(Cm, full_matrices=False)
+            U, s, Vt = _svd(Cm)
             core_vecs, other = U, Vt.T
             target = fixed[k] if fixed else None
             ek = None if fixed else eps_k[k - 1]
         else:
             n = dims[k - 1] * r_carry
             Cm = C.reshape(C.size // n, n, order="F")
-            U, s, Vt = np.linalg.svd(Cm, full_matrices=False)
+            U, s, Vt = _svd(Cm)
             core_vecs, other = Vt.T, U
             target = fixed[k - 1] if fixed else None
             ek = None if fixed else eps_k[k - 2]
@@ -453,6 +472,42 @@ def tt_reconstruct(cores):
         T = T @ g.reshape(rk_1, Ik * rk, order="F")                        # (P, I_k r_k)
         T = T.reshape(-1, rk, order="F")                                    # (P I_k, r_k)
     return T.reshape(-1, order="F")
+
+
+def _left_interface(cores, k):
+    """Product of cores 1..k-1 (0-based: cores[:k]) as a (I_1..I_{k-1}) x r_{k-1}
+    matrix, rows in ivec order; the 1 x 1 identity for k = 0."""
+    T = np.ones((1, 1))
+    for g in cores[:k]:
+        rk_1, Ik, rk = g.shape
+        T = (T @ g.reshape(rk_1, Ik * rk, order="F")).reshape(-1, rk, order="F")
+    return T
+
+
+def _right_interface(cores, k):
+    """Product of cores k+1..d (0-based: cores[k+1:]) as an r_k x (I_{k+1}..I_d)
+    matrix, columns in ivec order; the 1 x 1 identity for k = d-1."""
+    T = np.ones((1, 1))
+    for g in reversed(cores[k + 1:]):
+        rk_1, Ik, rk = g.shape
+        T = (g.reshape(rk_1 * Ik, rk, order="F") @ T).reshape(rk_1, -1, order="F")
+    return T
+
+
+def tt_reconstruct_grad(cores, gout):
+    """Gradients of L = <gout, A_TT> (gout a dense tensor, flat in ivec order)
+    with respect to every core, from Eq. (TT): A_TT(p, i, q) = sum_{a,b}
+    Left_k(p, a) G_k(a, i, b) Right_k(b, q) with p the modes before k and q
+    the modes after it, so dL/dG_k(a, i, b) = sum_{p,q} Left_k(p, a) gout(p, i, q)
+    Right_k(b, q)."""
+    gout = np.asarray(gout, dtype=np.float64).reshape(-1, order="F")
+    grads = []
+    for k, g in enumerate(cores):
+        Lk = _left_interface(cores, k)                   # (P, r_{k-1})
+        Rk = _right_interface(cores, k)                  # (r_k, Q)
+        G3 = gout.reshape(Lk.shape[0], g.shape[1], Rk.shape[1], order="F")   # (P, I_k, Q)
+        grads.append(np.einsum("pa,piq,bq->aib", Lk, G3, Rk, optimize=True))
+    return grads
 
 
 def tt_sample(cores, idx):

@@ -21,7 +21,8 @@ SWEEPS = {"L2R": 0, "R2L": 1}
 VARIANTS = {"ULV": 0, "URV": 1, "SVD": 2}
 DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose",
-           "tt_reconstruct_workspace", "tt_reconstruct", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed",
+           "tt_reconstruct_workspace", "tt_reconstruct", "tt_reconstruct_backward_workspace",
+           "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed",
            "tt_last_error", "tt_kernel_class_name"]
 
 
@@ -82,13 +83,16 @@ def load_library(path=LIB_PATH):
     lib.tt_reconstruct_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(ctypes.c_size_t)]
     lib.tt_reconstruct.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int, vp,
                                    ctypes.c_size_t, vp]
+    lib.tt_reconstruct_backward_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(ctypes.c_size_t)]
+    lib.tt_reconstruct_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int,
+                                            ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
     lib.tt_sample.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp, vp]
     lib.tt_sample_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp,
                                        ctypes.POINTER(vp), vp]
     lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
                                              ctypes.c_int64, vp, ctypes.POINTER(vp), vp]
     for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_reconstruct_workspace",
-                 "tt_reconstruct", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed"):
+                 "tt_reconstruct", "tt_reconstruct_backward_workspace", "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -113,6 +117,49 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _numel(dims):
+    n = 1
+    for x in dims:
+        n *= int(x)
+    return n
+
+
+def _check_tensor_size(A, dims):
+    if A.numel() != _numel(dims):
+        raise ValueError(f"A has {A.numel()} elements, dims {list(dims)} need {_numel(dims)}")
+
+
+def check_indices(idx, dims, device=None):
+    """Validate sampling indices before they reach a kernel: an (N, d) int64
+    tensor with 0 <= idx[:, k] < dims[k] (one min/max reduction per mode; the
+    kernels use the indices as addresses), on `device` when given.  Returns
+    the contiguous int64 tensor."""
+    d = len(dims)
+    if device is not None and (not idx.is_cuda or idx.device != device):
+        raise ValueError(f"idx must be a tensor on {device}, got {idx.device}")
+    if idx.dim() != 2 or idx.shape[1] != d:
+        raise ValueError(f"idx must have shape (N, {d}), got {tuple(idx.shape)}")
+    if idx.dtype.is_floating_point or idx.dtype.is_complex or idx.dtype == torch.bool:
+        raise ValueError(f"idx must hold integers, got {idx.dtype}")
+    idx = idx.contiguous().to(torch.int64)
+    if idx.shape[0] > 0:
+        lo = idx.amin(dim=0).tolist()
+        hi = idx.amax(dim=0).tolist()
+        for k in range(d):
+            if lo[k] < 0 or hi[k] >= dims[k]:
+                raise ValueError(f"idx[:, {k}] spans [{lo[k]}, {hi[k]}], outside [0, {dims[k] - 1}]")
+    return idx
+
+
+def check_gout(gout, n, device=None):
+    """Validate the upstream gradient of N sampled entries (N values on `device`)."""
+    if device is not None and (not gout.is_cuda or gout.device != device):
+        raise ValueError(f"gout must be a tensor on {device}, got {gout.device}")
+    if gout.numel() != n:
+        raise ValueError(f"gout has {gout.numel()} elements for {n} sampled entries")
+    return gout.contiguous().reshape(-1).to(torch.float64)
 
 
 def _full_ranks(ranks, d):
@@ -172,6 +219,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
         raise ValueError("A must be float64 or float32")
     dims = [int(x) for x in dims]
     d = len(dims)
+    _check_tensor_size(A, dims)
     if (ranks is None) == (eps is None):
         raise ValueError("give exactly one of ranks and eps")
     o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata)
@@ -242,11 +290,37 @@ def tt_reconstruct(cores, dtype=torch.float64, stream=None):
     return out
 
 
+def tt_reconstruct_backward(cores, gout, stream=None):
+    """Core gradients of <gout, A_TT> for a dense upstream gradient gout (flat,
+    ivec order, float64 or float32, on the device); list of (r0, I, r1)
+    float64 tensors."""
+    lib = load_library()
+    dims, ranks = _train_shape(cores)
+    d = len(dims)
+    dev = cores[0].device
+    if not gout.is_cuda or gout.device != dev:
+        raise ValueError(f"gout must be a tensor on {dev}, got {gout.device}")
+    if gout.dtype not in DTYPES:
+        raise ValueError("gout must be float64 or float32")
+    if gout.numel() != _numel(dims):
+        raise ValueError(f"gout has {gout.numel()} elements, the train has {_numel(dims)}")
+    gout = gout.contiguous()
+    bufs = _core_buffers(cores)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.tt_reconstruct_backward_workspace(d, _i64(dims), _i64(ranks), ctypes.byref(nbytes)))
+    work = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+    gflat = [torch.empty_like(b) for b in bufs]
+    _check(lib.tt_reconstruct_backward(d, _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(gout.data_ptr()),
+                                       DTYPES[gout.dtype], _ptrs(gflat), ctypes.c_void_p(work.data_ptr()),
+                                       nbytes.value, _stream(stream)))
+    return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(d)]
+
+
 def tt_sample(cores, idx, stream=None):
     """Train entries at the rows of idx (N x d int64, 0-based, on the device)."""
     lib = load_library()
     dims, ranks = _train_shape(cores)
-    idx = idx.contiguous().to(torch.int64)
+    idx = check_indices(idx, dims, cores[0].device)
     N = idx.shape[0]
     bufs = _core_buffers(cores)
     out = torch.empty(N, dtype=torch.float64, device=cores[0].device)
@@ -259,9 +333,9 @@ def tt_sample_backward(cores, idx, gout, stream=None):
     """Core gradients of sum_s gout[s] * A_TT[idx_s]; list of (r0, I, r1) tensors."""
     lib = load_library()
     dims, ranks = _train_shape(cores)
-    idx = idx.contiguous().to(torch.int64)
-    gout = gout.contiguous().to(torch.float64)
+    idx = check_indices(idx, dims, cores[0].device)
     N = idx.shape[0]
+    gout = check_gout(gout, N, cores[0].device)
     bufs = _core_buffers(cores)
     gflat = [torch.empty_like(b) for b in bufs]
     _check(lib.tt_sample_backward(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()),
@@ -277,9 +351,9 @@ def tt_sample_backward_mixed(left_cores, right_cores, idx, gout, stream=None):
     dims, ranks = _train_shape(left_cores)
     if _train_shape(right_cores) != (dims, ranks):
         raise ValueError("left and right cores must describe trains of the same shape and ranks")
-    idx = idx.contiguous().to(torch.int64)
-    gout = gout.contiguous().to(torch.float64)
+    idx = check_indices(idx, dims, left_cores[0].device)
     N = idx.shape[0]
+    gout = check_gout(gout, N, left_cores[0].device)
     lb, rb = _core_buffers(left_cores), _core_buffers(right_cores)
     gflat = [torch.empty_like(b) for b in lb]
     _check(lib.tt_sample_backward_mixed(len(dims), _i64(dims), _i64(ranks), _ptrs(lb), _ptrs(rb),
@@ -302,6 +376,23 @@ class TTSample(torch.autograd.Function):
         idx, *cores = ctx.saved_tensors
         grads = tt_sample_backward(list(cores), idx, gout)
         return (None, *[g.to(c.dtype) for g, c in zip(grads, cores)])
+
+
+class TTReconstruct(torch.autograd.Function):
+    """The dense tensor of a train (flat, ivec order) as a differentiable
+    function of its cores; the backward is the hand-written
+    tt_reconstruct_backward (partial products recomputed, not stored)."""
+
+    @staticmethod
+    def forward(ctx, *cores):
+        ctx.save_for_backward(*cores)
+        return tt_reconstruct(list(cores))
+
+    @staticmethod
+    def backward(ctx, gout):
+        cores = ctx.saved_tensors
+        grads = tt_reconstruct_backward(list(cores), gout)
+        return tuple(g.to(c.dtype) for g, c in zip(grads, cores))
 
 
 class Decomposer:
@@ -338,8 +429,9 @@ class Decomposer:
         self.rep = tt_report()
 
     def __call__(self, A, stream=None, allow_rank_miss=False):
-        if A.dtype != self.dtype or not A.is_contiguous():
-            raise ValueError("A must be contiguous with the planned dtype")
+        if A.dtype != self.dtype or not A.is_contiguous() or not A.is_cuda:
+            raise ValueError("A must be a contiguous device tensor with the planned dtype")
+        _check_tensor_size(A, self.dims)
         rc = self.lib.tt_utv_decompose(ctypes.c_void_p(A.data_ptr()), DTYPES[self.dtype], self.d, self._dims,
                                        self._ranks, self.eps, self.sweep, self.variant, ctypes.byref(self.opts),
                                        ctypes.c_void_p(self.work.data_ptr()), self.work_bytes, self._cores,

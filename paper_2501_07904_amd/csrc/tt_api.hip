@@ -105,6 +105,7 @@ struct Problem {
   bool fixed;
   int64_t ranks[TT_MAX_D + 1];  // fixed: given ranks; eps: caps
   double eps;
+  double eps_rule;   // eps the per-step rank rule targets (eps less the FP32 carry budget, mixed forms)
   tt_sweep sweep;
   tt_variant variant;
   tt_dtype dtype;
@@ -175,6 +176,20 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
       sw += wk * wk;
     }
     if (P.o.weights && fabs(sw - 1.0) > 1e-9) return fail(TT_EINVAL, "sum of squared weights is %g, not 1", sw);
+    // Mixed forms store the d-2 intermediate carries in FP32.  Rounding to
+    // nearest perturbs carry k by rho_k <= 2^-24 ||carry_k|| <= 2^-24 ||A|| (the
+    // carries are orthogonal projections of the unfoldings, hence no larger than
+    // A, up to the earlier rho), and the reported bound is sqrt(sum delta^2) +
+    // sum rho (sum delta + sum rho for Alg. 4).  The steps' rank rule therefore
+    // aims at eps less this a-priori budget, so that the bound stays <= eps.
+    P.eps_rule = P.eps;
+    if (P.mixed) {
+      const double budget = (double)(d - 2) * ldexp(1.0, -24) * 1.001;
+      P.eps_rule = P.eps - budget;
+      if (d > 2 && !(P.eps_rule > 0.0))
+        return fail(TT_EINVAL, "eps = %g is not above the FP32 carry rounding budget %g of the mixed form", P.eps,
+                    budget);
+    }
   }
   return TT_OK;
 }
@@ -365,7 +380,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   a.mode_fastest = s.mode_fastest;
   a.r_fixed = P.fixed ? s.r : 0;
   const double wk = P.fixed ? 0.0 : P.w[s.unfolding - 1];
-  a.eps_factor2 = wk * P.eps * wk * P.eps;
+  a.eps_factor2 = wk * P.eps_rule * wk * P.eps_rule;
   a.max_rank = P.fixed ? 0 : (int)std::min<int64_t>(s.r, TT_MAX_ELL);
   a.core_layout = (P.sweep == TT_L2R) ? 0 : 1;
   a.core = io.core;
@@ -663,11 +678,30 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     bool retry = false;
     while (true) {
       rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, prev_parts, W, st, PF, retry);
-      retry = true;
       if (rc) return rc;
+      // ||A||^2 is known after the first pass over A: a non-finite input stops
+      // the sweep here instead of running every step on NaNs
+      if (first && !retry) {
+        double nA2_first = 0.0;
+        HIP_OK(hipMemcpyAsync(&nA2_first, W.normA2, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (!P.fixed) HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (!isfinite(nA2_first)) {
+          if (rep) {
+            memset(rep, 0, sizeof(*rep));
+            rep->d = d;
+            rep->norm_A = nA2_first;
+          }
+          return fail(TT_ENONFINITE, "input holds non-finite values (||A||^2 = %g after the first pass)", nA2_first);
+        }
+      }
+      const bool synced = first && !retry;
+      retry = true;
       if (P.fixed) { r = std::min(s.r, ell); break; }
-      HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));
-      HIP_OK(hipStreamSynchronize(st));
+      if (!synced) {
+        HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+      }
       r = host[si].r;
       const int lim = (int)std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
       if (host[si].sat || ell >= lim || (s.r > 0 && r >= s.r)) {
@@ -691,6 +725,20 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   double nA2 = 0.0;
   HIP_OK(hipMemcpyAsync(&nA2, W.normA2, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
+  // the bound the report states; in eps mode it must not exceed eps ||A||
+  {
+    double sum2 = 0.0, sum1 = 0.0, rho_sum = 0.0;
+    for (int si = 0; si < nsteps; ++si) {
+      const StepRec& h = host[si];
+      double dl2 = (h.resid2 >= 0.0) ? h.resid2 : h.normC2 - h.carry2;
+      if (dl2 < 0.0) dl2 = 0.0;
+      sum2 += dl2;
+      sum1 += sqrt(dl2);
+      rho_sum += sqrt(std::max(h.rho2, 0.0));
+    }
+    const double bound = (P.alg4 ? sum1 : sqrt(sum2)) + rho_sum;
+    if (!P.fixed && !(bound <= P.eps * sqrt(std::max(nA2, 0.0)))) all_sat = false;
+  }
   if (rep) {
     memset(rep, 0, sizeof(*rep));
     rep->d = d;
@@ -816,6 +864,157 @@ int tt_reconstruct(int d, const int64_t* dims, const int64_t* ranks, const doubl
   }
   HIP_OK(launch_gemm_smallk(L, R, out, dtype == TT_F32, prod(dims, 0, h), prod(dims, h, d),
                             (int)ranks[h], st));
+  return TT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Backward of the reconstruction.  With the train split after core h, A =
+// L_h R_{h+1} (L_h: P_h x r_h, the product of cores 1..h; R_{h+1}: r_h x
+// Q_{h+1}, the product of cores h+1..d), and for L = <gout, A>:
+//   dL_h = gout R_{h+1}^T  and  dR_{h+1} = L_h^T gout     (the two passes over gout)
+// then the chain rule back through the partial products, recomputed from the
+// cores (not kept from a forward call):
+//   L_k = L_{k-1} G_k (P_{k-1} x I_k r_k):  dG_k = L_{k-1}^T dL_k,  dL_{k-1} = dL_k G_k^T
+//   R_k = G_k R_{k+1} (r_{k-1} I_k x Q_{k+1}):  dG_k = dR_k R_{k+1}^T,  dR_{k+1} = G_k^T dR_k
+// (dL_k and dR_k read in the reshaped shapes shown).  h is the first split
+// with P_h >= Q_{h+1}, so that gout is a tall matrix for the two passes.
+struct RecBwdPlan {
+  int h;
+  int64_t P[TT_MAX_D + 1];   // P[k] = I_1 ... I_k
+  int64_t Q[TT_MAX_D + 2];   // Q[k] = I_k ... I_d (1-based), Q[d+1] = 1
+  size_t off_L[TT_MAX_D + 1], off_R[TT_MAX_D + 1];
+  size_t off_dL[2], off_dR[2], off_tmp, off_part;
+  int64_t part_len;
+  size_t bytes;
+};
+
+int recbwd_plan(int d, const int64_t* dims, const int64_t* ranks, RecBwdPlan& bp) {
+  if (d < 2 || d > TT_MAX_D || !dims || !ranks) return fail(TT_EINVAL, "bad train description");
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+  for (int k = 0; k < d; ++k)
+    if (dims[k] < 1) return fail(TT_EINVAL, "dims[%d] < 1", k);
+  for (int k = 0; k <= d; ++k)
+    if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
+  bp.P[0] = 1;
+  for (int k = 1; k <= d; ++k) bp.P[k] = bp.P[k - 1] * dims[k - 1];
+  bp.Q[d + 1] = 1;
+  for (int k = d; k >= 1; --k) bp.Q[k] = bp.Q[k + 1] * dims[k - 1];
+  bp.h = d - 1;
+  for (int h = 1; h < d; ++h)
+    if (bp.P[h] >= bp.Q[h + 1]) { bp.h = h; break; }
+  const int h = bp.h;
+  size_t off = 0;
+  auto take = [&](int64_t doubles) { const size_t o = off; off += align_up((size_t)doubles * 8); return o; };
+  for (int k = 2; k <= h; ++k) bp.off_L[k] = take(bp.P[k] * ranks[k]);           // L_k, k = 2..h
+  for (int k = h + 1; k <= d - 1; ++k) bp.off_R[k] = take(ranks[k - 1] * bp.Q[k]);   // R_k, k = h+1..d-1
+  int64_t maxL = 1, maxR = 1;
+  for (int k = 1; k <= h; ++k) maxL = std::max(maxL, bp.P[k] * ranks[k]);
+  for (int k = h + 1; k <= d; ++k) maxR = std::max(maxR, ranks[k - 1] * bp.Q[k]);
+  bp.off_dL[0] = take(maxL);
+  bp.off_dL[1] = take(maxL);
+  bp.off_dR[0] = take(maxR);
+  bp.off_dR[1] = take(maxR);
+  const int64_t Qh = bp.Q[h + 1], rh = ranks[h];
+  bp.off_tmp = take(Qh * rh);
+  // partials: the second pass over gout, and every chain product
+  const int nch = atb2_chunks(bp.P[h], (int)std::min<int64_t>(Qh, 1 << 30));
+  int64_t part = nch > 1 ? (int64_t)nch * Qh * rh : 1;
+  auto gpart = [&](int64_t M, int64_t N, int64_t K) {
+    const int z = gemm_any_splits(M, N, K);
+    if (z > 1) part = std::max(part, (int64_t)z * M * N);
+  };
+  for (int k = h; k >= 2; --k) {
+    gpart(ranks[k - 1], dims[k - 1] * ranks[k], bp.P[k - 1]);
+    gpart(bp.P[k - 1], ranks[k - 1], dims[k - 1] * ranks[k]);
+  }
+  for (int k = h + 1; k <= d - 1; ++k) {
+    gpart(ranks[k - 1] * dims[k - 1], ranks[k], bp.Q[k + 1]);
+    gpart(ranks[k], bp.Q[k + 1], ranks[k - 1] * dims[k - 1]);
+  }
+  bp.part_len = part;
+  bp.off_part = take(part);
+  bp.bytes = off;
+  if (bp.P[h] > (int64_t)1 << 40 || Qh > (1 << 30)) return fail(TT_EUNSUPPORTED, "train too large");
+  return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tt_reconstruct_backward_workspace(int d, const int64_t* dims, const int64_t* ranks, size_t* bytes) {
+  if (!bytes) return fail(TT_EINVAL, "bytes is NULL");
+  RecBwdPlan bp;
+  const int rc = recbwd_plan(d, dims, ranks, bp);
+  if (rc) return rc;
+  *bytes = bp.bytes;
+  return TT_OK;
+}
+
+int tt_reconstruct_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
+                            const void* gout, tt_dtype dtype, double* const* gcores, void* work, size_t work_bytes,
+                            void* stream) {
+  RecBwdPlan bp;
+  int rc = recbwd_plan(d, dims, ranks, bp);
+  if (rc) return rc;
+  if (!cores || !gout || !gcores) return fail(TT_EINVAL, "cores/gout/gcores is NULL");
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "bad dtype");
+  for (int k = 0; k < d; ++k)
+    if (!cores[k] || !gcores[k]) return fail(TT_EINVAL, "cores[%d] or gcores[%d] is NULL", k, k);
+  if (!work || work_bytes < bp.bytes) return fail(TT_ENOSPC, "workspace %zu < %zu", work_bytes, bp.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)work;
+  auto buf = [&](size_t off) { return (double*)(base + off); };
+  const int h = bp.h;
+  const int a_f32 = dtype == TT_F32;
+  double* part = buf(bp.off_part);
+  // left partial products L_2..L_h (L_1 = G_1) and right ones R_{d-1}..R_{h+1} (R_d = G_d)
+  auto Lk = [&](int k) -> const double* { return k == 1 ? cores[0] : buf(bp.off_L[k]); };
+  auto Rk = [&](int k) -> const double* { return k == d ? cores[d - 1] : buf(bp.off_R[k]); };
+  for (int k = 2; k <= h; ++k)
+    HIP_OK(launch_gemm_smallk(Lk(k - 1), cores[k - 1], buf(bp.off_L[k]), 0, bp.P[k - 1], dims[k - 1] * ranks[k],
+                              (int)ranks[k - 1], st));
+  for (int k = d - 1; k >= h + 1; --k)
+    HIP_OK(launch_gemm_smallk(cores[k - 1], Rk(k + 1), buf(bp.off_R[k]), 0, ranks[k - 1] * dims[k - 1], bp.Q[k + 1],
+                              (int)ranks[k], st));
+  const int64_t Ph = bp.P[h], Qh = bp.Q[h + 1];
+  const int rh = (int)ranks[h];
+  // pass 1: dL_h = gout R_{h+1}^T (R_{h+1}, r_h x Q column-major, is the k-major right operand)
+  double* dL = (h == 1) ? gcores[0] : buf(bp.off_dL[h & 1]);
+  HIP_OK(launch_ax(gout, a_f32, Rk(h + 1), dL, 0, Ph, (int)Qh, rh, COL, ax_chunks(Ph, (int)Qh, rh), nullptr,
+                   nullptr, nullptr, st));
+  // pass 2: dR_{h+1}^T = gout^T L_h (Q x r_h), then transposed to r_h x Q
+  {
+    const int nch = atb2_chunks(Ph, (int)Qh);
+    double* tmp = buf(bp.off_tmp);
+    HIP_OK(launch_atb2(gout, a_f32, Lk(h), 0, Ph, (int)Qh, rh, COL, 0, nch == 1 ? tmp : part, nch, st));
+    if (nch > 1) HIP_OK(launch_reduce(part, nch, Qh * rh, tmp, nullptr, st));
+    double* dR = (h + 1 == d) ? gcores[d - 1] : buf(bp.off_dR[(h + 1) & 1]);
+    HIP_OK(launch_transpose(tmp, Qh, rh, dR, st));
+  }
+  // back through the left products: dL_k read as dM (P_{k-1} x I_k r_k)
+  for (int k = h; k >= 2; --k) {
+    const double* dM = buf(bp.off_dL[k & 1]);
+    const int64_t P = bp.P[k - 1], ra = ranks[k - 1], J = dims[k - 1] * ranks[k];
+    // dG_k (r_{k-1} x I_k r_k) = L_{k-1}^T dM
+    HIP_OK(launch_gemm_any(Lk(k - 1), P, 1, dM, 1, P, gcores[k - 1], ra, J, P, part, gemm_any_splits(ra, J, P), st));
+    // dL_{k-1} (P_{k-1} x r_{k-1}) = dM G_k^T (G_k read as r_{k-1} x I_k r_k)
+    double* dst = (k == 2) ? gcores[0] : buf(bp.off_dL[(k - 1) & 1]);
+    HIP_OK(launch_gemm_any(dM, 1, P, cores[k - 1], ra, 1, dst, P, ra, J, part, gemm_any_splits(P, ra, J), st));
+  }
+  // back through the right products: dR_k read as dN (r_{k-1} I_k x Q_{k+1})
+  for (int k = h + 1; k <= d - 1; ++k) {
+    const double* dN = buf(bp.off_dR[k & 1]);
+    const int64_t X = ranks[k - 1] * dims[k - 1], rb = ranks[k], Q = bp.Q[k + 1];
+    // dG_k (r_{k-1} I_k x r_k) = dN R_{k+1}^T
+    HIP_OK(launch_gemm_any(dN, 1, X, Rk(k + 1), rb, 1, gcores[k - 1], X, rb, Q, part, gemm_any_splits(X, rb, Q), st));
+    // dR_{k+1} (r_k x Q_{k+1}) = G_k^T dN (G_k read as r_{k-1} I_k x r_k)
+    double* dst = (k + 1 == d) ? gcores[d - 1] : buf(bp.off_dR[(k + 1) & 1]);
+    HIP_OK(launch_gemm_any(cores[k - 1], X, 1, dN, 1, X, dst, rb, Q, X, part, gemm_any_splits(rb, Q, X), st));
+  }
   return TT_OK;
 }
 

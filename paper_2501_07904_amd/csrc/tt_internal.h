@@ -138,6 +138,15 @@ hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs&
 // C (M x N) = A (M x K) B (K x N), all column-major, K <= kCMax; C is double or float.
 hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f32, int64_t M,
                               int64_t N, int K, hipStream_t st);
+// C (M x N, column-major) = A B with A(m, k) at A[m sam + k sak] and B(k, n)
+// at B[k sbk + n sbn]; the k range is split over `splits` workgroup layers
+// (gemm_any_splits) whose M x N partials (partials: splits * M * N doubles,
+// unused for one split) are summed in a fixed order.
+int gemm_any_splits(int64_t M, int64_t N, int64_t K);
+hipError_t launch_gemm_any(const double* A, int64_t sam, int64_t sak, const double* B, int64_t sbk, int64_t sbn,
+                           double* C, int64_t M, int64_t N, int64_t K, double* partials, int splits, hipStream_t st);
+// out (cols x rows) = in^T (in: rows x cols), both column-major.
+hipError_t launch_transpose(const double* in, int64_t rows, int64_t cols, double* out, hipStream_t st);
 hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
                          const double* const* cores, const int64_t* idx, int64_t N, double* out,
                          hipStream_t st);

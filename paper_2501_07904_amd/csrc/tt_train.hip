@@ -1,6 +1,8 @@
 // Contractions of a tensor train (Eq. (TT)): dense reconstruction as a chain
 // of small-K GEMMs, entries at given multi-indices, and the gradient of a
 // weighted sum of sampled entries with respect to every core.
+#include <algorithm>
+
 #include "tt_internal.h"
 
 namespace ttutv {
@@ -81,6 +83,91 @@ __global__ __launch_bounds__(kThreads) void k_gemm_smallk(const double* __restri
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (ti + u < mi) C[(i0 + ti + u) + M * (j0 + tj + v)] = (TC)acc[u][v];
+  }
+}
+
+// C (M x N, column-major) = sum over k of A(m, k) B(k, n), with A(m, k) at
+// A[m sam + k sak] and B(k, n) at B[k sbk + n sbn]: any transposition of
+// either operand.  Workgroup z of Z takes the k range [z kper, (z+1) kper) and
+// writes its own M x N partial (out + z M N); the partials are then summed in
+// a fixed order, so the result does not depend on timing.  64 x 64 output
+// tile, 4 x 4 per thread, KT-deep operand tiles staged in LDS with the loads
+// mapped along whichever index has unit stride.
+constexpr int kGaKT = 16;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_any(const double* __restrict__ A, int64_t sam, int64_t sak,
+                                                       const double* __restrict__ B, int64_t sbk, int64_t sbn,
+                                                       double* __restrict__ out, int64_t M, int64_t N, int64_t K,
+                                                       int64_t kper) {
+  __shared__ double sA[kGaKT][64 + 1];
+  __shared__ double sB[kGaKT][64 + 1];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  const int64_t kb = (int64_t)blockIdx.z * kper;
+  const int64_t ke = min(K, kb + kper);
+  const bool a_m_fast = sam <= sak, b_k_fast = sbk <= sbn;
+  const int ti = (t % 16) * 4, tj = (t / 16) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t k0 = kb; k0 < ke; k0 += kGaKT) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (64 * kGaKT) / kThreads; ++u) {
+      const int e = t + kThreads * u;
+      int i, k;
+      if (a_m_fast) { i = e % 64; k = e / 64; } else { k = e % kGaKT; i = e / kGaKT; }
+      const int64_t gi = i0 + i, gk = k0 + k;
+      sA[k][i] = (gi < M && gk < ke) ? A[gi * sam + gk * sak] : 0.0;
+      int j, k2;
+      if (b_k_fast) { k2 = e % kGaKT; j = e / kGaKT; } else { j = e % 64; k2 = e / 64; }
+      const int64_t gj = j0 + j, gk2 = k0 + k2;
+      sB[k2][j] = (gj < N && gk2 < ke) ? B[gk2 * sbk + gj * sbn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kGaKT; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = sA[k][ti + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = sB[k][tj + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+  }
+  double* C = out + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t j = j0 + tj + v;
+    if (j >= N) break;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + ti + u;
+      if (i < M) C[i + M * j] = acc[u][v];
+    }
+  }
+}
+
+// out (cols x rows, column-major) = in^T, in rows x cols column-major; 32 x 32
+// tiles through LDS so that both sides are read and written along columns.
+__global__ __launch_bounds__(kThreads) void k_transpose(const double* __restrict__ in, int64_t rows, int64_t cols,
+                                                        double* __restrict__ out) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + tx, c = c0 + y;
+    tile[y][tx] = (r < rows && c < cols) ? in[r + rows * c] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t c = c0 + tx, r = r0 + y;   // out(c, r) at c + cols r
+    if (r < rows && c < cols) out[c + cols * r] = tile[tx][y];
   }
 }
 
@@ -217,6 +304,40 @@ hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f
     if (K <= 16) TT_GSK(double, 16); else if (K <= 32) TT_GSK(double, 32); else TT_GSK(double, 64);
   }
 #undef TT_GSK
+  return hipGetLastError();
+}
+
+int gemm_any_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int64_t s = (K + 255) / 256;                 // at least 256 of k per workgroup
+  const int64_t cap = std::max<int64_t>(1, 1024 / tiles);
+  if (s > cap) s = cap;
+  if (s > 4096) s = 4096;
+  return (int)std::max<int64_t>(s, 1);
+}
+
+hipError_t launch_gemm_any(const double* A, int64_t sam, int64_t sak, const double* B, int64_t sbk, int64_t sbn,
+                           double* C, int64_t M, int64_t N, int64_t K, double* partials, int splits, hipStream_t st) {
+  if (M < 1 || N < 1 || K < 1 || splits < 1) return hipErrorInvalidValue;
+  const int64_t gx = (M + 63) / 64, gy = (N + 63) / 64;
+  if (gy > 65535 || gx > 0x7fffffff || splits > 65535) return hipErrorInvalidValue;
+  int64_t kper = (K + splits - 1) / splits;
+  kper = (kper + kGaKT - 1) / kGaKT * kGaKT;
+  const int z = (int)((K + kper - 1) / kper);   // splits actually used (never an empty one)
+  double* dst = (z == 1) ? C : partials;
+  if (z > 1 && !partials) return hipErrorInvalidValue;
+  TT_LAUNCH(k_gemm_any, dim3((unsigned)gx, (unsigned)gy, (unsigned)z), dim3(kThreads), 0, st, A, sam, sak, B, sbk, sbn,
+            dst, M, N, K, kper);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || z == 1) return e;
+  return launch_reduce(partials, z, M * N, C, nullptr, st);
+}
+
+hipError_t launch_transpose(const double* in, int64_t rows, int64_t cols, double* out, hipStream_t st) {
+  if (rows < 1 || cols < 1) return hipErrorInvalidValue;
+  const int64_t gx = (rows + 31) / 32, gy = (cols + 31) / 32;
+  if (gy > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
+  TT_LAUNCH(k_transpose, dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, st, in, rows, cols, out);
   return hipGetLastError();
 }
 

@@ -77,6 +77,44 @@ def _compare_conditioned(gpu_cores, ora_cores, svals, sweep, tol=1e-8, floor=1e-
     assert checked > 0
 
 
+U64 = 2.0 ** -53
+
+
+def _gram_floor_tol(orep, ranks, sweep):
+    """Tolerance for comparing a prescribed-accuracy reconstruction with the
+    oracle's, relative to ||A||_F.  The library takes the Rayleigh-Ritz
+    factorisation of each step from the eigenvectors of the Gram matrix
+    (AX)^T(AX), whose squared spectrum fixes the kept subspace only to about
+    u s_1^2 / (s_r^2 - s_{r+1}^2) (Davis-Kahan with a Gram perturbation of
+    u s_1^2); turning the subspace by that angle changes the rank-r part C V1
+    V1^T by that angle times s_r.  Summed over the steps (the later steps see
+    the perturbation linearly), with a factor 64 for the dimension-dependent
+    constants of the rounding bounds, floored at the FP64 target 1e-10."""
+    tol = 0.0
+    nA = orep["norm_A"]
+    d = len(ranks) - 1
+    for k in range(d - 1):
+        s = np.asarray(orep["s"][k], dtype=np.float64)
+        r = ranks[k + 1] if sweep == "L2R" else ranks[k + 1]
+        if r >= len(s):
+            continue
+        gap = s[r - 1] ** 2 - s[r] ** 2
+        if gap <= 0:
+            return float("inf")
+        tol += U64 * s[0] ** 2 / gap * s[r - 1] / nA
+    return max(1e-10, 64.0 * tol)
+
+
+def _compare_reconstruction(cores, oc, orep, sweep):
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    orec = oracle.tt_reconstruct(oc)
+    diff = np.linalg.norm(rec - orec) / orep["norm_A"]
+    tol = _gram_floor_tol(orep, orep["ranks"], sweep)
+    print(f"reconstruction vs oracle: {diff:.3e} (tolerance {tol:.3e})", flush=True)
+    assert diff <= tol, (diff, tol)
+    return rec
+
+
 def _run(a, dims, sweep, variant, ranks=None, eps=None, q=1, p=8, seed=0, dtype=np.float64, **kw):
     A = _dev(a.astype(dtype))
     cores, rep = T.tt_utv_decompose(A, dims, ranks=ranks, eps=eps, sweep=sweep, variant=variant, q=q,
@@ -306,7 +344,7 @@ def test_eps_mode_function_tensor(sweep, variant):
         assert rep["ranks"] == orep["ranks"]
         assert rep["rank_rule_met"]
         _compare_conditioned(cores, oc, orep["s"], sweep)
-        rec = T.tt_reconstruct(cores).cpu().numpy()
+        rec = _compare_reconstruction(cores, oc, orep, sweep)
         assert np.linalg.norm(rec - a) / np.linalg.norm(a) <= eps
         np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-3, atol=1e-3 * eps * orep["norm_A"])
 
@@ -327,6 +365,7 @@ def test_eps_mode_retries_and_step_norms(sweep, variant):
     np.testing.assert_allclose(rep["normC"], orep["normC"], rtol=1e-12)
     np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6)
     _compare_conditioned(cores, oc, orep["s"], sweep)
+    _compare_reconstruction(cores, oc, orep, sweep)
 
 
 def test_eps_mode_fp32_input_c3_shape():
@@ -339,9 +378,43 @@ def test_eps_mode_fp32_input_c3_shape():
     oc, orep = oracle.tt_utv(a32.astype(np.float64), dims, eps=1e-6, sweep="R2L", variant="URV", q=1, p=8, seed=3)
     assert rep["ranks"] == orep["ranks"]
     _compare_conditioned(cores, oc, orep["s"], "R2L")
-    rec = T.tt_reconstruct(cores).cpu().numpy()
+    rec = _compare_reconstruction(cores, oc, orep, "R2L")
     a = a32.astype(np.float64)
     assert np.linalg.norm(rec - a) / np.linalg.norm(a) <= 1e-6
+
+
+def test_c5_shape_order5_40_fp32_eps():
+    """The 40^6 workload's recipe one order down (40^5 FP32, 410 MB: Gaussian
+    TT ranks 32 plus 1e-5 noise, eps = 1e-4, TT-URV right-to-left, q = 1,
+    p = 8, rank cap 48), small enough for the oracle: the FP64 form against
+    the oracle through the cores and the reconstruction; the mixed form within
+    its stated bound, which stays below eps."""
+    dims = [40] * 5
+    a, _ = ttgen.gaussian_tt_tensor(dims, [32] * 4, 1e-5, 5)
+    a32 = a.astype(np.float32)
+    a = a32.astype(np.float64)
+    A = _dev(a32)
+    kw = dict(eps=1e-4, sweep="R2L", variant="URV", q=1, oversample=8, seed=5, max_rank=48)
+    print("40^5 FP32: FP64 form", flush=True)
+    cores, rep = T.tt_utv_decompose(A, dims, exact_delta=True, **kw)
+    torch.cuda.synchronize()
+    print("40^5 FP32: oracle", flush=True)
+    oc, orep = oracle.tt_utv(a, dims, eps=1e-4, sweep="R2L", variant="URV", q=1, p=8, seed=5, max_rank=48)
+    assert rep["ranks"] == orep["ranks"] == [1, 32, 32, 32, 32, 1]
+    assert rep["ell"] == orep["ell"]
+    _compare_conditioned(cores, oc, orep["s"], "R2L")
+    rec = _compare_reconstruction(cores, oc, orep, "R2L")
+    err = np.linalg.norm(rec - a)
+    assert err <= rep["err_bound"] * (1 + 1e-9) <= 1e-4 * np.linalg.norm(a)
+    del rec
+    print("40^5 FP32: mixed form", flush=True)
+    cmx, rmx = T.tt_utv_decompose(A, dims, exact_delta=True, prec="mixed", **kw)
+    assert rmx["rank_rule_met"] and rmx["ranks"] == rep["ranks"]
+    recmx = T.tt_reconstruct(cmx).cpu().numpy()
+    errmx = np.linalg.norm(recmx - a)
+    print(f"40^5 mixed: error {errmx / np.linalg.norm(a):.4e}, bound {rmx['err_bound'] / rmx['norm_A']:.4e}",
+          flush=True)
+    assert errmx <= rmx["err_bound"] * (1 + 1e-9) <= 1e-4 * rmx["norm_A"] * (1 + 1e-12)
 
 
 def test_eps_rank_cap_reports_erank():

@@ -113,6 +113,46 @@ def test_sample_grad_finite_differences():
         np.testing.assert_allclose(grads[k], fd, rtol=1e-6, atol=1e-7)
 
 
+def test_reconstruct_grad_finite_differences():
+    """<gout, A_TT> is linear in each core, so central differences of it are
+    exact up to rounding: every entry of every core gradient is checked."""
+    dims, ranks = [3, 4, 2, 5], [1, 2, 3, 2, 1]
+    cores = ttgen.gaussian_cores(dims, ranks, 7)
+    rng = np.random.default_rng(8)
+    gout = rng.standard_normal(int(np.prod(dims)))
+    grads = oracle.tt_reconstruct_grad(cores, gout)
+    h = 1e-6
+    for k in range(len(cores)):
+        assert grads[k].shape == cores[k].shape
+        fd = np.zeros_like(cores[k])
+        for pos in np.ndindex(*cores[k].shape):
+            cp = [c.copy() for c in cores]; cp[k][pos] += h
+            cm = [c.copy() for c in cores]; cm[k][pos] -= h
+            fd[pos] = (gout @ oracle.tt_reconstruct(cp) - gout @ oracle.tt_reconstruct(cm)) / (2 * h)
+        np.testing.assert_allclose(grads[k], fd, rtol=1e-7, atol=1e-8)
+
+
+def test_reconstruct_grad_euler_identity_and_sparse_gout():
+    """A_TT is homogeneous of degree one in each core, so sum_k <dL/dG_k, G_k>
+    = d <gout, A_TT> (Euler); with gout a weighted sum of unit tensors the dense
+    gradient is the sampled-entry gradient (itself pinned by differences)."""
+    dims, ranks = [4, 3, 5, 2, 3], [1, 3, 2, 4, 2, 1]
+    cores = ttgen.gaussian_cores(dims, ranks, 17)
+    rng = np.random.default_rng(18)
+    gout = rng.standard_normal(int(np.prod(dims)))
+    grads = oracle.tt_reconstruct_grad(cores, gout)
+    lhs = sum(float(np.sum(g * c)) for g, c in zip(grads, cores))
+    assert lhs == pytest.approx(len(dims) * float(gout @ oracle.tt_reconstruct(cores)), rel=1e-12)
+    # sparse gout: 25 entries (some repeated) with weights
+    idx = np.stack([rng.integers(0, I, 25) for I in dims], axis=1)
+    w = rng.standard_normal(25)
+    dense = np.zeros(int(np.prod(dims)))
+    flat = np.ravel_multi_index(idx.T, dims, order="F")
+    np.add.at(dense, flat, w)
+    for g1, g2 in zip(oracle.tt_reconstruct_grad(cores, dense), oracle.tt_sample_grad(cores, idx, w)):
+        np.testing.assert_allclose(g1, g2, rtol=1e-12, atol=1e-12)
+
+
 # ---------------------------------------------------------------- sweeps
 @pytest.mark.parametrize("sweep,variant", COMBOS + [("L2R", "SVD"), ("R2L", "SVD")])
 def test_exact_tt_rank_reconstructs(sweep, variant):
@@ -146,6 +186,45 @@ def test_alg4_sum_bound():
         err = np.linalg.norm(oracle.tt_reconstruct(cores) - a)
         assert err <= np.sum(rep["delta"]) * (1 + 1e-12)
         assert rep["err_bound"] == pytest.approx(np.sum(rep["delta"]))
+
+
+def test_alg4_step_is_a_ulv_with_range_side_orthogonality():
+    """Alg. 4 (appendix): each step is a truncated ULV with the orthogonality on
+    the range side, C = U1 S_r V1^T + E with U1^T E = 0, and its carry U1 S_r
+    drops the part (I - U1 U1^T) C V1 = E V1 that TT-URV keeps (its carry is
+    C V1, so E V1 = 0 there).  Checked on two successive unfoldings of a
+    right-to-left sweep with ell < n, against the TT-URV step on the same
+    matrices: a sign error or a swapped side in either step fails one of the
+    conditions."""
+    dims = [6, 7, 5, 6]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 5, 3], 5e-2, 23)
+    C = a
+    r_next = 1
+    for k, r in ((4, 3), (3, 4)):
+        n = dims[k - 1] * r_next
+        Cm = C.reshape(-1, n, order="F")
+        out = {}
+        for kind in ("ulv_tall", "urv_tall"):
+            U1, s_r, V1, _, ell, dk, _ = O._step(Cm, kind, r, None, 1, 1, 7, k, dims[k - 1], r_next, True,
+                                                 k == 4, None, None, {"rank_rule_met": True})
+            assert ell < n
+            E = Cm - (U1 * s_r) @ V1.T
+            out[kind] = (U1, s_r, V1, E)
+            assert np.max(np.abs(U1.T @ U1 - np.eye(r))) < 1e-13
+            assert np.max(np.abs(V1.T @ V1 - np.eye(r))) < 1e-13
+            assert dk == pytest.approx(np.linalg.norm(E), rel=1e-12)
+        U1, s_r, V1, E = out["ulv_tall"]
+        nC = np.linalg.norm(Cm)
+        assert np.linalg.norm(U1.T @ E) <= 1e-13 * nC                 # range side exact
+        ev = np.linalg.norm(E @ V1)
+        assert ev >= 1e-8 * nC                                         # the dropped U2 L21 term, far above rounding
+        assert ev == pytest.approx(np.linalg.norm(Cm @ V1 - U1 @ (U1.T @ Cm @ V1)), rel=1e-10)
+        U1u, s_ru, V1u, Eu = out["urv_tall"]
+        assert np.linalg.norm(Eu @ V1u) <= 1e-13 * nC                  # TT-URV: core side exact
+        # and the two carries differ by exactly the dropped term: C V1 - U1 S_r = E V1
+        assert np.linalg.norm(Cm @ V1 - U1 * s_r) == pytest.approx(ev, rel=1e-10)
+        C = (U1 * s_r).reshape(-1, order="F")                           # Alg. 4 carry U1 S_r
+        r_next = r
 
 
 @pytest.mark.parametrize("sweep,variant", COMBOS)
