@@ -170,6 +170,26 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
                      const tt_opts* opts, void* work, size_t work_bytes,
                      double* const* cores, tt_report* rep, void* stream);
 
+/* Bytes of the static device scratch of tt_utv_decompose_noalloc. */
+#define TT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* tt_utv_decompose without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array
+ * of TT_NOALLOC_SCRATCH_BYTES (64 MiB) that every device the library runs on
+ * holds until the process ends; a problem whose tt_utv_workspace exceeds it
+ * returns TT_ENOSPC before any work is enqueued.  opts.profile must be 0 (it
+ * would create HIP events).  Otherwise arguments, results, report and
+ * synchronisation are those of tt_utv_decompose, whose kernels it runs;
+ * nothing in the scratch needs to start cleared.  All calls on one device
+ * share its scratch: calls that overlap in time on one device (other host
+ * threads, or other streams before this call's work has finished) race and
+ * give undefined results.  Calls no hipMalloc/hipFree or other allocating
+ * routine; the first call on each device looks up the scratch's address. */
+int tt_utv_decompose_noalloc(const void* A, tt_dtype dtype, int d, const int64_t* dims,
+                             const int64_t* ranks, double eps, tt_sweep sweep, tt_variant variant,
+                             const tt_opts* opts, double* const* cores, tt_report* rep, void* stream);
+
 /* Device bytes of workspace tt_reconstruct needs for this train. */
 int tt_reconstruct_workspace(int d, const int64_t* dims, const int64_t* ranks, size_t* bytes);
 

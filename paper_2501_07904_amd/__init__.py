@@ -17,10 +17,12 @@ LIB_PATH = os.path.join(_HERE, "libttutv.so")
 TT_OK, TT_EINVAL, TT_ENOSPC, TT_ERANK, TT_ENONFINITE, TT_EHIP, TT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 TT_MAX_D = 32
 TT_MAX_ELL = 64
+TT_NOALLOC_SCRATCH_BYTES = 64 << 20
 SWEEPS = {"L2R": 0, "R2L": 1}
 VARIANTS = {"ULV": 0, "URV": 1, "SVD": 2}
 DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose",
+           "tt_utv_decompose_noalloc",
            "tt_reconstruct_workspace", "tt_reconstruct", "tt_reconstruct_backward_workspace",
            "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed",
            "tt_last_error", "tt_kernel_class_name"]
@@ -80,6 +82,9 @@ def load_library(path=LIB_PATH):
     lib.tt_utv_decompose.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64p, i64p, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.POINTER(tt_opts), vp, ctypes.c_size_t,
                                      ctypes.POINTER(vp), ctypes.POINTER(tt_report), vp]
+    lib.tt_utv_decompose_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64p, i64p, ctypes.c_double,
+                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(tt_opts), ctypes.POINTER(vp),
+                                             ctypes.POINTER(tt_report), vp]
     lib.tt_reconstruct_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(ctypes.c_size_t)]
     lib.tt_reconstruct.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int, vp,
                                    ctypes.c_size_t, vp]
@@ -91,7 +96,8 @@ def load_library(path=LIB_PATH):
                                        ctypes.POINTER(vp), vp]
     lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
                                              ctypes.c_int64, vp, ctypes.POINTER(vp), vp]
-    for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_reconstruct_workspace",
+    for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_utv_decompose_noalloc",
+                 "tt_reconstruct_workspace",
                  "tt_reconstruct", "tt_reconstruct_backward_workspace", "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -206,6 +212,52 @@ def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dty
     return nbytes.value
 
 
+def _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
+                    fuse_ata):
+    if not (A.is_cuda and A.is_contiguous()):
+        raise ValueError("A must be a contiguous device tensor")
+    if A.dtype not in DTYPES:
+        raise ValueError("A must be float64 or float32")
+    dims = [int(x) for x in dims]
+    _check_tensor_size(A, dims)
+    if (ranks is None) == (eps is None):
+        raise ValueError("give exactly one of ranks and eps")
+    o, keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata)
+    rk = None if ranks is None else _i64(_full_ranks(ranks, len(dims)))
+    epsv = -1.0 if eps is None else float(eps)
+    return dims, o, keep, rk, epsv
+
+
+def _report_dict(lib, rep, d, rc, profile):
+    report = {
+        "ranks": [int(rep.ranks[k]) for k in range(d + 1)], "ell": [int(rep.ell[k]) for k in range(d - 1)],
+        "delta": [float(rep.delta[k]) for k in range(d - 1)],
+        "normC": [float(rep.normC[k]) for k in range(d - 1)],
+        "norm_A": float(rep.norm_A), "err_bound": float(rep.err_bound),
+        "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
+        "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
+        "rho": [float(rep.rho[k]) for k in range(d - 1)],
+    }
+    if profile:
+        report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
+            "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),
+            "bytes": float(rep.kstat[c].bytes), "flops": float(rep.kstat[c].flops)} for c in range(TT_NKCLASS)}
+    return report
+
+
+def core_buffers_for(dims, ranks=None, eps=None, q=1, oversample=8, max_rank=0, device="cuda"):
+    """Flat float64 device buffers large enough for every core the problem can
+    produce (tt_utv_core_capacity), for callers that allocate them up front."""
+    lib = load_library()
+    dims = [int(x) for x in dims]
+    d = len(dims)
+    o, _keep = make_opts(q, oversample, 0, max_rank)
+    rk = None if ranks is None else _i64(_full_ranks(ranks, d))
+    cap = (ctypes.c_int64 * d)()
+    _check(lib.tt_utv_core_capacity(d, _i64(dims), rk, -1.0 if eps is None else float(eps), ctypes.byref(o), cap))
+    return [torch.empty(max(int(c), 1), dtype=torch.float64, device=device) for c in cap]
+
+
 def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
                      max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
                      profile=False, prec="fp64", fuse_ata=False):
@@ -213,18 +265,9 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
     fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
     float64 view of a column-major device buffer."""
     lib = load_library()
-    if not (A.is_cuda and A.is_contiguous()):
-        raise ValueError("A must be a contiguous device tensor")
-    if A.dtype not in DTYPES:
-        raise ValueError("A must be float64 or float32")
-    dims = [int(x) for x in dims]
+    dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
+                                               weights, profile, prec, fuse_ata)
     d = len(dims)
-    _check_tensor_size(A, dims)
-    if (ranks is None) == (eps is None):
-        raise ValueError("give exactly one of ranks and eps")
-    o, _keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata)
-    rk = None if ranks is None else _i64(_full_ranks(ranks, d))
-    epsv = -1.0 if eps is None else float(eps)
     nbytes = ctypes.c_size_t(0)
     _check(lib.tt_utv_workspace(d, _i64(dims), rk, epsv, SWEEPS[sweep], VARIANTS[variant], DTYPES[A.dtype],
                                 ctypes.byref(o), ctypes.byref(nbytes)))
@@ -240,20 +283,36 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
     _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
     r = [int(rep.ranks[k]) for k in range(d + 1)]
     cores = [_core_view(flats[k], r[k], dims[k], r[k + 1]) for k in range(d)]
-    report = {
-        "ranks": r, "ell": [int(rep.ell[k]) for k in range(d - 1)],
-        "delta": [float(rep.delta[k]) for k in range(d - 1)],
-        "normC": [float(rep.normC[k]) for k in range(d - 1)],
-        "norm_A": float(rep.norm_A), "err_bound": float(rep.err_bound),
-        "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
-        "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
-        "rho": [float(rep.rho[k]) for k in range(d - 1)],
-    }
-    if profile:
-        report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
-            "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),
-            "bytes": float(rep.kstat[c].bytes), "flops": float(rep.kstat[c].flops)} for c in range(TT_NKCLASS)}
-    return cores, report
+    return cores, _report_dict(lib, rep, d, rc, profile)
+
+
+def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
+                             oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, stream=None,
+                             allow_rank_miss=False, prec="fp64", fuse_ata=False):
+    """tt_utv_decompose on the library's static device scratch (no workspace
+    argument): for problems whose workspace fits TT_NOALLOC_SCRATCH_BYTES.
+    core_flats: caller-allocated flat float64 device buffers, one per core, at
+    least tt_utv_core_capacity long (core_buffers_for); the call allocates no
+    device memory.  Returns (cores, report) with cores viewing core_flats."""
+    lib = load_library()
+    dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
+                                               weights, False, prec, fuse_ata)
+    d = len(dims)
+    if len(core_flats) != d:
+        raise ValueError(f"need {d} core buffers, got {len(core_flats)}")
+    cap = (ctypes.c_int64 * d)()
+    _check(lib.tt_utv_core_capacity(d, _i64(dims), rk, epsv, ctypes.byref(o), cap))
+    for k, f in enumerate(core_flats):
+        if not (f.is_cuda and f.dtype == torch.float64 and f.is_contiguous()) or f.numel() < int(cap[k]):
+            raise ValueError(f"core buffer {k} must be a contiguous float64 device tensor of >= {int(cap[k])} entries")
+    rep = tt_report()
+    rc = lib.tt_utv_decompose_noalloc(ctypes.c_void_p(A.data_ptr()), DTYPES[A.dtype], d, _i64(dims), rk, epsv,
+                                      SWEEPS[sweep], VARIANTS[variant], ctypes.byref(o), _ptrs(core_flats),
+                                      ctypes.byref(rep), _stream(stream))
+    _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
+    r = [int(rep.ranks[k]) for k in range(d + 1)]
+    cores = [_core_view(core_flats[k], r[k], dims[k], r[k + 1]) for k in range(d)]
+    return cores, _report_dict(lib, rep, d, rc, False)
 
 
 def _core_buffers(cores):

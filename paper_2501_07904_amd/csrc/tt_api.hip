@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ttutv.h"
@@ -782,6 +783,58 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   if (!P.fixed && !all_sat)
     return fail(TT_ERANK, "eps = %g not reached within the rank cap", P.eps);
   return TT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of tt_utv_decompose_noalloc: one array per device, held from the
+// library's load to the end of the process.  Its name is a host-side stand-in;
+// kernels get the device address that hipGetSymbolAddress returns for the
+// current device (looked up once per device, on the first call there).
+static __device__ __align__(256) double scratch[TT_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_of_current_device(void** ptr) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TT_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(TT_EHIP, "hipGetSymbolAddress returned a null scratch address on device %d", dev);
+    g_scratch_dev[dev] = p;
+  }
+  *ptr = g_scratch_dev[dev];
+  return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tt_utv_decompose_noalloc(const void* A, tt_dtype dtype, int d, const int64_t* dims, const int64_t* ranks,
+                             double eps, tt_sweep sweep, tt_variant variant, const tt_opts* opts,
+                             double* const* cores, tt_report* rep, void* stream) {
+  size_t need = 0;
+  int rc = tt_utv_workspace(d, dims, ranks, eps, sweep, variant, dtype, opts, &need);
+  if (rc) return rc;
+  if (need > (size_t)TT_NOALLOC_SCRATCH_BYTES)
+    return fail(TT_ENOSPC, "problem needs %zu bytes of workspace, above the %zu-byte static scratch of "
+                "tt_utv_decompose_noalloc (use tt_utv_decompose with a caller workspace)",
+                need, (size_t)TT_NOALLOC_SCRATCH_BYTES);
+  if (opts && opts->profile)
+    return fail(TT_EINVAL, "opts.profile needs HIP events, which tt_utv_decompose_noalloc does not create");
+  void* work = nullptr;
+  rc = scratch_of_current_device(&work);
+  if (rc) return rc;
+  return tt_utv_decompose(A, dtype, d, dims, ranks, eps, sweep, variant, opts, work,
+                          (size_t)TT_NOALLOC_SCRATCH_BYTES, cores, rep, stream);
 }
 
 }  // extern "C"

@@ -170,3 +170,35 @@ def test_binding_rejects_a_tensor_of_the_wrong_size():
     T._check_tensor_size(torch.zeros(12), [3, 4])
     with pytest.raises(ValueError, match="device tensor"):
         T.tt_utv_decompose(torch.zeros(12, dtype=torch.float64), [3, 4], ranks=[2])
+
+
+def test_noalloc_entry_rejects_on_host(lib):
+    """tt_utv_decompose_noalloc refuses, before any device work, a problem
+    whose workspace exceeds its static scratch, and profiling (HIP events)."""
+    d = 5
+    dims = T._i64([32] * 5)
+    rk = T._i64([1, 16, 16, 16, 16, 1])
+    o = T.make_opts()[0]
+    fake = ctypes.c_void_p(0x1000)
+    cores = (ctypes.c_void_p * d)(*([0x2000] * d))
+    rep = T.tt_report()
+    need = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1)[1]
+    assert need > T.TT_NOALLOC_SCRATCH_BYTES
+    rc = lib.tt_utv_decompose_noalloc(fake, 0, d, dims, rk, -1.0, 1, 1, ctypes.byref(o), cores, ctypes.byref(rep),
+                                      None)
+    assert rc == T.TT_ENOSPC
+    msg = lib.tt_last_error().decode()
+    assert "static scratch" in msg and str(need) in msg
+    # a problem that fits, with profiling asked for
+    small = _ws(lib, [16] * 4, [1, 4, 6, 4, 1])[1]
+    assert small <= T.TT_NOALLOC_SCRATCH_BYTES
+    o.profile = T.TT_PROFILE_ALL
+    cores4 = (ctypes.c_void_p * 4)(*([0x2000] * 4))
+    rc = lib.tt_utv_decompose_noalloc(fake, 0, 4, T._i64([16] * 4), T._i64([1, 4, 6, 4, 1]), -1.0, 0, 0,
+                                      ctypes.byref(o), cores4, ctypes.byref(rep), None)
+    assert rc == T.TT_EINVAL and "profile" in lib.tt_last_error().decode()
+    # argument errors of the decomposition itself come first
+    o.profile = 0
+    rc = lib.tt_utv_decompose_noalloc(fake, 0, 4, T._i64([16] * 4), T._i64([2, 4, 6, 4, 1]), -1.0, 0, 0,
+                                      ctypes.byref(o), cores4, ctypes.byref(rep), None)
+    assert rc == T.TT_EINVAL

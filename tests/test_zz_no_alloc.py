@@ -1,0 +1,52 @@
+"""The allocation-free decomposition entry point (tt_utv_decompose_noalloc,
+workspace in the library's static device scratch) against tt_utv_decompose
+with a caller workspace: the same kernels on the same input, so cores and
+report must agree exactly.  Two calls in a row, the second on a smaller
+problem with a different scratch layout, so a stale scratch from the first
+call would show."""
+import numpy as np
+import pytest
+import torch
+
+import ttgen
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2501_07904_amd")
+
+
+def _case(dims, ranks, eps, sweep, variant, seed):
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks if ranks else [6] * (len(dims) - 1), 1e-6, seed)
+    A = torch.from_numpy(a).cuda()
+    print(f"noalloc case dims={dims} ranks={ranks} eps={eps} {sweep}/{variant}", flush=True)
+    kw = dict(ranks=ranks, eps=eps, sweep=sweep, variant=variant, q=1, oversample=8, seed=seed)
+    flats = T.core_buffers_for(dims, ranks=ranks, eps=eps)
+    need = T.tt_utv_workspace(dims, ranks=ranks, eps=eps, sweep=sweep, variant=variant)
+    assert need <= T.TT_NOALLOC_SCRATCH_BYTES
+    nc, nrep = T.tt_utv_decompose_noalloc(A, dims, flats, **kw)
+    rc, rrep = T.tt_utv_decompose(A, dims, **kw)
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(nc, rc)):
+        assert x.shape == y.shape, k
+        assert torch.equal(x, y), f"core {k + 1} differs"
+    for key in ("ranks", "ell", "delta", "normC", "norm_A", "err_bound", "rank_rule_met", "sweeps"):
+        assert nrep[key] == rrep[key], key
+    rec = T.tt_reconstruct(nc).cpu().numpy()
+    rse = np.linalg.norm(rec - a) / np.linalg.norm(a)
+    assert rse <= max(2 * nrep["err_bound"] / nrep["norm_A"], 1e-12)
+    return need
+
+
+def test_noalloc_matches_workspace_entry_two_calls():
+    first = _case([40, 40, 40, 40], [32, 32, 32], None, "R2L", "URV", 11)
+    second = _case([16, 16, 16, 16], None, 1e-6, "L2R", "ULV", 12)
+    third = _case([12, 10, 14, 9], [5, 7, 6], None, "R2L", "ULV", 13)
+    assert first > second > third
+
+
+def test_noalloc_rejects_beyond_its_scratch():
+    dims = [32] * 5
+    A = torch.zeros(32 ** 5, dtype=torch.float64, device="cuda")
+    flats = T.core_buffers_for(dims, ranks=[16] * 4)
+    with pytest.raises(T.TTError, match="static scratch"):
+        T.tt_utv_decompose_noalloc(A, dims, flats, ranks=[16] * 4, sweep="R2L", variant="URV")
