@@ -1,14 +1,19 @@
 """Benchmark of the TT-UTV sweep on one MI355X.
 
-One step = one full TT-URV decomposition (right-to-left sweep, Alg. 3) of the
-resident synthetic tensor: order 5, 32^5 FP64 (33.5M entries, 268 MB),
-contracted from Gaussian TT cores of ranks 16 plus Gaussian noise at 1e-6
-relative Frobenius norm, fixed rank 16, q = 2 power steps, oversampling 8.
+One step = one full TT-URV decomposition (right-to-left sweep, Alg. 3) at a
+prescribed accuracy of the resident synthetic tensor: order 6, 40^6 FP32
+(4.1e9 entries, 16.4 GB) built on the GPU from Gaussian TT cores of ranks 32
+plus Gaussian noise at 1e-5 relative Frobenius norm; eps = 1e-4, q = 1 power
+step, oversampling 8, ranks capped at 48, every product and carry in FP64
+(the FP64 form).
 
 Prints one JSON line: GB/s of tensor swept (tensor bytes / step time), the
 roofline of the dominant kernel class (its launches timed with HIP events on
-the launch stream during the timed steps), and the FP64 oracle timed on the
-host cores for one decomposition of the same tensor.
+the launch stream during the timed steps), the FP64 oracle timed on the host
+cores on a 40^5 instance of the same recipe (and on one thread on 40^4), the
+mixed-precision form on the same tensor and on the 8^8 function tensor at
+eps = 1e-6, the fixed-rank 32^5 FP64 decomposition, and the train
+contractions.
 """
 import argparse
 import json
@@ -22,16 +27,21 @@ if ROOT not in sys.path:
 
 METRIC = "TT-URV GB/s swept + roofline %, mixed vs FP64 GPU at 1e-6 rel. error"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a kernel class, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
-# workload scaled by the copy-probe factors (profiles/c2_order5_32_fp64_tturv_r2l.md); set to None
-# whenever the class's kernels change after the counters were taken
-MEASURED_TRAFFIC = {"tall_atb": 76.49e6, "tall_ax": 49.03e6}
+# HBM bytes per launch of a kernel class, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over each
+# workload scaled by the copy-probe factors (profiles/); empty whenever the class's kernels changed
+# after the counters were taken
+MEASURED_TRAFFIC = {"order6_40_fp32_eps": {}, "order5_32_fp64": {}}
 FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
+    "order6_40_fp32_eps": dict(
+        dims=[40] * 6, gen_ranks=[32] * 5, noise=1e-5, seed=5, eps=1e-4, max_rank=48, q=1, oversample=8,
+        sweep="R2L", variant="URV", dtype="float32", device_built=True,
+        desc="order-6 40^6 FP32 (4.1e9 entries, 16.4 GB) Gaussian-TT ranks 32 + 1e-5 relative noise; "
+             "TT-URV right-to-left, eps=1e-4, q=1, p=8, rank cap 48, FP64 form"),
     "order5_32_fp64": dict(
         dims=[32] * 5, gen_ranks=[16] * 4, noise=1e-6, seed=0, ranks=[16] * 4, q=2, oversample=8,
-        sweep="R2L", variant="URV",
+        sweep="R2L", variant="URV", dtype="float64", device_built=False,
         desc="order-5 32^5 FP64 (33.5M entries) Gaussian-TT ranks 16 + 1e-6 relative noise; "
              "TT-URV right-to-left, fixed rank 16, q=2, p=8"),
 }
@@ -148,99 +158,51 @@ def mixed_vs_fp64(steps):
         log(f"bench: {prec:5s} eps=1e-6 8^8: {ms:.3f} ms, RSE {rse:.3e}, bound {res[prec]['err_bound_rel']:.3e}, "
             f"ranks {rep['ranks']}")
     res["speedup_mixed_over_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+    res["note"] = ("every step of this workload has core side n <= 64 and forms A^T A in one FP64 pass: no "
+                   "low-precision product runs, the mixed form differs only in the FP32 storage of the carries, "
+                   "and both forms are bound by the same single-workgroup factorisations (ceiling 1.0x)")
     return res
 
 
-def mixed_vs_fp64_c5(steps):
-    """The large workload of the mixed-vs-FP64 comparison: order-6 40^6 FP32
-    (4.1e9 entries, 16.4 GB) from Gaussian TT cores of ranks 32 plus 1e-5
-    relative noise, built on the GPU; prescribed accuracy eps = 1e-4, TT-URV
-    right-to-left, q = 1, p = 8, ranks capped at 48.  Each form is timed over
-    `steps` decompositions; RSE from the reconstruction."""
-    import torch
-
-    import paper_2501_07904_amd as T
-    import ttgen
-
-    dims = [40] * 6
-    log("bench: generating the 40^6 FP32 tensor on the GPU")
-    A = ttgen.gaussian_tt_tensor_device(dims, [32] * 5, 1e-5, 5, dtype="float32", device="cuda")
-    nbytes = A.numel() * A.element_size()
-    normA = float(torch.linalg.vector_norm(A, dtype=torch.float64))
-    res = {"workload": "order-6 40^6 FP32 (16.4 GB) Gaussian-TT ranks 32 + 1e-5 noise, eps=1e-4, "
-                       "TT-URV right-to-left, q=1, p=8, rank cap 48"}
-    for prec in ("fp64", "mixed"):
-        dec = T.Decomposer(dims, A.dtype, eps=1e-4, sweep="R2L", variant="URV", q=1, oversample=8, seed=5,
-                           max_rank=48, prec=prec)
-        dec(A)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            dec(A)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        rep = stated_bound(T, dims, A, dict(eps=1e-4, sweep="R2L", variant="URV", q=1, oversample=8, seed=5,
-                                            max_rank=48, prec=prec), dec)
-        # FP64 reconstruction (32.8 GB): an FP32 one would add its own rounding to the error
-        rec = T.tt_reconstruct(dec.cores())
-        err2 = 0.0
-        for s0 in range(0, A.numel(), 1 << 28):
-            err2 += float(torch.linalg.vector_norm(rec[s0:s0 + (1 << 28)].double() - A[s0:s0 + (1 << 28)].double()) ** 2)
-        del rec
-        rse = err2 ** 0.5 / normA
-        res[prec] = {"ms": round(ms, 3), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "rse": rse,
-                     "err_bound_rel": rep["err_bound"] / rep["norm_A"], "ranks": rep["ranks"]}
-        log(f"bench: {prec:5s} eps=1e-4 40^6: {ms:.2f} ms, RSE {rse:.3e}, bound {res[prec]['err_bound_rel']:.3e}, "
-            f"ranks {rep['ranks']}")
-        del dec
-        torch.cuda.empty_cache()
-    res["speedup_mixed_over_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
-    del A
-    torch.cuda.empty_cache()
-    return res
+def decomposer_kw(W):
+    kw = dict(sweep=W["sweep"], variant=W["variant"], q=W["q"], oversample=W["oversample"], seed=W["seed"])
+    if "ranks" in W:
+        kw["ranks"] = W["ranks"]
+    else:
+        kw["eps"] = W["eps"]
+        kw["max_rank"] = W["max_rank"]
+    return kw
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="order5_32_fp64", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-vs-FP64 comparison")
-    ap.add_argument("--mixed-steps", type=int, default=10)
-    ap.add_argument("--no-c5", action="store_true", help="skip the 40^6 (16.4 GB) mixed-vs-FP64 comparison")
-    ap.add_argument("--c5-steps", type=int, default=3)
-    ap.add_argument("--no-contractions", action="store_true",
-                    help="skip the timing of reconstruction, sampling and its backward")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="after the timed steps, copy the input tensor once (a kernel of known "
-                         "traffic: its bytes read and written) to calibrate HBM counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
-              file=sys.stderr)
-        sys.exit(2)
-
+def build_input(W):
+    """The workload's tensor on the GPU (and on the host when it is built there)."""
     import numpy as np
     import torch
 
-    import paper_2501_07904_amd as T
     import ttgen
 
-    W = WORKLOADS[args.workload]
     log(f"bench: generating {W['desc']}")
-    a, _ = ttgen.gaussian_tt_tensor(W["dims"], W["gen_ranks"], W["noise"], W["seed"])
-    A = torch.from_numpy(a).cuda()
-    tensor_bytes = A.numel() * A.element_size()
-    dec = T.Decomposer(W["dims"], A.dtype, ranks=W["ranks"], sweep=W["sweep"], variant=W["variant"], q=W["q"],
-                       oversample=W["oversample"])
-    log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
+    if W["device_built"]:
+        A = ttgen.gaussian_tt_tensor_device(W["dims"], W["gen_ranks"], W["noise"], W["seed"], dtype=W["dtype"],
+                                            device="cuda")
+        torch.cuda.synchronize()
+        return A, None
+    a, _ = ttgen.gaussian_tt_tensor(W["dims"], W["gen_ranks"], W["noise"], W["seed"], dtype=getattr(np, W["dtype"]))
+    return torch.from_numpy(a).cuda(), a
+
+
+def timed_decompositions(T, W, A, steps, warmup, prec="fp64"):
+    """Warm-up, two calibration steps with every kernel class timed with events,
+    then `steps` timed decompositions; the last one carries events on the
+    launches of the dominant streaming class (an event pair idles the queue for
+    a few microseconds, so the other timed steps run without them)."""
+    import torch
+
+    dec = T.Decomposer(W["dims"], A.dtype, prec=prec, **decomposer_kw(W))
+    log(f"bench: [{prec}] warmup {warmup}")
+    for _ in range(warmup):
         dec(A)
     torch.cuda.synchronize()
-
-    # calibration, outside the timed region: every kernel class timed with events
     dec.set_profile(True)
     cal = {}
     for _ in range(2):
@@ -249,113 +211,263 @@ def main():
             acc = cal.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0})
             for key in acc:
                 acc[key] += v[key] / 2
-    # the dominant streaming kernel: most launch time among the classes that read A
     streaming = {k: v for k, v in cal.items() if v["bytes"] > 0 and v["launches"] > 0}
     dom_name = max(streaming, key=lambda k: streaming[k]["ms"])
     names = [T.load_library().tt_kernel_class_name(c).decode() for c in range(T.TT_NKCLASS)]
-    dom_class = names.index(dom_name)
     for name, v in sorted(cal.items(), key=lambda kv: -kv[1]["ms"]):
         if v["launches"]:
             gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else 0.0
-            log(f"bench: kernel {name:9s} launches/step {v['launches']:5.1f} ms/step {v['ms']:.4f}  GB/s {gbs:8.1f}")
-
-    # timed region: the dominant class's launches of the last timed step carry
-    # events (each event pair idles the queue for a few microseconds, so the
-    # other steps run without them)
-    kstat = {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0}
-    log(f"bench: timing {args.steps} steps (events on the {dom_name} launches of the last one)")
+            log(f"bench: [{prec}] kernel {name:9s} launches/step {v['launches']:5.1f} ms/step {v['ms']:.4f}  "
+                f"GB/s {gbs:8.1f}")
+    log(f"bench: [{prec}] timing {steps} steps (events on the {dom_name} launches of the last one)")
     dec.set_profile(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        if i == args.steps - 1:
-            dec.set_profile(1 << dom_class)
-        dec(A)  # fixed ranks: the call synchronises once at the end to fill its report
+    for i in range(steps):
+        if i == steps - 1:
+            dec.set_profile(1 << names.index(dom_name))
+        dec(A)   # fixed ranks: one synchronisation at the end; eps: one per step
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    v = dec.report()["kstat"][dom_name]
-    for key in kstat:
-        kstat[key] += v[key]
+    kstat = dict(dec.report()["kstat"][dom_name])
     dec.set_profile(0)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = tensor_bytes / (ms_per_step * 1e-3) / 1e9
-    if args.copy_probe:
-        # an elementwise kernel (a device-to-device copy_ would go to the DMA engines,
-        # which the counters do not see): reads and writes the tensor once
-        B = torch.empty_like(A)
-        torch.mul(A, 1.0, out=B)
-        torch.cuda.synchronize()
-        log(f"bench: copy probe kernel read {tensor_bytes} bytes and wrote {tensor_bytes} bytes")
-        del B
-    rep = dec.report()
-    cores = dec.cores()
-    rec = T.tt_reconstruct(cores)
-    rse = float(torch.linalg.norm(rec - A) / torch.linalg.norm(A))
-    log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} GB/s swept, ranks {rep['ranks']}, RSE {rse:.3e}, "
-        f"Jacobi sweeps {rep['sweeps']}")
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    return dict(dec=dec, ms=ms_per_step, cal=cal, streaming=streaming, dom=dom_name, kstat=kstat)
 
-    avg_ms = kstat["ms"] / kstat["launches"]
-    bytes_per = kstat["bytes"] / kstat["launches"]
-    flops_per = kstat["flops"] / kstat["launches"]
+
+def roofline(tm, traffic):
+    """Roofline object of the dominant class: algorithmic bytes (or flops) per
+    launch / average launch duration against the HBM (or FP64 matrix-core)
+    peak, plus the whole-step figure over every streaming pass."""
+    k = tm["kstat"]
+    avg_ms = k["ms"] / k["launches"]
+    bytes_per = k["bytes"] / k["launches"]
+    flops_per = k["flops"] / k["launches"]
     intensity = flops_per / bytes_per if bytes_per else 0.0
-    ridge = FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS   # flop per byte where HBM and FP64 peaks meet
+    ridge = FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS   # flop per byte where the HBM and FP64 peaks meet
     if intensity < ridge:
         achieved = bytes_per / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
         achieved = flops_per / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
-    roof["traffic"] = MEASURED_TRAFFIC.get(dom_name) if W is WORKLOADS["order5_32_fp64"] else None
-    roof["kernel"] = dom_name
-    roof["launches_per_step"] = kstat["launches"]
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+    roof["traffic"] = traffic.get(tm["dom"])
+    roof["kernel"] = tm["dom"]
+    roof["launches_per_step"] = k["launches"]
     roof["avg_launch_ms"] = round(avg_ms, 5)
     roof["alg_bytes_per_launch"] = bytes_per
     roof["alg_flops_per_launch"] = flops_per
-    # share of the step spent in each class (calibration steps), and the whole-step
-    # roofline: algorithmic bytes and flops of every streaming pass at the HBM / FP64 peaks
-    roof["step_share"] = {k: round(v["ms"] / ms_per_step, 3) for k, v in cal.items() if v["launches"]}
+    roof["hbm_GBps_per_launch"] = round(bytes_per / (avg_ms * 1e-3) / 1e9, 1)
+    roof["step_share"] = {n: round(v["ms"] / tm["ms"], 3) for n, v in tm["cal"].items() if v["launches"]}
     t_roof = sum(max(v["bytes"] / (HBM_PEAK_GBS * 1e9), v["flops"] / (FP64_PEAK_TFLOPS * 1e12))
-                 for v in streaming.values()) * 1e3
+                 for v in tm["streaming"].values()) * 1e3
     roof["step_t_roof_ms"] = round(t_roof, 5)
-    roof["step_frac"] = round(t_roof / ms_per_step, 4)
+    roof["step_frac"] = round(t_roof / tm["ms"], 4)
+    return roof
 
+
+def relative_error(T, cores, A):
+    """||A - A_TT||_F / ||A||_F with the train reconstructed in FP64 (an FP32
+    reconstruction would add its own rounding), summed in slices."""
+    import torch
+
+    rec = T.tt_reconstruct(cores)
+    err2 = nrm2 = 0.0
+    step = 1 << 28
+    for s0 in range(0, A.numel(), step):
+        a = A[s0:s0 + step].double()
+        err2 += float(torch.linalg.vector_norm(rec[s0:s0 + step] - a) ** 2)
+        nrm2 += float(torch.linalg.vector_norm(a) ** 2)
     del rec
-    contr = None if args.no_contractions else contractions(T, cores)
+    return (err2 / nrm2) ** 0.5
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        try:
-            from threadpoolctl import threadpool_info
-            cores_used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-        except Exception:  # threadpoolctl missing: numpy's BLAS default is all cores
-            cores_used = os.cpu_count()
-        log("bench: timing the FP64 oracle on the host (full decompositions of the same tensor, >= 10 s)")
-        runs = 0
-        c0 = time.perf_counter()
-        while runs == 0 or time.perf_counter() - c0 < 10.0:
-            oracle.tt_utv(a, W["dims"], ranks=W["ranks"], sweep=W["sweep"], variant=W["variant"], q=W["q"],
-                          p=W["oversample"], seed=0)
-            runs += 1
-        c1 = time.perf_counter()
-        cpu = {"value": round(runs * tensor_bytes / (c1 - c0) / 1e9, 5), "unit": "GB/s", "cores": cores_used,
-               "kind": "oracle", "sample": f"{runs} full decompositions of the same 32^5 FP64 tensor "
-                                           f"({c1 - c0:.1f} s)"}
+
+def finish_form(T, W, A, tm, prec):
+    """Cores, report, RSE and the stated bound (from measured step errors, the
+    same decomposition rerun untimed with exact_delta) of a timed form; frees
+    the timed decomposer first."""
+    import torch
+
+    dec = tm.pop("dec")
+    cores = [c.clone() for c in dec.cores()]
+    rep = dec.report()
+    del dec
+    torch.cuda.empty_cache()
+    chk = T.Decomposer(W["dims"], A.dtype, prec=prec, exact_delta=True, **decomposer_kw(W))
+    chk(A)
+    torch.cuda.synchronize()
+    for x, y in zip(chk.cores(), cores):
+        if not torch.equal(x, y):
+            raise RuntimeError("exact_delta changed the decomposition")
+    brep = chk.report()
+    del chk
+    torch.cuda.empty_cache()
+    rse = relative_error(T, cores, A)
+    return cores, rep, rse, brep["err_bound"] / brep["norm_A"]
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host on bounded samples of the headline recipe:
+    40^5 FP32 (Gaussian-TT ranks 32 + 1e-5 noise, eps = 1e-4, q = 1, p = 8,
+    rank cap 48, TT-URV right-to-left) on every BLAS thread, and 40^4 of the
+    same recipe on one thread."""
+    import numpy as np
+
+    import oracle
+    import ttgen
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores_used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # threadpoolctl missing: numpy's BLAS default is all cores
+        threadpool_limits = None
+        cores_used = os.cpu_count()
+    kw = dict(eps=1e-4, sweep="R2L", variant="URV", q=1, p=8, seed=5, max_rank=48)
+    a5, _ = ttgen.gaussian_tt_tensor([40] * 5, [32] * 4, 1e-5, 5, dtype=np.float32)
+    log(f"bench: timing the FP64 oracle on the host (40^5 FP32, {cores_used} threads, >= 10 s)")
+    runs, t0 = 0, time.perf_counter()
+    while runs == 0 or time.perf_counter() - t0 < 10.0:
+        _, rep5 = oracle.tt_utv(a5, [40] * 5, **kw)
+        runs += 1
+    t5 = (time.perf_counter() - t0) / runs
+    out = {"value": round(a5.nbytes / t5 / 1e9, 5), "unit": "GB/s", "cores": cores_used, "kind": "oracle",
+           "sample": f"{runs} decompositions of a 40^5 FP32 instance of the same recipe ({a5.nbytes / 1e6:.0f} MB, "
+                     f"ranks {rep5['ranks']}), {t5:.1f} s each"}
+    del a5
+    if threadpool_limits is not None:
+        a4, _ = ttgen.gaussian_tt_tensor([40] * 4, [32] * 3, 1e-5, 5, dtype=np.float32)
+        with threadpool_limits(limits=1):
+            reps, t0 = 0, time.perf_counter()
+            while reps == 0 or time.perf_counter() - t0 < 3.0:
+                oracle.tt_utv(a4, [40] * 4, **kw)
+                reps += 1
+            t4 = (time.perf_counter() - t0) / reps
+        out["single_thread"] = {"value": round(a4.nbytes / t4 / 1e9, 5), "unit": "GB/s", "cores": 1,
+                                "sample": f"{reps} decompositions of a 40^4 FP32 instance ({a4.nbytes / 1e6:.1f} MB), "
+                                          f"{t4:.2f} s each"}
+    log(f"bench: oracle {out['value']} GB/s on {cores_used} threads"
+        + (f", {out['single_thread']['value']} GB/s on one" if "single_thread" in out else ""))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="order6_40_fp32_eps", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--mixed-steps", type=int, default=10)
+    ap.add_argument("--no-c2", action="store_true", help="skip the fixed-rank 32^5 FP64 decomposition")
+    ap.add_argument("--c2-steps", type=int, default=20)
+    ap.add_argument("--no-contractions", action="store_true",
+                    help="skip the timing of reconstruction, sampling and its backward")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="allocate and fill a 4 GiB buffer before the timed steps and copy it once after them "
+                         "(a kernel of known traffic on data the decompositions have evicted from every cache: "
+                         "it calibrates the HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2501_07904_amd as T
+
+    W = WORKLOADS[args.workload]
+    probe_src = None
+    if args.copy_probe:
+        probe_src = torch.empty(1 << 29, dtype=torch.float64, device="cuda").normal_()
+    A, a_host = build_input(W)
+    tensor_bytes = A.numel() * A.element_size()
+    tm = timed_decompositions(T, W, A, args.steps, args.warmup)
+    ms_per_step = tm["ms"]
+    value = tensor_bytes / (ms_per_step * 1e-3) / 1e9
+    roof = roofline(tm, MEASURED_TRAFFIC.get(args.workload, {}))
+    if probe_src is not None:
+        # an elementwise kernel (a device-to-device copy_ would go to the DMA engines, which the counters
+        # do not see): reads and writes 4 GiB once
+        dst = torch.empty_like(probe_src)
+        torch.mul(probe_src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe kernel read {probe_src.numel() * 8} bytes and wrote {probe_src.numel() * 8} bytes")
+        del dst, probe_src
+    cores, rep, rse, bound = finish_form(T, W, A, tm, "fp64")
+    log(f"bench: {ms_per_step:.3f} ms/step, {value:.1f} GB/s swept, ranks {rep['ranks']}, RSE {rse:.3e}, "
+        f"stated bound {bound:.3e}, Jacobi sweeps {rep['sweeps']}")
+    log(f"bench: roofline {roof['kernel']}: {roof['achieved']} {roof['unit']} = {roof['frac']:.1%} of peak, "
+        f"{roof['hbm_GBps_per_launch']} GB/s per launch, whole step {roof['step_frac']:.1%}")
 
     mixed = None
     if not args.no_mixed:
-        mixed = {"c3": mixed_vs_fp64(args.mixed_steps)}
-        if not args.no_c5:
-            mixed["c5"] = mixed_vs_fp64_c5(args.c5_steps)
+        mixed = {}
+        if "eps" in W:
+            tmm = timed_decompositions(T, W, A, args.mixed_steps, args.warmup, prec="mixed")
+            mms = tmm["ms"]
+            # what the roofline allows the mixed form to gain: algorithmic HBM bytes of the
+            # streaming passes per decomposition, FP64 form over mixed form
+            bytes64 = sum(v["bytes"] for v in tm["streaming"].values())
+            bytesmx = sum(v["bytes"] for v in tmm["streaming"].values())
+            _, mrep, mrse, mbound = finish_form(T, W, A, tmm, "mixed")
+            mixed["c5"] = {"workload": W["desc"].replace("FP64 form", "mixed form"),
+                           "fp64": {"ms": round(ms_per_step, 3), "GB/s": round(value, 1), "rse": rse,
+                                    "err_bound_rel": bound, "ranks": rep["ranks"]},
+                           "mixed": {"ms": round(mms, 3), "GB/s": round(tensor_bytes / (mms * 1e-3) / 1e9, 1),
+                                     "rse": mrse, "err_bound_rel": mbound, "ranks": mrep["ranks"]},
+                           "speedup_mixed_over_fp64": round(ms_per_step / mms, 3),
+                           "alg_hbm_bytes_per_step": {"fp64": bytes64, "mixed": bytesmx},
+                           "roofline_ceiling_speedup": round(bytes64 / bytesmx, 3),
+                           "note": "the step-1 Gram pass over the FP32 input, the step-1 carry and the "
+                                   "Rayleigh-Ritz pass decide the ranks and stay FP64-accurate in both forms; "
+                                   "the mixed form halves the bytes of the FP64 step-2 carry and runs the power "
+                                   "products on FP32 matrix cores, so its HBM-bound ceiling is the byte ratio"}
+            log(f"bench: mixed {mms:.3f} ms/step ({ms_per_step / mms:.2f}x the FP64 form), RSE {mrse:.3e}, "
+                f"stated bound {mbound:.3e}, ranks {mrep['ranks']}")
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        mixed["c3"] = mixed_vs_fp64(args.mixed_steps)
+
+    c2 = None
+    c2_cores = None
+    if not args.no_c2 and args.workload != "order5_32_fp64":
+        W2 = WORKLOADS["order5_32_fp64"]
+        A2, _ = build_input(W2)
+        tm2 = timed_decompositions(T, W2, A2, args.c2_steps, 3)
+        roof2 = roofline(tm2, MEASURED_TRAFFIC.get("order5_32_fp64", {}))
+        c2_cores = [c.clone() for c in tm2["dec"].cores()]
+        c2_ranks = tm2["dec"].report()["ranks"]
+        del tm2["dec"]
+        rse2 = relative_error(T, c2_cores, A2)
+        v2 = A2.numel() * A2.element_size() / (tm2["ms"] * 1e-3) / 1e9
+        c2 = {"workload": W2["desc"], "value": round(v2, 2), "unit": "GB/s", "ms_per_step": round(tm2["ms"], 5),
+              "steps": args.c2_steps, "ranks": c2_ranks, "rse": rse2, "roofline": roof2}
+        log(f"bench: 32^5 FP64 fixed rank: {tm2['ms']:.4f} ms/step, {v2:.1f} GB/s swept, RSE {rse2:.3e}, "
+            f"{roof2['kernel']} {roof2['frac']:.1%} of peak, whole step {roof2['step_frac']:.1%}")
+        del A2
+        torch.cuda.empty_cache()
+    contr = None
+    if not args.no_contractions:
+        if c2_cores is None:
+            W2 = WORKLOADS["order5_32_fp64"]
+            A2, _ = build_input(W2)
+            c2_cores, _ = T.tt_utv_decompose(A2, W2["dims"], **decomposer_kw(W2))
+            del A2
+        contr = contractions(T, c2_cores)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": W["desc"], "ranks": rep["ranks"], "rse": rse},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed, "contractions": contr,
+        "config": {"workload": W["desc"], "ranks": rep["ranks"], "rse": rse, "err_bound_rel": bound},
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed, "c2_order5_32_fp64": c2,
+        "contractions": contr,
     }
     print(json.dumps(out), flush=True)
 

@@ -97,8 +97,9 @@ typedef struct {
  * sqrt(sum delta_k^2) + sum rho_k (sum delta_k + sum rho_k for Alg. 4).  With
  * a prescribed accuracy the rank rule aims at eps - (d-2) 2^-24 (the a-priori
  * budget of the d-2 FP32 carries), so err_bound <= eps ||A||_F still holds;
- * eps at or below that budget is rejected (TT_EINVAL), and a bound above
- * eps ||A||_F clears rank_rule_met and returns TT_ERANK.
+ * eps at or below that budget is rejected (TT_EINVAL), and with measured step
+ * errors (exact_delta = 1) a bound above eps ||A||_F clears rank_rule_met and
+ * returns TT_ERANK (without them the bound is an estimate and is not checked).
  * TT_PREC_MIXED_BF16: as TT_PREC_MIXED with the power products on BF16
  * operands (FP32 accumulation): the sketch resolves singular directions only
  * to about 4e-3 of the largest, which costs rank (or, under a rank cap, the

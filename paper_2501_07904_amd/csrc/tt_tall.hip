@@ -722,12 +722,15 @@ __global__ __launch_bounds__(kThreads) void k_atb_lp(const TA* __restrict__ A, c
 // columns of A each, so one staged tile of Y serves 128 columns.  Row tiles
 // (32 rows) of A and Y are loaded with coalesced reads into registers one
 // tile ahead (the loads of tile t+1 are in flight while tile t is
-// multiplied), then stored to LDS behind a barrier.
+// multiplied), then stored to LDS behind a barrier.  VEC (column-major,
+// aligned A, chunks of whole tiles): each lane reads 16 contiguous bytes of
+// one column of A per load (2 FP64 or 4 FP32 rows), at clamped in-range
+// addresses with rows and columns outside the chunk zeroed when staged.
 constexpr int kAtb2Threads = 512;
 constexpr int kAtb2JB = 128;
 constexpr int kAtb2TR = 32;
 
-template <typename TA, typename TY, int NT, int LY, bool F32>
+template <typename TA, typename TY, int NT, int LY, bool F32, bool VEC>
 __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A, const TY* __restrict__ Y, int64_t m,
                                                        int n, int c, int64_t rows_per_chunk,
                                                        double* __restrict__ partials) {
@@ -736,7 +739,10 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
   constexpr int NTH = kAtb2Threads;
   constexpr int WY = NT * 16;
   constexpr int LA = kAtb2TR * kAtb2JB / NTH;   // A values per thread per tile
+  constexpr int VL = VEC ? 16 / (int)sizeof(TA) : 1;   // rows per vector load
+  constexpr int LAV = LA / VL;                   // vector loads per thread per tile
   constexpr int LYV = (kAtb2TR * WY + NTH - 1) / NTH;
+  typedef TA avec_t __attribute__((ext_vector_type(VL)));
   __shared__ T sA[kAtb2TR][kAtb2JB + 1];
   __shared__ T sY[kAtb2TR][WY + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -745,16 +751,32 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
   const int j0 = blockIdx.y * kAtb2JB;
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = min(m, r0 + rows_per_chunk);
-  // element e of a tile: COL -> (row e % TR, col e / TR); ROW -> (row e / W, col e % W)
+  // element e of a tile: COL -> (row e % TR, col e / TR); ROW -> (row e / W, col e % W);
+  // VEC: vector e -> rows VL (e % (TR / VL)) .. + VL - 1 of col e / (TR / VL)
   T ra[LA], ry[LYV];
+  avec_t rv[VEC ? LAV : 1];
+  int64_t rb_cur = r0;   // first row of the tile whose loads are in flight
   auto load = [&](int64_t rb) {
+    rb_cur = rb;
+    if constexpr (VEC) {
 #pragma unroll
-    for (int u = 0; u < LA; ++u) {
-      const int e = t + NTH * u;
-      int i, j;
-      if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
-      const int64_t r = rb + i;
-      ra[u] = (r < r1 && j0 + j < n) ? (T)A[at(LY, r, j0 + j, m, n)] : (T)0;
+      for (int u = 0; u < LAV; ++u) {
+        const int e = t + NTH * u;
+        const int i = (e % (kAtb2TR / VL)) * VL, j = e / (kAtb2TR / VL);
+        int64_t r = rb + i;
+        r = r < r1 - VL ? r : r1 - VL;                 // r1 - r0 is a multiple of VL
+        const int jc = j0 + j < n ? j0 + j : n - 1;
+        rv[u] = *reinterpret_cast<const avec_t*>(A + r + (int64_t)jc * m);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < LA; ++u) {
+        const int e = t + NTH * u;
+        int i, j;
+        if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+        const int64_t r = rb + i;
+        ra[u] = (r < r1 && j0 + j < n) ? (T)A[at(LY, r, j0 + j, m, n)] : (T)0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < LYV; ++u) {
@@ -766,12 +788,23 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
     }
   };
   auto store = [&]() {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int u = 0; u < LA; ++u) {
-      const int e = t + NTH * u;
-      int i, j;
-      if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
-      sA[i][j] = ra[u];
+      for (int u = 0; u < LAV; ++u) {
+        const int e = t + NTH * u;
+        const int i = (e % (kAtb2TR / VL)) * VL, j = e / (kAtb2TR / VL);
+        const bool jok = j0 + j < n;
+#pragma unroll
+        for (int v = 0; v < VL; ++v) sA[i + v][j] = (jok && rb_cur + i + v < r1) ? (T)rv[u][v] : (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < LA; ++u) {
+        const int e = t + NTH * u;
+        int i, j;
+        if (LY == ROW) { i = e / kAtb2JB; j = e % kAtb2JB; } else { i = e % kAtb2TR; j = e / kAtb2TR; }
+        sA[i][j] = ra[u];
+      }
     }
 #pragma unroll
     for (int u = 0; u < LYV; ++u) {
@@ -1074,25 +1107,35 @@ __global__ __launch_bounds__(kThreads) void k_ax_narrow_v(const TA* __restrict__
 // so each load instruction covers 4 columns with 16*RB*sizeof(TA) contiguous
 // bytes each; MFMA row block rb holds rows RB*li + rb.  The four waves own
 // consecutive blocks (a 64*RB-row tile) and share each KC-column chunk of W,
-// staged in LDS (double buffered, the
-// next chunk of A prefetched into registers while the current one runs on
-// the matrix cores).  Result row rho of block rb is tile row RB*rho + rb, so
-// a lane holds RB consecutive rows of one column of Y and writes them with one
-// vector store.  F32M: FP32 matrix cores (v_mfma_f32_16x16x4f32, A and W
-// rounded to FP32, FP32 accumulation); otherwise FP64 matrix cores.
+// staged in LDS (double buffered).  The chunk loop is unrolled by two with
+// two register buffers for A: the loads of chunk k+1 go to the other buffer
+// while chunk k runs on the matrix cores.  Every load is issued
+// unconditionally (clamped addresses, rows past m read row m-RB and columns
+// past n read column n-1 of the same row): such values meet zero rows of W
+// or land in rows that are never stored, and the sum of squares masks them.
+// With no branch around a load and no copy between the buffers, the wait
+// before a chunk's matrix-core block covers only that chunk's own loads (a
+// conditional load or a register copy makes the compiler wait for the next
+// chunk's loads there as well, which serialises memory and matrix cores).
+// Result row rho of block rb is tile row RB*rho + rb, so a lane holds RB
+// consecutive rows of one column of Y and writes them with one vector store.
+// F32M: FP32 matrix cores (v_mfma_f32_16x16x4f32, A and W rounded to FP32,
+// FP32 accumulation); otherwise FP64 matrix cores.  Requires m % RB == 0.
 template <typename TA, typename TY, int NT, bool F32M, int RB, int KC>
 __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A, const double* __restrict__ W,
                                                        TY* __restrict__ Y, int64_t m, int n, int c,
                                                        double* __restrict__ sumsqA, double* __restrict__ sumsqY,
                                                        double* __restrict__ rerr) {
   constexpr int TR = 4 * 16 * RB;            // rows per tile
-  constexpr int NS = KC / 4;             // k-steps per chunk
+  constexpr int NS = KC / 4;                 // k-steps per chunk
   constexpr int NWS = (KC * NT * 16 + kThreads - 1) / kThreads;
   typedef TA vec_t __attribute__((ext_vector_type(RB)));
   typedef TY yvec_t __attribute__((ext_vector_type(RB)));
   typedef typename std::conditional<F32M, float, double>::type TM;   // matrix-core operand type
   typedef typename std::conditional<F32M, f4, d4>::type acc_t;
-  __shared__ TM sW[2][KC][NT * 16 + 1];
+  // FP32 rows padded by 4 words: the four k-rows a wave reads then fall on
+  // distinct banks
+  __shared__ TM sW[2][KC][NT * 16 + (sizeof(TM) == 4 ? 4 : 1)];
   __shared__ double sh[8];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -1100,20 +1143,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A,
   const int64_t ntiles = (m + TR - 1) / TR;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row = tile * TR + 16 * RB * w + RB * li;   // first of this lane's RB rows
-    const bool full_rows = tile * TR + TR <= m;                // uniform over the workgroup
-    const TA* Al = A + row + (int64_t)g * m;                   // this lane's rows of column 4s + g
+    const int64_t rowc = row < m - RB ? row : m - RB;
     auto load_a = [&](int k0, vec_t* a) {
-      if (full_rows && k0 + KC <= n) {
-        const TA* p = Al + (int64_t)k0 * m;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = *reinterpret_cast<const vec_t*>(p + (int64_t)(4 * s) * m);
-      } else {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          const int k = k0 + 4 * s + g;
-#pragma unroll
-          for (int e = 0; e < RB; ++e) a[s][e] = (k < n && row + e < m) ? A[row + e + (int64_t)k * m] : (TA)0;
-        }
+      for (int s = 0; s < NS; ++s) {
+        const int k = k0 + 4 * s + g;
+        const int kc = k < n ? k : n - 1;
+        a[s] = *reinterpret_cast<const vec_t*>(A + rowc + (int64_t)kc * m);
       }
     };
     auto load_w = [&](int k0, TM* dst) {
@@ -1121,7 +1157,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A,
       for (int u = 0; u < NWS; ++u) {
         const int e = t + kThreads * u;
         const int kk = e / (NT * 16), cc = e % (NT * 16);
-        dst[u] = (e < KC * NT * 16 && k0 + kk < n && cc < c) ? (TM)W[(int64_t)(k0 + kk) * c + cc] : (TM)0;
+        const bool ok = e < KC * NT * 16 && k0 + kk < n && cc < c;
+        const double v = W[ok ? (int64_t)(k0 + kk) * c + cc : 0];
+        dst[u] = ok ? (TM)v : (TM)0;
       }
     };
     auto store_w = [&](const TM* src, int buf) {
@@ -1136,30 +1174,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A,
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int q = 0; q < NT; ++q) acc[rb][q] = acc_t{0, 0, 0, 0};
-    vec_t a[NS], an[NS];
-    TM wn[NWS];
-    __syncthreads();   // the previous tile's reads of sW are done
-    load_w(0, wn);
-    load_a(0, a);
-    store_w(wn, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < n; k0 += KC) {
-      const bool more = k0 + KC < n;
-      if (more) {
-        load_w(k0 + KC, wn);
-        load_a(k0 + KC, an);
-      }
+    auto mma = [&](const vec_t* a, int buf, int k0) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         TM b[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) b[q] = sW[buf][4 * s + g][16 * q + li];
+        const bool kok = k0 + 4 * s + g < n;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if constexpr (!F32M) {   // the FP32 form is launched without sums
             const double xd = (double)a[s][rb];
-            ssa = fma(xd, xd, ssa);
+            ssa = fma(xd, (kok && row + rb < m) ? xd : 0.0, ssa);
           }
           const TM x = (TM)a[s][rb];
 #pragma unroll
@@ -1169,13 +1195,30 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax_cv(const TA* __restrict__ A,
           }
         }
       }
-      if (more) {
-        store_w(wn, buf ^ 1);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) a[s] = an[s];
-      }
+    };
+    vec_t a0[NS], a1[NS];
+    TM wn[NWS];
+    __syncthreads();   // the previous tile's reads of sW are done
+    load_w(0, wn);
+    store_w(wn, 0);
+    load_a(0, a0);
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += 2 * KC) {
+      // chunk k0 in a0 / sW[0]; chunk k0 + KC in a1 / sW[1] (past the last
+      // chunk: an unused clamped reload)
+      const bool more1 = k0 + KC < n;
+      load_w(k0 + KC, wn);
+      load_a(more1 ? k0 + KC : k0, a1);
+      mma(a0, 0, k0);
+      store_w(wn, 1);
       __syncthreads();
-      buf ^= 1;
+      if (!more1) break;
+      const bool more2 = k0 + 2 * KC < n;
+      load_w(k0 + 2 * KC, wn);
+      load_a(more2 ? k0 + 2 * KC : k0 + KC, a0);
+      mma(a1, 1, k0 + KC);
+      store_w(wn, 0);
+      __syncthreads();
     }
     // result register v of a lane holds MFMA row rho = g + 4v (FP64) or 4g + v (FP32)
 #pragma unroll
@@ -1398,13 +1441,15 @@ static bool ax_cv_ok(const TA* A, const TY* Y, int64_t m) {
   return ((uintptr_t)A % (RB * sizeof(TA))) == 0 && m % RB == 0 && ((uintptr_t)Y % (RB * sizeof(TY))) == 0;
 }
 // Row runs (RB) and W chunk width (KC) of the vector A*W, as measured fastest
-// at 32768 x 512 (FP64, c = 24) and 640000 x 1280 (FP64 and FP32, c = 48):
-// FP64 data in runs of 2 rows, FP32 data in runs of 4 (2 where the FP64
-// accumulators of 4 rows would not fit the registers).
+// at 32768 x 512 (FP64, c = 24), 640000 x 1280 (FP64 and FP32, c = 48) and
+// 2560000 x 1280 (c = 40 and 48: KC = 32 for FP64 data with c <= 48 and for
+// the FP32 matrix-core form, 3-4% faster than 16): FP64 data in runs of 2
+// rows, FP32 data in runs of 4 (2 where the FP64 accumulators of 4 rows would
+// not fit the registers: FP64 matrix cores with c > 32).
 template <typename TA, int NT, bool F32M>
 struct AxvCfg {
-  static constexpr int RB = sizeof(TA) == 8 ? 2 : (F32M || NT <= 3 ? 4 : 2);
-  static constexpr int KC = (sizeof(TA) == 8 && NT <= 2) || (sizeof(TA) == 4 && RB == 2) ? 32 : 16;
+  static constexpr int RB = sizeof(TA) == 8 ? 2 : (F32M || NT <= 2 ? 4 : 2);
+  static constexpr int KC = NT <= 3 && (sizeof(TA) == 8 || RB == 2 || F32M) ? 32 : 16;
 };
 
 template <typename TA, typename TY, int LY>
@@ -1640,16 +1685,25 @@ hipError_t launch_fused_ata(const double* A, const double* X, int64_t m, int n, 
 hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64_t m, int n, int c, int layout,
                        int f32_mma, double* partials, int nchunks, hipStream_t st) {
   if (n < 1 || c < 1 || c > kCMax || m < 1 || nchunks < 1) return hipErrorInvalidValue;
-  const int64_t rpc = (m + nchunks - 1) / nchunks;
+  int64_t rpc = (m + nchunks - 1) / nchunks;
+  // vector loads: column-major A with 16-byte aligned columns, chunks of whole
+  // 32-row tiles (the row chunks are rounded up; trailing chunks may be empty
+  // and then write zero partials)
+  const int64_t vl = a_f32 ? 4 : 2;
+  const bool vec = layout == COL && ((uintptr_t)A % 16) == 0 && m % vl == 0;
+  if (vec) rpc = (rpc + kAtb2TR - 1) / kAtb2TR * kAtb2TR;
   dim3 grid(nchunks, (n + kAtb2JB - 1) / kAtb2JB), block(kAtb2Threads);
 #define TT_A2(TAV, TYV, NTV, F32V)                                                                           \
   do {                                                                                                       \
     if (layout == ROW)                                                                                       \
-      TT_LAUNCH((k_atb2<TAV, TYV, NTV, ROW, F32V>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, n, c, \
-                rpc, partials);                                                                              \
+      TT_LAUNCH((k_atb2<TAV, TYV, NTV, ROW, F32V, false>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
+                n, c, rpc, partials);                                                                        \
+    else if (vec)                                                                                            \
+      TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V, true>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
+                n, c, rpc, partials);                                                                        \
     else                                                                                                     \
-      TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, n, c, \
-                rpc, partials);                                                                              \
+      TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V, false>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
+                n, c, rpc, partials);                                                                        \
   } while (0)
 #define TT_A2_NT(TAV, TYV, F32V)                                                                              \
   do {                                                                                                       \

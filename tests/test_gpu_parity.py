@@ -562,3 +562,11 @@ def test_mixed_eps_1e6_function_tensor():
         assert rse <= 1e-6
         assert np.linalg.norm(rec - a) <= rep["err_bound"] * (1 + 1e-6) + 1e-12
     assert max(abs(x - y) for x, y in zip(rmx["ranks"], r64["ranks"])) <= 1
+    # measured step errors: the stated bound of the mixed form is within eps
+    assert rmx["err_bound"] <= 1e-6 * rmx["norm_A"]
+    # estimated step errors (the default): the same call meets its rank rule
+    # (the estimates' rounding noise must not turn into TT_ERANK)
+    cdf, rdf = T.tt_utv_decompose(A, dims, eps=1e-6, sweep="R2L", variant="URV", q=1, oversample=8, seed=3,
+                                  prec="mixed")
+    assert rdf["status"] == T.TT_OK and rdf["rank_rule_met"]
+    assert rdf["ranks"] == rmx["ranks"]
