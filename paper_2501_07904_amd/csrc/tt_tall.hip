@@ -726,13 +726,19 @@ __global__ __launch_bounds__(kThreads) void k_atb_lp(const TA* __restrict__ A, c
 // aligned A, chunks of whole tiles): each lane reads 16 contiguous bytes of
 // one column of A per load (2 FP64 or 4 FP32 rows), at clamped in-range
 // addresses with rows and columns outside the chunk zeroed when staged.
+// The (chunk, column block) pairs are numbered chunk-major and dealt to the
+// eight XCDs in contiguous runs (hardware workgroup b runs on XCD b % 8), so
+// that the column blocks sharing a chunk's rows of Y mostly run on one XCD
+// and read those rows once from HBM into its L2: dealt round-robin, each
+// chunk's ten column blocks (n = 1280) spread over all eight XCDs and Y was
+// fetched about eight times.
 constexpr int kAtb2Threads = 512;
 constexpr int kAtb2JB = 128;
 constexpr int kAtb2TR = 32;
 
 template <typename TA, typename TY, int NT, int LY, bool F32, bool VEC>
 __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A, const TY* __restrict__ Y, int64_t m,
-                                                       int n, int c, int64_t rows_per_chunk,
+                                                       int n, int c, int64_t rows_per_chunk, int nchunks,
                                                        double* __restrict__ partials) {
   typedef typename std::conditional<F32, float, double>::type T;
   typedef typename std::conditional<F32, f4, d4>::type V4;
@@ -747,8 +753,13 @@ __global__ __launch_bounds__(kAtb2Threads) void k_atb2(const TA* __restrict__ A,
   __shared__ T sY[kAtb2TR][WY + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t chunk = blockIdx.x;
-  const int j0 = blockIdx.y * kAtb2JB;
+  const int ncb = (n + kAtb2JB - 1) / kAtb2JB;
+  const int64_t npairs = (int64_t)nchunks * ncb;
+  const int64_t per_xcd = gridDim.x / 8;                // gridDim.x = roundup(npairs, 8)
+  const int64_t pair = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (pair >= npairs) return;
+  const int64_t chunk = pair / ncb;
+  const int j0 = (int)(pair % ncb) * kAtb2JB;
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = min(m, r0 + rows_per_chunk);
   // element e of a tile: COL -> (row e % TR, col e / TR); ROW -> (row e / W, col e % W);
@@ -1692,18 +1703,21 @@ hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64
   const int64_t vl = a_f32 ? 4 : 2;
   const bool vec = layout == COL && ((uintptr_t)A % 16) == 0 && m % vl == 0;
   if (vec) rpc = (rpc + kAtb2TR - 1) / kAtb2TR * kAtb2TR;
-  dim3 grid(nchunks, (n + kAtb2JB - 1) / kAtb2JB), block(kAtb2Threads);
+  // one workgroup per (chunk, column block) pair, rounded up to whole XCD shares
+  const int64_t npairs = (int64_t)nchunks * ((n + kAtb2JB - 1) / kAtb2JB);
+  if (npairs > 0x7ffffff8LL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((npairs + 7) / 8 * 8)), block(kAtb2Threads);
 #define TT_A2(TAV, TYV, NTV, F32V)                                                                           \
   do {                                                                                                       \
     if (layout == ROW)                                                                                       \
       TT_LAUNCH((k_atb2<TAV, TYV, NTV, ROW, F32V, false>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
-                n, c, rpc, partials);                                                                        \
+                n, c, rpc, nchunks, partials);                                                               \
     else if (vec)                                                                                            \
       TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V, true>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
-                n, c, rpc, partials);                                                                        \
+                n, c, rpc, nchunks, partials);                                                               \
     else                                                                                                     \
       TT_LAUNCH((k_atb2<TAV, TYV, NTV, COL, F32V, false>), grid, block, 0, st, (const TAV*)A, (const TYV*)Y, m, \
-                n, c, rpc, partials);                                                                        \
+                n, c, rpc, nchunks, partials);                                                               \
   } while (0)
 #define TT_A2_NT(TAV, TYV, F32V)                                                                              \
   do {                                                                                                       \
