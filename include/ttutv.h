@@ -223,31 +223,51 @@ int tt_reconstruct_backward(int d, const int64_t* dims, const int64_t* ranks, co
                             const void* gout, tt_dtype dtype, double* const* gcores, void* work,
                             size_t work_bytes, void* stream);
 
-/* Entries of the train at N multi-indices, Eq. (TT).  idx: device, N x d
- * int64 row-major, 0-based, each i_k < I_k (not checked on the device: the
- * caller guarantees it); out: device, N doubles.  Enqueues only. */
-int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
-              const int64_t* idx, int64_t N, double* out, void* stream);
+/* Entries of the train at N multi-indices, Eq. (TT).  cores: host array of d
+ * device pointers of `core_dtype` (TT_F64 or TT_F32; layout above); idx:
+ * device, N x d int64 row-major, 0-based, each i_k < I_k (not checked on the
+ * device: the caller guarantees it); out: device, N doubles (FP64 products).
+ * With every rank <= 32 each thread carries one sample's running row vector
+ * in registers, the cores staged once per workgroup in LDS when they fit;
+ * wider trains (ranks up to 64, FP64 cores only) take one wave per sample.
+ * Enqueues only. */
+int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const void* const* cores,
+              tt_dtype core_dtype, const int64_t* idx, int64_t N, double* out, void* stream);
 
-/* Gradient of L = sum_s gout[s] * A_TT[idx_s] with respect to every core:
- * gcores[k] (device, same layout and size as core k) is overwritten with
- * dL/dG_k.  The left and right interface products of each sample are
- * recomputed, not stored.  Enqueues only. */
+/* Device bytes of workspace tt_sample_backward(_mixed) needs for N samples of
+ * this train (0 when a rank exceeds 32). */
+int tt_sample_backward_workspace(int d, const int64_t* dims, const int64_t* ranks, int64_t N,
+                                 size_t* bytes);
+
+/* Gradient of L = sum_s gout[s] * A_TT[idx_s] with respect to every core, the
+ * derivative of Eq. (TT) at the sampled entries: dL/dG_k(a, i, b) = sum over
+ * the samples with i_k = i of gout[s] Left_k^s(a) Right_k^s(b), Left_k^s =
+ * G_1[i_1] ... G_{k-1}[i_{k-1}] and Right_k^s = G_{k+1}[i_{k+1}] ... G_d[i_d].
+ * gcores[k] (device, same type, layout and size as core k) is overwritten.
+ * The interface products of each sample are recomputed from the cores (not
+ * kept from a forward call) into `work` (tt_sample_backward_workspace bytes,
+ * in blocks of at most 2^20 samples); each of 256 workgroups sums the products
+ * of its share of the samples in LDS, every gradient entry owned by one
+ * thread that adds in sample order, and the workgroups' partials are summed
+ * in a fixed order: the result is bitwise reproducible.  Trains with a rank
+ * above 32 use FP64 atomics instead (not reproducible bitwise; work unused).
+ * Enqueues only. */
 int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks,
-                       const double* const* cores, const int64_t* idx, int64_t N,
-                       const double* gout, double* const* gcores, void* stream);
+                       const void* const* cores, tt_dtype core_dtype, const int64_t* idx, int64_t N,
+                       const double* gout, void* const* gcores, void* work, size_t work_bytes,
+                       void* stream);
 
 /* The same gradient taken at the mixed-canonical points of one train, the
  * ingredient of its Riemannian gradient (Sec. 4.3, RGrad for completion):
  * gcores[k] = dL/dC_k of L = sum_s gout[s] * (L_1..L_{k-1} C_k R_{k+1}..R_d)[idx_s],
  * where L_j = left_cores[j] (left-orthogonal form) and R_j = right_cores[j]
  * (right-orthogonal form of the same train, same ranks); with left_cores ==
- * right_cores it is tt_sample_backward.  Same layouts, checks and stream
- * behaviour as tt_sample_backward. */
+ * right_cores it is tt_sample_backward.  Same layouts, checks, workspace and
+ * stream behaviour as tt_sample_backward. */
 int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks,
-                             const double* const* left_cores, const double* const* right_cores,
-                             const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
-                             void* stream);
+                             const void* const* left_cores, const void* const* right_cores,
+                             tt_dtype core_dtype, const int64_t* idx, int64_t N, const double* gout,
+                             void* const* gcores, void* work, size_t work_bytes, void* stream);
 
 const char* tt_last_error(void);
 

@@ -24,7 +24,8 @@ DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose",
            "tt_utv_decompose_noalloc",
            "tt_reconstruct_workspace", "tt_reconstruct", "tt_reconstruct_backward_workspace",
-           "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed",
+           "tt_reconstruct_backward", "tt_sample", "tt_sample_backward_workspace", "tt_sample_backward",
+           "tt_sample_backward_mixed",
            "tt_last_error", "tt_kernel_class_name"]
 
 
@@ -91,14 +92,19 @@ def load_library(path=LIB_PATH):
     lib.tt_reconstruct_backward_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(ctypes.c_size_t)]
     lib.tt_reconstruct_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int,
                                             ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
-    lib.tt_sample.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp, vp]
-    lib.tt_sample_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), vp, ctypes.c_int64, vp,
-                                       ctypes.POINTER(vp), vp]
-    lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
-                                             ctypes.c_int64, vp, ctypes.POINTER(vp), vp]
+    lib.tt_sample.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_int64, vp,
+                              vp]
+    lib.tt_sample_backward_workspace.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int64,
+                                                 ctypes.POINTER(ctypes.c_size_t)]
+    lib.tt_sample_backward.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.c_int, vp,
+                                       ctypes.c_int64, vp, ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             ctypes.c_int, vp, ctypes.c_int64, vp, ctypes.POINTER(vp), vp,
+                                             ctypes.c_size_t, vp]
     for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_utv_decompose_noalloc",
                  "tt_reconstruct_workspace",
-                 "tt_reconstruct", "tt_reconstruct_backward_workspace", "tt_reconstruct_backward", "tt_sample", "tt_sample_backward", "tt_sample_backward_mixed"):
+                 "tt_reconstruct", "tt_reconstruct_backward_workspace", "tt_reconstruct_backward", "tt_sample",
+                 "tt_sample_backward_workspace", "tt_sample_backward", "tt_sample_backward_mixed"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -375,30 +381,50 @@ def tt_reconstruct_backward(cores, gout, stream=None):
     return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(d)]
 
 
+def _sample_buffers(cores):
+    """Column-major flat buffers of the cores for the sampling kernels: FP32
+    when every core is float32 (the kernels take FP32 cores as they are),
+    else FP64.  Returns (buffers, dtype code)."""
+    if all(g.dtype == torch.float32 for g in cores):
+        return [g.permute(2, 1, 0).contiguous().reshape(-1) for g in cores], DTYPES[torch.float32]
+    return _core_buffers(cores), DTYPES[torch.float64]
+
+
 def tt_sample(cores, idx, stream=None):
-    """Train entries at the rows of idx (N x d int64, 0-based, on the device)."""
+    """Train entries at the rows of idx (N x d int64, 0-based, on the device);
+    float64 results for float64 or float32 cores."""
     lib = load_library()
     dims, ranks = _train_shape(cores)
     idx = check_indices(idx, dims, cores[0].device)
     N = idx.shape[0]
-    bufs = _core_buffers(cores)
+    bufs, dt = _sample_buffers(cores)
     out = torch.empty(N, dtype=torch.float64, device=cores[0].device)
-    _check(lib.tt_sample(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()), N,
+    _check(lib.tt_sample(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), dt, ctypes.c_void_p(idx.data_ptr()), N,
                          ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 
+def _sample_work(dims, ranks, N, device):
+    lib = load_library()
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.tt_sample_backward_workspace(len(dims), _i64(dims), _i64(ranks), N, ctypes.byref(nbytes)))
+    return torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=device), nbytes.value
+
+
 def tt_sample_backward(cores, idx, gout, stream=None):
-    """Core gradients of sum_s gout[s] * A_TT[idx_s]; list of (r0, I, r1) tensors."""
+    """Core gradients of sum_s gout[s] * A_TT[idx_s]; list of (r0, I, r1)
+    tensors in the cores' precision (float32 for float32 cores)."""
     lib = load_library()
     dims, ranks = _train_shape(cores)
     idx = check_indices(idx, dims, cores[0].device)
     N = idx.shape[0]
     gout = check_gout(gout, N, cores[0].device)
-    bufs = _core_buffers(cores)
+    bufs, dt = _sample_buffers(cores)
     gflat = [torch.empty_like(b) for b in bufs]
-    _check(lib.tt_sample_backward(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), ctypes.c_void_p(idx.data_ptr()),
-                                  N, ctypes.c_void_p(gout.data_ptr()), _ptrs(gflat), _stream(stream)))
+    work, nbytes = _sample_work(dims, ranks, N, cores[0].device)
+    _check(lib.tt_sample_backward(len(dims), _i64(dims), _i64(ranks), _ptrs(bufs), dt,
+                                  ctypes.c_void_p(idx.data_ptr()), N, ctypes.c_void_p(gout.data_ptr()), _ptrs(gflat),
+                                  ctypes.c_void_p(work.data_ptr()), nbytes, _stream(stream)))
     return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
 
 
@@ -413,11 +439,15 @@ def tt_sample_backward_mixed(left_cores, right_cores, idx, gout, stream=None):
     idx = check_indices(idx, dims, left_cores[0].device)
     N = idx.shape[0]
     gout = check_gout(gout, N, left_cores[0].device)
-    lb, rb = _core_buffers(left_cores), _core_buffers(right_cores)
+    lb, dl = _sample_buffers(left_cores)
+    rb, dr = _sample_buffers(right_cores)
+    if dl != dr:
+        lb, rb, dl = _core_buffers(left_cores), _core_buffers(right_cores), DTYPES[torch.float64]
     gflat = [torch.empty_like(b) for b in lb]
-    _check(lib.tt_sample_backward_mixed(len(dims), _i64(dims), _i64(ranks), _ptrs(lb), _ptrs(rb),
+    work, nbytes = _sample_work(dims, ranks, N, left_cores[0].device)
+    _check(lib.tt_sample_backward_mixed(len(dims), _i64(dims), _i64(ranks), _ptrs(lb), _ptrs(rb), dl,
                                         ctypes.c_void_p(idx.data_ptr()), N, ctypes.c_void_p(gout.data_ptr()),
-                                        _ptrs(gflat), _stream(stream)))
+                                        _ptrs(gflat), ctypes.c_void_p(work.data_ptr()), nbytes, _stream(stream)))
     return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
 
 

@@ -1075,46 +1075,82 @@ int tt_reconstruct_backward(int d, const int64_t* dims, const int64_t* ranks, co
   return TT_OK;
 }
 
-int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
-              const int64_t* idx, int64_t N, double* out, void* stream) {
-  if (d < 2 || d > TT_MAX_D || !dims || !ranks || !cores) return fail(TT_EINVAL, "bad train description");
+static int train_checks(int d, const int64_t* dims, const int64_t* ranks, tt_dtype dtype) {
+  if (d < 2 || d > TT_MAX_D || !dims || !ranks) return fail(TT_EINVAL, "bad train description");
+  for (int k = 0; k < d; ++k)
+    if (dims[k] < 1) return fail(TT_EINVAL, "dims[%d] < 1", k);
   for (int k = 0; k <= d; ++k)
     if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
   if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "bad core dtype");
+  // the one-sample-per-thread kernels hold vectors of up to 32 entries; wider
+  // trains take the wave-per-sample kernels, which read FP64 cores only
+  if (dtype == TT_F32 && sample_rm(d, ranks) == 0)
+    return fail(TT_EUNSUPPORTED, "FP32 cores need every rank <= 32");
+  return TT_OK;
+}
+
+int tt_sample(int d, const int64_t* dims, const int64_t* ranks, const void* const* cores, tt_dtype core_dtype,
+              const int64_t* idx, int64_t N, double* out, void* stream) {
+  int rc = train_checks(d, dims, ranks, core_dtype);
+  if (rc) return rc;
+  if (!cores) return fail(TT_EINVAL, "cores is NULL");
   if (N < 0) return fail(TT_EINVAL, "N < 0");
   if (N > 0 && (!idx || !out)) return fail(TT_EINVAL, "idx/out is NULL");
-  HIP_OK(launch_sample(d, dims, ranks, cores, idx, N, out, (hipStream_t)stream));
+  for (int k = 0; k < d; ++k)
+    if (!cores[k]) return fail(TT_EINVAL, "cores[%d] is NULL", k);
+  if (sample_rm(d, ranks))
+    HIP_OK(launch_sample2(d, dims, ranks, cores, core_dtype == TT_F32, idx, N, out, (hipStream_t)stream));
+  else
+    HIP_OK(launch_sample(d, dims, ranks, (const double* const*)cores, idx, N, out, (hipStream_t)stream));
   return TT_OK;
 }
 
-static int sample_bwd_checks(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
-                             const int64_t* idx, int64_t N, const double* gout, double* const* gcores) {
-  if (d < 2 || d > TT_MAX_D || !dims || !ranks || !cores || !gcores) return fail(TT_EINVAL, "bad train description");
-  for (int k = 0; k <= d; ++k)
-    if (ranks[k] < 1 || ranks[k] > kCMax) return fail(TT_EUNSUPPORTED, "rank %lld outside [1, 64]", (long long)ranks[k]);
-  if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "r_0 and r_d must be 1");
+int tt_sample_backward_workspace(int d, const int64_t* dims, const int64_t* ranks, int64_t N, size_t* bytes) {
+  if (!bytes) return fail(TT_EINVAL, "bytes is NULL");
+  int rc = train_checks(d, dims, ranks, TT_F64);
+  if (rc) return rc;
+  if (N < 0) return fail(TT_EINVAL, "N < 0");
+  *bytes = sample_rm(d, ranks) ? sample_bwd2_workspace(d, dims, ranks, N) : 0;
+  return TT_OK;
+}
+
+static int sample_bwd(int d, const int64_t* dims, const int64_t* ranks, const void* const* left,
+                      const void* const* right, tt_dtype dtype, const int64_t* idx, int64_t N, const double* gout,
+                      void* const* gcores, void* work, size_t work_bytes, void* stream) {
+  int rc = train_checks(d, dims, ranks, dtype);
+  if (rc) return rc;
+  if (!left || !right || !gcores) return fail(TT_EINVAL, "cores/gcores is NULL");
+  for (int k = 0; k < d; ++k)
+    if (!left[k] || !right[k] || !gcores[k]) return fail(TT_EINVAL, "core or gradient pointer %d is NULL", k);
   if (N < 0) return fail(TT_EINVAL, "N < 0");
   if (N > 0 && (!idx || !gout)) return fail(TT_EINVAL, "idx/gout is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (sample_rm(d, ranks)) {
+    const size_t need = sample_bwd2_workspace(d, dims, ranks, N);
+    if (!work || work_bytes < need) return fail(TT_ENOSPC, "workspace %zu bytes < %zu needed", work_bytes, need);
+    HIP_OK(launch_sample_bwd2(d, dims, ranks, left, right, dtype == TT_F32, idx, N, gout, gcores, work, work_bytes,
+                              st));
+  } else {
+    HIP_OK(launch_sample_bwd(d, dims, ranks, (const double* const*)left,
+                             right == left ? nullptr : (const double* const*)right, idx, N, gout,
+                             (double* const*)gcores, st));
+  }
   return TT_OK;
 }
 
-int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
-                       const int64_t* idx, int64_t N, const double* gout, double* const* gcores,
-                       void* stream) {
-  const int rc = sample_bwd_checks(d, dims, ranks, cores, idx, N, gout, gcores);
-  if (rc != TT_OK) return rc;
-  HIP_OK(launch_sample_bwd(d, dims, ranks, cores, nullptr, idx, N, gout, gcores, (hipStream_t)stream));
-  return TT_OK;
+int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks, const void* const* cores,
+                       tt_dtype core_dtype, const int64_t* idx, int64_t N, const double* gout, void* const* gcores,
+                       void* work, size_t work_bytes, void* stream) {
+  return sample_bwd(d, dims, ranks, cores, cores, core_dtype, idx, N, gout, gcores, work, work_bytes, stream);
 }
 
-int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks, const double* const* left_cores,
-                             const double* const* right_cores, const int64_t* idx, int64_t N, const double* gout,
-                             double* const* gcores, void* stream) {
-  const int rc = sample_bwd_checks(d, dims, ranks, left_cores, idx, N, gout, gcores);
-  if (rc != TT_OK) return rc;
+int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks, const void* const* left_cores,
+                             const void* const* right_cores, tt_dtype core_dtype, const int64_t* idx, int64_t N,
+                             const double* gout, void* const* gcores, void* work, size_t work_bytes, void* stream) {
   if (!right_cores) return fail(TT_EINVAL, "right_cores is NULL");
-  HIP_OK(launch_sample_bwd(d, dims, ranks, left_cores, right_cores, idx, N, gout, gcores, (hipStream_t)stream));
-  return TT_OK;
+  return sample_bwd(d, dims, ranks, left_cores, right_cores, core_dtype, idx, N, gout, gcores, work, work_bytes,
+                    stream);
 }
 
 }  // extern "C"

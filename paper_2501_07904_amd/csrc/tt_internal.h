@@ -150,6 +150,17 @@ hipError_t launch_transpose(const double* in, int64_t rows, int64_t cols, double
 hipError_t launch_sample(int d, const int64_t* dims, const int64_t* ranks,
                          const double* const* cores, const int64_t* idx, int64_t N, double* out,
                          hipStream_t st);
+// One sample per thread (every rank <= 32: sample_rm > 0): cores FP64 or FP32
+// (f32), staged in LDS when they fit.
+int sample_rm(int d, const int64_t* ranks);
+hipError_t launch_sample2(int d, const int64_t* dims, const int64_t* ranks, const void* const* cores, int f32,
+                          const int64_t* idx, int64_t N, double* out, hipStream_t st);
+// Backward through interface products stored in `work` and per-workgroup
+// partial gradients summed in a fixed order; gcores in the cores' type.
+size_t sample_bwd2_workspace(int d, const int64_t* dims, const int64_t* ranks, int64_t N);
+hipError_t launch_sample_bwd2(int d, const int64_t* dims, const int64_t* ranks, const void* const* left,
+                              const void* const* right, int f32, const int64_t* idx, int64_t N, const double* gout,
+                              void* const* gcores, void* work, size_t work_bytes, hipStream_t st);
 // right_cores: NULL for the gradient of the train itself; else the right
 // interface products come from right_cores (a second form of the same train).
 hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,

@@ -288,6 +288,341 @@ bool fill_desc(TrainDesc& D, int d, const int64_t* dims, const int64_t* ranks,
   return true;
 }
 
+// ---- sampled entries, one sample per thread --------------------------------
+// The forward chain v <- v G_k[:, i_k, :] and the interface products of the
+// backward run one sample per thread with the running vector in registers
+// (RM >= every rank).  The cores are staged once per workgroup into LDS when
+// they fit, each core k as a padded copy with element (a, i, b) at a + P_k (i +
+// I_k b), P_k the smallest odd number >= r_{k-1}: the lanes of a wave read the
+// same (a, b) of different slices i, and an odd slice stride puts those reads
+// on different banks.  Cores that do not fit are read from global memory.
+constexpr int kSmpMaxD = 32;
+constexpr int kSmpGroups = 256;          // workgroups of the staged kernels (one per CU)
+constexpr int kAccThreads = 512;         // gradient accumulation workgroup
+constexpr int kAccSB = 128;              // samples staged per accumulation round
+constexpr int kLdsMax = 160 * 1024;      // LDS per workgroup on gfx950
+
+struct SmpTrain {
+  int d;
+  int f32;                           // cores stored as FP32 (else FP64)
+  int64_t dims[kSmpMaxD];
+  int ranks[kSmpMaxD + 1];
+  const void* left[kSmpMaxD];        // cores of the forward chain and of the left products
+  const void* right[kSmpMaxD];       // cores of the right products
+  int stride[kSmpMaxD];              // a-stride P_k of the padded LDS copies
+  int loff[kSmpMaxD];                // LDS offset (doubles) of left core k; -1: global memory
+  int roff[kSmpMaxD];                // the same for right core k (== loff when shared)
+};
+
+struct LdsAcc {
+  const double* base;   // slice i of the padded copy
+  int sb;               // stride between b columns
+  __device__ __forceinline__ double operator()(int a, int b) const { return base[a + sb * b]; }
+};
+template <typename TC>
+struct GlbAcc {
+  const TC* base;       // core + r_{k-1} i
+  int64_t sb;           // r_{k-1} I_k
+  __device__ __forceinline__ double operator()(int a, int b) const { return (double)base[a + sb * b]; }
+};
+
+// nv[b] = sum_{a < ra} v[a] G(a, b) for b < rb; nv[b] = 0 beyond rb
+template <int RM, typename ACC>
+__device__ __forceinline__ void mv_left(const ACC& G, int ra, int rb, const double* v, double* nv) {
+#pragma unroll
+  for (int b = 0; b < RM; ++b) {
+    double acc = 0.0;
+    if (b < rb) {
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < ra) acc = fma(v[a], G(a, b), acc);
+    }
+    nv[b] = acc;
+  }
+}
+// nr[a] = sum_{b < rb} G(a, b) r[b] for a < ra; nr[a] = 0 beyond ra
+template <int RM, typename ACC>
+__device__ __forceinline__ void mv_right(const ACC& G, int ra, int rb, const double* r, double* nr) {
+#pragma unroll
+  for (int a = 0; a < RM; ++a) nr[a] = 0.0;
+#pragma unroll
+  for (int b = 0; b < RM; ++b) {
+    if (b < rb) {
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < ra) nr[a] = fma(G(a, b), r[b], nr[a]);
+    }
+  }
+}
+
+template <int RM>
+__device__ __forceinline__ void step_left(const SmpTrain& T, const double* sh, int k, int64_t i, const double* v,
+                                          double* nv) {
+  const int ra = T.ranks[k], rb = T.ranks[k + 1];
+  if (T.loff[k] >= 0)
+    mv_left<RM>(LdsAcc{sh + T.loff[k] + (int64_t)T.stride[k] * i, T.stride[k] * (int)T.dims[k]}, ra, rb, v, nv);
+  else if (T.f32)
+    mv_left<RM>(GlbAcc<float>{(const float*)T.left[k] + ra * i, (int64_t)ra * T.dims[k]}, ra, rb, v, nv);
+  else
+    mv_left<RM>(GlbAcc<double>{(const double*)T.left[k] + ra * i, (int64_t)ra * T.dims[k]}, ra, rb, v, nv);
+}
+template <int RM>
+__device__ __forceinline__ void step_right(const SmpTrain& T, const double* sh, int k, int64_t i, const double* r,
+                                           double* nr) {
+  const int ra = T.ranks[k], rb = T.ranks[k + 1];
+  if (T.roff[k] >= 0)
+    mv_right<RM>(LdsAcc{sh + T.roff[k] + (int64_t)T.stride[k] * i, T.stride[k] * (int)T.dims[k]}, ra, rb, r, nr);
+  else if (T.f32)
+    mv_right<RM>(GlbAcc<float>{(const float*)T.right[k] + ra * i, (int64_t)ra * T.dims[k]}, ra, rb, r, nr);
+  else
+    mv_right<RM>(GlbAcc<double>{(const double*)T.right[k] + ra * i, (int64_t)ra * T.dims[k]}, ra, rb, r, nr);
+}
+
+// copy the cores marked for LDS into their padded layout
+template <int NTH>
+__device__ void stage_cores(const SmpTrain& T, double* sh) {
+  for (int k = 0; k < T.d; ++k) {
+    for (int side = 0; side < 2; ++side) {
+      const int off = side ? T.roff[k] : T.loff[k];
+      if (off < 0 || (side == 1 && T.roff[k] == T.loff[k])) continue;
+      const void* src = side ? T.right[k] : T.left[k];
+      const int ra = T.ranks[k], rb = T.ranks[k + 1];
+      const int64_t I = T.dims[k];
+      const int64_t n = (int64_t)ra * I * rb;
+      for (int64_t e = threadIdx.x; e < n; e += NTH) {
+        const int a = (int)(e % ra);
+        const int64_t rest = e / ra;
+        const int64_t i = rest % I, b = rest / I;
+        const double x = T.f32 ? (double)((const float*)src)[e] : ((const double*)src)[e];
+        sh[off + a + (int64_t)T.stride[k] * (i + I * b)] = x;
+      }
+    }
+  }
+}
+
+// out[s] = the train's entry at row s of idx
+template <int RM, int NTH>
+__global__ __launch_bounds__(NTH) void k_sample_t(SmpTrain T, const int64_t* __restrict__ idx, int64_t N,
+                                                  double* __restrict__ out) {
+  extern __shared__ double sh[];
+  stage_cores<NTH>(T, sh);
+  __syncthreads();
+  const int d = T.d;
+  for (int64_t s = (int64_t)blockIdx.x * NTH + threadIdx.x; s < N; s += (int64_t)gridDim.x * NTH) {
+    const int64_t* ix = idx + s * d;
+    double v[RM], nv[RM];
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = a == 0 ? 1.0 : 0.0;
+    for (int k = 0; k < d; ++k) {
+      step_left<RM>(T, sh, k, ix[k], v, nv);
+#pragma unroll
+      for (int a = 0; a < RM; ++a) v[a] = nv[a];
+    }
+    out[s] = v[0];
+  }
+}
+
+// Interface products of samples s0 .. s0+nb-1 (one per thread): for every
+// core k, L_k[s] = gout[s] * G_1[i_1] ... G_{k-1}[i_{k-1}] (r_{k-1} entries,
+// left cores) and R_k[s] = G_{k+1}[i_{k+1}] ... G_d[i_d] (r_k entries, right
+// cores), stored sample-major at ws + lo[k] and ws + ro[k].
+struct IfaceOut {
+  int64_t lo[kSmpMaxD], ro[kSmpMaxD];
+};
+template <int RM, int NTH>
+__global__ __launch_bounds__(NTH) void k_sample_iface(SmpTrain T, const int64_t* __restrict__ idx, int64_t s0,
+                                                      int64_t nb, const double* __restrict__ gout,
+                                                      double* __restrict__ ws, IfaceOut O) {
+  extern __shared__ double sh[];
+  stage_cores<NTH>(T, sh);
+  __syncthreads();
+  const int d = T.d;
+  for (int64_t q = (int64_t)blockIdx.x * NTH + threadIdx.x; q < nb; q += (int64_t)gridDim.x * NTH) {
+    const int64_t s = s0 + q;
+    const int64_t* ix = idx + s * d;
+    const double w = gout[s];
+    double v[RM], nv[RM];
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = a == 0 ? 1.0 : 0.0;
+    for (int k = 0; k < d; ++k) {
+      const int ra = T.ranks[k];
+      double* L = ws + O.lo[k] + q * ra;
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < ra) L[a] = w * v[a];
+      if (k + 1 < d) {
+        step_left<RM>(T, sh, k, ix[k], v, nv);
+#pragma unroll
+        for (int a = 0; a < RM; ++a) v[a] = nv[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = a == 0 ? 1.0 : 0.0;
+    for (int k = d - 1; k >= 0; --k) {
+      const int rb = T.ranks[k + 1];
+      double* R = ws + O.ro[k] + q * rb;
+#pragma unroll
+      for (int b = 0; b < RM; ++b)
+        if (b < rb) R[b] = v[b];
+      if (k > 0) {
+        step_right<RM>(T, sh, k, ix[k], v, nv);
+#pragma unroll
+        for (int a = 0; a < RM; ++a) v[a] = nv[a];
+      }
+    }
+  }
+}
+
+// Gradient of core k over samples s0 .. s0+nb-1 from their interface
+// products, on the FP64 matrix cores: the gradient is I_k slices of r_{k-1} x
+// r_k, each sum over the samples with i_k = i of L_s R_s^T, cut into 16 x 16
+// tiles.  Workgroup w takes a contiguous share of the samples and stages 128
+// of them at a time in LDS (their L, R and i_k); wave v owns tiles tau0 + v,
+// tau0 + v + 8, ... (at most eight, the accumulators held in registers for
+// the whole launch).  For a tile of slice i the wave finds the staged samples
+// with i_k = i by a ballot and feeds them four at a time, in sample order, as
+// the k dimension of v_mfma_f64_16x16x4 (operand A: L_s[a], lane (g, l) ->
+// sample g, a = l; operand B: R_s[b]).  Every tile has one owner and the
+// order of its products is fixed, so the partial sums do not depend on
+// timing; a workgroup starts from its partial of the previous sample block
+// (partials + w * total) unless `first`, and the partials are summed over
+// workgroups in a fixed order afterwards.
+struct AccDesc {
+  int d;
+  int64_t dims[kSmpMaxD];
+  int ranks[kSmpMaxD + 1];
+  int64_t coff[kSmpMaxD + 1];
+  IfaceOut O;
+};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kAccTilesPerWave = 8;
+
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_grad_mfma(AccDesc A, const int64_t* __restrict__ idx, int64_t s0, int64_t nb,
+                                                   const double* __restrict__ ws, double* __restrict__ partials,
+                                                   int64_t total, int first, int k, int tau0, int tau1, int lda) {
+  constexpr int NW = NTH / 64;
+  extern __shared__ double sh[];
+  double* stl = sh;                               // [kAccSB][lda]: L_s
+  double* str = stl + kAccSB * lda;               // [kAccSB][lda]: R_s
+  int* sti = (int*)(str + kAccSB * lda);          // [kAccSB]: i_k of the staged samples
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int d = A.d;
+  const int ra = A.ranks[k], rb = A.ranks[k + 1];
+  const int I = (int)A.dims[k];
+  const int tpa = (ra + 15) / 16, tps = tpa * ((rb + 15) / 16);   // tiles per slice
+  const int64_t coff = A.coff[k];
+  double* mine = partials + (int64_t)blockIdx.x * total;
+  d4 acc[kAccTilesPerWave];
+#pragma unroll
+  for (int j = 0; j < kAccTilesPerWave; ++j) {
+    acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+    const int tau = tau0 + wv + NW * j;
+    if (!first && tau < tau1) {
+      const int i = tau / tps, ta = (tau % tps) % tpa, tb = (tau % tps) / tpa;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * ta + g + 4 * v, b = 16 * tb + li;
+        if (a < ra && b < rb) acc[j][v] = mine[coff + a + (int64_t)ra * (i + (int64_t)I * b)];
+      }
+    }
+  }
+  const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
+  const int64_t q_beg = min(nb, (int64_t)blockIdx.x * per), q_end = min(nb, q_beg + per);
+  const double* L = ws + A.O.lo[k];
+  const double* Rv = ws + A.O.ro[k];
+  // the next round's staged values are loaded into registers while the
+  // current round runs on the matrix cores, then stored to LDS behind a barrier
+  constexpr int NPF = kAccSB * 32 / NTH;   // values per thread, ranks <= 32
+  double pl[NPF], pr[NPF];
+  int pi = 0;
+  auto fetch = [&](int64_t q0) {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = t + NTH * u;
+      const int q = e / ra, a = e % ra;
+      pl[u] = (e < kAccSB * ra && q0 + q < q_end) ? L[(q0 + q) * ra + a] : 0.0;
+      const int qb = e / rb, b = e % rb;
+      pr[u] = (e < kAccSB * rb && q0 + qb < q_end) ? Rv[(q0 + qb) * rb + b] : 0.0;
+    }
+    pi = (t < kAccSB && q0 + t < q_end) ? (int)idx[(s0 + q0 + t) * d + k] : -1;
+  };
+  if (q_beg < q_end) fetch(q_beg);
+  for (int64_t q0 = q_beg; q0 < q_end; q0 += kAccSB) {
+    __syncthreads();   // the previous round's reads of the staging area are done
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = t + NTH * u;
+      if (e < kAccSB * ra) stl[(e / ra) * lda + e % ra] = pl[u];
+      if (e < kAccSB * rb) str[(e / rb) * lda + e % rb] = pr[u];
+    }
+    if (t < kAccSB) sti[t] = pi;
+    __syncthreads();
+    if (q0 + kAccSB < q_end) fetch(q0 + kAccSB);
+    const int key0 = sti[lane], key1 = sti[64 + lane];   // -1 past the last staged sample
+#pragma unroll
+    for (int j = 0; j < kAccTilesPerWave; ++j) {
+      const int tau = tau0 + wv + NW * j;
+      if (tau >= tau1) continue;   // uniform
+      const int i = tau / tps, ta = (tau % tps) % tpa, tb = (tau % tps) / tpa;
+      uint64_t m0 = __ballot(key0 == i), m1 = __ballot(key1 == i);
+      const int a = 16 * ta + li, b = 16 * tb + li;
+      while (m0 | m1) {   // uniform: four samples of slice i per step, in sample order
+        int sg = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int sq = -1;
+          if (m0) {
+            sq = __ffsll((unsigned long long)m0) - 1;
+            m0 &= m0 - 1;
+          } else if (m1) {
+            sq = 64 + __ffsll((unsigned long long)m1) - 1;
+            m1 &= m1 - 1;
+          }
+          if (g == u) sg = sq;
+        }
+        const double lv = (sg >= 0 && a < ra) ? stl[sg * lda + a] : 0.0;
+        const double rv = (sg >= 0 && b < rb) ? str[sg * lda + b] : 0.0;
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv, rv, acc[j], 0, 0, 0);
+      }
+    }
+  }
+  // result register v of lane (g, l): row a = 16 ta + g + 4 v, column b = 16 tb + l
+#pragma unroll
+  for (int j = 0; j < kAccTilesPerWave; ++j) {
+    const int tau = tau0 + wv + NW * j;
+    if (tau >= tau1) continue;
+    const int i = tau / tps, ta = (tau % tps) % tpa, tb = (tau % tps) / tpa;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * ta + g + 4 * v, b = 16 * tb + li;
+      if (a < ra && b < rb) mine[coff + a + (int64_t)ra * (i + (int64_t)I * b)] = acc[j][v];
+    }
+  }
+}
+
+// gcores[k][e - coff[k]] = sum over workgroups of the partials, fixed order
+struct GradOut {
+  void* cores[kSmpMaxD];
+  int64_t coff[kSmpMaxD + 1];
+  int d;
+  int f32;
+};
+__global__ __launch_bounds__(kThreads) void k_grad_reduce(const double* __restrict__ partials, int nparts,
+                                                          int64_t total, GradOut G) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= total) return;
+  double s = 0.0;
+  for (int w = 0; w < nparts; ++w) s += partials[(int64_t)w * total + e];
+  int k = 0;
+  while (k + 1 < G.d && e >= G.coff[k + 1]) ++k;
+  const int64_t o = e - G.coff[k];
+  if (G.f32) ((float*)G.cores[k])[o] = (float)s;
+  else ((double*)G.cores[k])[o] = s;
+}
+
 }  // namespace
 
 hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f32, int64_t M,
@@ -373,6 +708,198 @@ hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
   }
   if (N > 0)
     TT_LAUNCH(k_sample_bwd, dim3(sample_blocks(N)), dim3(kThreads), 0, st, D, DR, idx, N, gout, G);
+  return hipGetLastError();
+}
+
+// ---- host side of the one-sample-per-thread kernels -------------------------
+namespace {
+
+constexpr int64_t kBwdBlock = (int64_t)1 << 20;   // samples per interface block of the backward
+
+struct SmpPlan {
+  SmpTrain T;
+  int rm;                // register vector length: 8, 16 or 32
+  size_t lds;            // bytes of staged cores
+  int64_t total;         // gradient entries of the concatenated cores
+  int64_t coff[kSmpMaxD + 1];
+};
+
+int smp_rm(int d, const int64_t* ranks) {
+  int64_t r = 1;
+  for (int k = 0; k <= d; ++k) r = std::max(r, ranks[k]);
+  return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : 0;
+}
+
+// Cores into LDS while the padded copies fit in `budget` bytes: the left set
+// first, then the right set when it is a different train.
+bool smp_plan(int d, const int64_t* dims, const int64_t* ranks, const void* const* left, const void* const* right,
+              int f32, size_t budget, SmpPlan& P) {
+  if (d < 2 || d > kSmpMaxD) return false;
+  P.rm = smp_rm(d, ranks);
+  if (!P.rm) return false;
+  SmpTrain& T = P.T;
+  T.d = d;
+  T.f32 = f32;
+  P.coff[0] = 0;
+  for (int k = 0; k <= d; ++k) T.ranks[k] = (int)ranks[k];
+  for (int k = 0; k < d; ++k) {
+    T.dims[k] = dims[k];
+    T.left[k] = left[k];
+    T.right[k] = right ? right[k] : left[k];
+    T.stride[k] = (int)(ranks[k] | 1);
+    P.coff[k + 1] = P.coff[k] + ranks[k] * dims[k] * ranks[k + 1];
+  }
+  P.total = P.coff[d];
+  if (P.total >= ((int64_t)1 << 31)) return false;   // 32-bit entry offsets in the accumulation
+  int64_t need_l = 0;
+  for (int k = 0; k < d; ++k) need_l += (int64_t)T.stride[k] * dims[k] * ranks[k + 1];
+  const bool same = !right || right == left;
+  int64_t used = 0;
+  const bool lds_l = need_l * 8 <= (int64_t)budget;
+  for (int k = 0; k < d; ++k) {
+    T.loff[k] = lds_l ? (int)used : -1;
+    if (lds_l) used += (int64_t)T.stride[k] * dims[k] * ranks[k + 1];
+  }
+  const bool lds_r = !same && (used + need_l) * 8 <= (int64_t)budget;
+  for (int k = 0; k < d; ++k) {
+    if (same) { T.roff[k] = T.loff[k]; continue; }
+    T.roff[k] = lds_r ? (int)used : -1;
+    if (lds_r) used += (int64_t)T.stride[k] * dims[k] * ranks[k + 1];
+  }
+  P.lds = (size_t)used * 8;
+  return true;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+unsigned smp_grid(int64_t n, int nth, size_t lds) {
+  int64_t g = (n + nth - 1) / nth;
+  const int64_t cap = lds > 0 ? kSmpGroups : 2048;   // staged cores: one workgroup per CU
+  if (g > cap) g = cap;
+  return (unsigned)std::max<int64_t>(g, 1);
+}
+
+template <int RM, int NTH>
+hipError_t run_sample(const SmpPlan& P, const int64_t* idx, int64_t N, double* out, hipStream_t st) {
+  hipError_t e = allow_lds(k_sample_t<RM, NTH>, P.lds);
+  if (e != hipSuccess) return e;
+  TT_LAUNCH((k_sample_t<RM, NTH>), dim3(smp_grid(N, NTH, P.lds)), dim3(NTH), P.lds, st, P.T, idx, N, out);
+  return hipGetLastError();
+}
+
+template <int RM, int NTH>
+hipError_t run_iface(const SmpPlan& P, const int64_t* idx, int64_t s0, int64_t nb, const double* gout, double* ws,
+                     const IfaceOut& O, hipStream_t st) {
+  hipError_t e = allow_lds(k_sample_iface<RM, NTH>, P.lds);
+  if (e != hipSuccess) return e;
+  TT_LAUNCH((k_sample_iface<RM, NTH>), dim3(smp_grid(nb, NTH, P.lds)), dim3(NTH), P.lds, st, P.T, idx, s0, nb,
+            gout, ws, O);
+  return hipGetLastError();
+}
+
+// LDS of the accumulation: two staged rows of lda = rm + 1 doubles per sample
+// (rows 2 banks apart for the four samples a matrix-core step reads) and the
+// slice indices
+size_t acc_lds_bytes(int rm) { return (size_t)2 * kAccSB * (rm + 1) * 8 + kAccSB * 4 + 64; }
+
+// iface block (doubles) and partials (doubles) of the backward
+void bwd_sizes(int d, const int64_t* ranks, int64_t N, int64_t total, int64_t* iface, int64_t* parts) {
+  int64_t per = 0;
+  for (int k = 0; k < d; ++k) per += ranks[k] + ranks[k + 1];
+  *iface = std::min<int64_t>(std::max<int64_t>(N, 1), kBwdBlock) * per;
+  *parts = (int64_t)kSmpGroups * total;
+}
+
+}  // namespace
+
+int sample_rm(int d, const int64_t* ranks) { return smp_rm(d, ranks); }
+
+hipError_t launch_sample2(int d, const int64_t* dims, const int64_t* ranks, const void* const* cores, int f32,
+                          const int64_t* idx, int64_t N, double* out, hipStream_t st) {
+  SmpPlan P;
+  if (!smp_plan(d, dims, ranks, cores, nullptr, f32, kLdsMax, P) || N < 0) return hipErrorInvalidValue;
+  if (N == 0) return hipSuccess;
+  switch (P.rm) {
+    case 8: return run_sample<8, 1024>(P, idx, N, out, st);
+    case 16: return run_sample<16, 1024>(P, idx, N, out, st);
+    default: return run_sample<32, 512>(P, idx, N, out, st);
+  }
+}
+
+size_t sample_bwd2_workspace(int d, const int64_t* dims, const int64_t* ranks, int64_t N) {
+  int64_t total = 0;
+  for (int k = 0; k < d; ++k) total += ranks[k] * dims[k] * ranks[k + 1];
+  int64_t iface, parts;
+  bwd_sizes(d, ranks, N, total, &iface, &parts);
+  return (size_t)(iface + parts) * 8 + 256;
+}
+
+hipError_t launch_sample_bwd2(int d, const int64_t* dims, const int64_t* ranks, const void* const* left,
+                              const void* const* right, int f32, const int64_t* idx, int64_t N, const double* gout,
+                              void* const* gcores, void* work, size_t work_bytes, hipStream_t st) {
+  SmpPlan P;
+  if (!smp_plan(d, dims, ranks, left, right, f32, kLdsMax, P) || N < 0) return hipErrorInvalidValue;
+  if (work_bytes < sample_bwd2_workspace(d, dims, ranks, N)) return hipErrorInvalidValue;
+  int64_t iface, parts;
+  bwd_sizes(d, ranks, N, P.total, &iface, &parts);
+  double* ws = (double*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+  double* partials = ws + iface;
+  GradOut G;
+  G.d = d;
+  G.f32 = f32;
+  for (int k = 0; k < d; ++k) G.cores[k] = gcores[k];
+  for (int k = 0; k <= d; ++k) G.coff[k] = P.coff[k];
+  if (N == 0) {
+    // no samples: every partial is zero
+    TT_LAUNCH(k_fill_zero, dim3((unsigned)((parts + 255) / 256)), dim3(256), 0, st, partials, parts);
+  } else {
+    const int64_t cap = std::min<int64_t>(N, kBwdBlock);
+    IfaceOut O;
+    int64_t off = 0;
+    for (int k = 0; k < d; ++k) {
+      O.lo[k] = off;
+      off += cap * ranks[k];
+      O.ro[k] = off;
+      off += cap * ranks[k + 1];
+    }
+    AccDesc A;
+    A.d = d;
+    A.O = O;
+    for (int k = 0; k < d; ++k) A.dims[k] = dims[k];
+    for (int k = 0; k <= d; ++k) {
+      A.ranks[k] = (int)ranks[k];
+      A.coff[k] = P.coff[k];
+    }
+    const size_t acc_lds = acc_lds_bytes(P.rm);
+    hipError_t e = allow_lds(k_grad_mfma<kAccThreads>, acc_lds);
+    if (e != hipSuccess) return e;
+    constexpr int tiles_per_launch = (kAccThreads / 64) * kAccTilesPerWave;
+    for (int64_t s0 = 0; s0 < N; s0 += cap) {
+      const int64_t nb = std::min(cap, N - s0);
+      switch (P.rm) {
+        case 8: e = run_iface<8, 1024>(P, idx, s0, nb, gout, ws, O, st); break;
+        case 16: e = run_iface<16, 1024>(P, idx, s0, nb, gout, ws, O, st); break;
+        default: e = run_iface<32, 512>(P, idx, s0, nb, gout, ws, O, st); break;
+      }
+      if (e != hipSuccess) return e;
+      for (int k = 0; k < d; ++k) {
+        const int tiles = (int)(dims[k] * ((ranks[k] + 15) / 16) * ((ranks[k + 1] + 15) / 16));
+        for (int tau0 = 0; tau0 < tiles; tau0 += tiles_per_launch) {
+          const int tau1 = std::min(tiles, tau0 + tiles_per_launch);
+          TT_LAUNCH(k_grad_mfma<kAccThreads>, dim3(kSmpGroups), dim3(kAccThreads), acc_lds, st, A, idx, s0, nb, ws,
+                    partials, P.total, s0 == 0 ? 1 : 0, k, tau0, tau1, P.rm + 1);
+          e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+      }
+    }
+  }
+  TT_LAUNCH(k_grad_reduce, dim3((unsigned)((P.total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, partials,
+            kSmpGroups, P.total, G);
   return hipGetLastError();
 }
 

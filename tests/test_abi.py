@@ -128,8 +128,35 @@ def test_reconstruct_and_sample_argument_errors(lib):
     assert lib.tt_reconstruct_workspace(3, T._i64([4, 5, 6]), T._i64([2, 2, 3, 1]), ctypes.byref(n)) == T.TT_EINVAL
     assert lib.tt_reconstruct_workspace(3, T._i64([4, 5, 6]), T._i64([1, 65, 3, 1]), ctypes.byref(n)) == T.TT_EUNSUPPORTED
     cores = (ctypes.c_void_p * 2)(0x1000, 0x1000)
-    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, None, -1, None, None) == T.TT_EINVAL
-    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, None, 5, None, None) == T.TT_EINVAL
+    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, 0, None, -1, None, None) == T.TT_EINVAL
+    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, 0, None, 5, None, None) == T.TT_EINVAL
+    assert lib.tt_sample(2, T._i64([3, 4]), T._i64([1, 2, 1]), cores, 7, None, 0, None, None) == T.TT_EINVAL
+    # FP32 cores need every rank <= 32 (wider trains take the FP64-only kernels)
+    assert lib.tt_sample(2, T._i64([40, 40]), T._i64([1, 40, 1]), cores, 1, None, 0, None, None) == T.TT_EUNSUPPORTED
+    assert lib.tt_sample(2, T._i64([40, 40]), T._i64([1, 40, 1]), cores, 0, None, 0, None, None) == T.TT_OK
+
+
+def test_sample_backward_workspace(lib):
+    """Workspace of the sampled-entry backward: the interface products of at
+    most 2^20 samples (sum_k r_{k-1} + r_k doubles each) plus 256 partial
+    gradients; none for trains with a rank above 32."""
+    n = ctypes.c_size_t(0)
+    dims, ranks = [16, 16, 16, 16, 16, 10], [1, 16, 16, 16, 16, 10, 1]
+    total = sum(ranks[k] * dims[k] * ranks[k + 1] for k in range(6))
+    per = sum(ranks[k] + ranks[k + 1] for k in range(6))
+    assert lib.tt_sample_backward_workspace(6, T._i64(dims), T._i64(ranks), 3145728, ctypes.byref(n)) == 0
+    assert n.value == ((1 << 20) * per + 256 * total) * 8 + 256
+    assert lib.tt_sample_backward_workspace(6, T._i64(dims), T._i64(ranks), 1000, ctypes.byref(n)) == 0
+    assert n.value == (1000 * per + 256 * total) * 8 + 256
+    assert lib.tt_sample_backward_workspace(2, T._i64([40, 40]), T._i64([1, 40, 1]), 10, ctypes.byref(n)) == 0
+    assert n.value == 0
+    assert lib.tt_sample_backward_workspace(2, T._i64([40, 40]), T._i64([1, 4, 1]), -1, ctypes.byref(n)) == T.TT_EINVAL
+    # too small a workspace is refused before any device work
+    cores = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    g = (ctypes.c_void_p * 2)(0x2000, 0x2000)
+    rc = lib.tt_sample_backward(2, T._i64([4, 4]), T._i64([1, 2, 1]), cores, 0, ctypes.c_void_p(0x3000), 10,
+                                ctypes.c_void_p(0x4000), g, ctypes.c_void_p(0x5000), 16, None)
+    assert rc == T.TT_ENOSPC and "workspace" in lib.tt_last_error().decode()
 
 
 def test_binding_rejects_bad_indices_and_gradients():
