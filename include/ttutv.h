@@ -82,7 +82,24 @@ typedef struct {
                                A^T Y, which measure faster at n = 512: the one-pass
                                kernel can hold only 16-row tiles of A on chip, and
                                128-byte column segments stream at about 2 TB/s */
+  int32_t orth;             /* tt_orth: orthonormaliser of the intermediate power
+                               iterates (the last one before the Rayleigh-Ritz step
+                               always takes Householder QR) */
 } tt_opts;
+
+/* TT_ORTH_HOUSEHOLDER: Householder QR (one workgroup, or a tree of block QRs
+ * for iterates taller than one workgroup holds).
+ * TT_ORTH_CHOLQR: shifted CholeskyQR (after Fukaya et al., SIAM J. Sci.
+ * Comput. 2020), three rounds of Gram matrix M^T M (FP64, streaming kernel),
+ * Cholesky factor R of M^T M + s I and its inverse in one wave, M <- M R^{-1},
+ * with s = 11 (n ell + ell (ell + 1)) 2^-53 tr(M^T M): positive definite for
+ * iterates conditioned up to about 2^53 (power iterates of noisy tensors
+ * reach 1e14), each round squaring down the condition number, and finite for
+ * exactly rank-deficient iterates.  The result spans the same space as M and
+ * is orthonormal to about the shift's size; only the basis differs from
+ * Householder's, and the Rayleigh-Ritz step after the last (Householder)
+ * iterate does not depend on it. */
+typedef enum { TT_ORTH_HOUSEHOLDER = 0, TT_ORTH_CHOLQR = 1 } tt_orth;
 
 /* TT_PREC_FP64: every carry, sketch and product in FP64.
  * TT_PREC_MIXED: carries and power iterates stored in FP32 (half the traffic
@@ -136,7 +153,7 @@ const char* tt_kernel_class_name(int c);
 
 /* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
  * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64,
- * fuse_ata = 0. */
+ * fuse_ata = 0, orth = TT_ORTH_HOUSEHOLDER. */
 void tt_default_opts(tt_opts* opts);
 
 /* Device bytes of workspace tt_utv_decompose needs for this problem.

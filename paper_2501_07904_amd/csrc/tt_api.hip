@@ -145,6 +145,8 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
   if (P.o.prec != TT_PREC_FP64 && P.o.prec != TT_PREC_MIXED && P.o.prec != TT_PREC_MIXED_BF16)
     return fail(TT_EINVAL, "bad prec %d", P.o.prec);
   if (P.o.fuse_ata != 0 && P.o.fuse_ata != 1) return fail(TT_EINVAL, "fuse_ata = %d is not 0 or 1", P.o.fuse_ata);
+  if (P.o.orth != TT_ORTH_HOUSEHOLDER && P.o.orth != TT_ORTH_CHOLQR)
+    return fail(TT_EINVAL, "orth = %d is not a tt_orth value", P.o.orth);
   P.mixed = (P.o.prec != TT_PREC_FP64);
   P.bf16 = (P.o.prec == TT_PREC_MIXED_BF16) ? 1 : 0;
   P.sweep = sweep;
@@ -300,8 +302,10 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
     } else {
       z.Y = std::max(z.Y, s.m * (int64_t)c);
       z.X = std::max(z.X, (int64_t)s.n * c);
-      for (int cc = 1; cc <= c; ++cc)   // reused by the orthonormalisation of a tall n x cc iterate
+      for (int cc = 1; cc <= c; ++cc) {   // reused by the orthonormalisation of a tall n x cc iterate
         z.part = std::max(z.part, orth_scratch(s.n, cc));
+        if (P.o.orth == TT_ORTH_CHOLQR && cc <= s.n) z.part = std::max(z.part, orth_cholqr_scratch(s.n, cc));
+      }
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, c) * s.n * c);
       if (P.o.fuse_ata && s.layout == COL && s.n <= 512)   // one-pass power products
         z.part = std::max(z.part, (int64_t)fused_ata_blocks(s.m) * s.n * std::min(c, 32));
@@ -367,6 +371,16 @@ struct StepIO {
   int out_f32;       // carry stored in FP32 (mixed precision, not the last core)
   double* core;      // core buffer of this step
 };
+
+// X = orth(M) for an iterate of the power loop: the option's orthonormaliser
+// for the intermediate ones, Householder QR for the last (which feeds the
+// Rayleigh-Ritz step)
+hipError_t orth_iterate(const Problem& P, bool intermediate, double* M, double* X, int n, int c, const Work& W,
+                        hipStream_t st) {
+  if (intermediate && P.o.orth == TT_ORTH_CHOLQR && c <= n)
+    return launch_orth_cholqr(M, X, n, c, W.part, W.part_len, st);
+  return launch_orth(M, X, n, c, W.part, W.part_len, st);
+}
 
 int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
              StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF, bool retry) {
@@ -457,7 +471,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
           LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
                  launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       }
-      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, orth_iterate(P, it < P.o.q, W.M, W.X, n, c, W, st));
     }
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
     // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank); in the
@@ -489,7 +503,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
                launch_fused_ata((const double*)io.A, W.X, m, n, c, W.part, fb, st));
         LAUNCH(PF, KC_REDUCE, (double)(fb + 1) * n * c * 8, (double)fb * n * c,
                launch_reduce(W.part, fb, (int64_t)n * c, W.M, nullptr, st));
-        LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
+        LAUNCH(PF, KC_SMALL, 0, 0, orth_iterate(P, it + 1 < P.o.q, W.M, W.X, n, c, W, st));
         continue;
       }
       const double sy = P.mixed ? 4.0 : 8.0;
@@ -505,7 +519,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
              launch_atb2(io.A, io.a_f32, W.Y, P.mixed, m, n, c, s.layout, 0, W.part, nch, st));
       LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
              launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
-      LAUNCH(PF, KC_SMALL, 0, 0, launch_orth(W.M, W.X, n, c, W.part, W.part_len, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, orth_iterate(P, it + 1 < P.o.q, W.M, W.X, n, c, W, st));
     }
     LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
            launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,

@@ -122,6 +122,12 @@ hipError_t launch_gen_sketch(double* G, const SolveArgs& a, hipStream_t st);
 // tree of block QRs in `scratch` (orth_scratch(n, c) doubles, may be 0).
 int64_t orth_scratch(int n, int c);
 hipError_t launch_orth(double* M, double* X, int n, int c, double* scratch, int64_t scratch_len, hipStream_t st);
+// X = orth(M) (M n x c column-major, X k-major) by shifted CholeskyQR3: three
+// Gram / shifted Cholesky / triangular-solve rounds,
+// scratch of orth_cholqr_scratch(n, c) doubles; M is not modified.
+int64_t orth_cholqr_scratch(int n, int c);
+hipError_t launch_orth_cholqr(const double* M, double* X, int n, int c, double* scratch, int64_t scratch_len,
+                              hipStream_t st);
 // Rayleigh-Ritz on span(X) (X k-major): K = (A X)^T (A X) (ell x ell) -> rank,
 // V1 = X Z_r, W = Z_r.
 hipError_t launch_rr_solve(const double* K, const double* X, const SolveArgs& a, hipStream_t st);

@@ -1139,3 +1139,168 @@ hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs&
   return hipGetLastError();
 }
 }  // namespace ttutv
+
+namespace ttutv {
+
+// ---- shifted CholeskyQR3 orthonormalisation --------------------------------
+// X = orth(M) for M n x c (column-major), c <= 64, by three shifted
+// Cholesky-QR rounds: Q <- Q R^{-1} with R^T R = Q^T Q + s I, starting from Q
+// = M.  The shift s = 11 (n c + c (c + 1)) u tr(Q^T Q) (tr bounds ||Q||_2^2
+// from above) keeps each factorisation positive definite for condition
+// numbers up to about 1/u, and each round takes the condition number of Q to
+// about its square root (the shifted CholeskyQR of Fukaya, Kannan,
+// Nakatsukasa, Yamamoto and Yanagisawa, SIAM J. Sci. Comput. 2020, whose
+// CholeskyQR3 shifts only the first round).  The later rounds are shifted too
+// so that an exactly rank-deficient iterate (an exact-rank tensor sketched
+// wider than its rank) stays finite: its dead directions, scaled up round by
+// round, end as further orthonormal columns.  The result is orthonormal to
+// about the shift's size rather than to rounding, which suffices for the
+// intermediate power iterates it is used for (the last iterate, which feeds
+// the Rayleigh-Ritz step, takes Householder QR).  The Gram matrices go
+// through the streaming Gram kernel; each factorisation is one wave.
+namespace {
+
+// One wave: K (c x c, column-major) + shift I = R^T R (R upper), then Rinv =
+// R^{-1} (c x c column-major) to global.  Lane l carries column l of the
+// trailing matrix in registers; row j of R is broadcast through LDS.
+template <int CM>
+__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ K, double* __restrict__ Rinv, int c,
+                                                 double shift_factor) {
+  __shared__ double sR[CM][CM + 2];
+  const int l = threadIdx.x;
+  double k[CM];
+#pragma unroll
+  for (int i = 0; i < CM; ++i) k[i] = (i < c && l < c) ? K[i + (int64_t)c * l] : 0.0;
+  if (shift_factor > 0.0) {
+    // trace of K: lane l holds K(l, l) in k[l]; summed in a fixed order through LDS
+    double dl = 0.0;
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if (i == l) dl = k[i];
+    if (l < c) sR[0][l] = dl;
+    __syncthreads();
+    double tr = 0.0;
+    for (int i = 0; i < c; ++i) tr += sR[0][i];
+    __syncthreads();
+    const double s = shift_factor * tr;
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if (i == l && l < c) k[i] += s;
+  }
+  for (int j = 0; j < c; ++j) {
+    // pivot K(j, j), held by lane j
+    double kjl = 0.0;
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if (i == j) kjl = k[i];
+    if (l == j) sR[j][CM + 1] = kjl;
+    __syncthreads();
+    const double dj = sR[j][CM + 1];
+    // a non-positive pivot (only for non-finite or exactly singular input
+    // beyond the shift) is replaced by the smallest normal number
+    const double piv = dj > 0.0 ? sqrt(dj) : 2.2250738585072014e-308;
+    if (l < CM) sR[j][l] = (l >= j && l < c) ? kjl / piv : 0.0;   // R(j, l)
+    __syncthreads();
+    double rj[CM];
+#pragma unroll
+    for (int i = 0; i < CM; ++i) rj[i] = sR[j][i];
+    const double rjl = (l < CM) ? sR[j][l] : 0.0;
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if (i > j) k[i] = fma(-rj[i], rjl, k[i]);
+  }
+  __syncthreads();
+  // Rinv column l by back substitution on R (upper): R x = e_l
+  double x[CM];
+#pragma unroll
+  for (int i = CM - 1; i >= 0; --i) {
+    double v = (i == l) ? 1.0 : 0.0;
+    if (i < c) {
+#pragma unroll
+      for (int p = i + 1; p < CM; ++p)
+        if (p < c) v = fma(-sR[i][p], x[p], v);
+      v /= sR[i][i];
+    } else {
+      v = 0.0;
+    }
+    x[i] = v;
+  }
+  if (l < c) {
+#pragma unroll
+    for (int i = 0; i < CM; ++i)
+      if (i < c) Rinv[i + (int64_t)c * l] = x[i];
+  }
+}
+
+// X = M Rinv row by row (Rinv c x c upper, in LDS): one row per thread.  M and
+// X column-major (COL) or k-major (row-major, ROW).
+template <int CM>
+__global__ __launch_bounds__(256) void k_rows_rinv(const double* __restrict__ M, int m_row_major,
+                                                   const double* __restrict__ Rinv, double* __restrict__ X,
+                                                   int x_row_major, int n, int c) {
+  __shared__ double sI[CM][CM + 1];
+  for (int e = threadIdx.x; e < c * c; e += 256) sI[e % c][e / c] = Rinv[e];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  double m[CM];
+#pragma unroll
+  for (int j = 0; j < CM; ++j) m[j] = (j < c) ? M[m_row_major ? r * c + j : r + (int64_t)n * j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < CM; ++j) {
+    if (j >= c) break;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i <= j; ++i) v = fma(m[i], sI[i][j], v);
+    X[x_row_major ? r * c + j : r + (int64_t)n * j] = v;
+  }
+}
+
+template <int CM>
+hipError_t cholqr_round(const double* src, int src_row_major, double* dst, int dst_row_major, int n, int c,
+                        double shift_factor, double* K, double* Rinv, double* parts, hipStream_t st) {
+  const int kch = atb_chunks(n, c, c);
+  hipError_t e = launch_atb(src, 0, src, 0, n, c, c, src_row_major ? ROW : COL, kch == 1 ? K : parts, kch, st);
+  if (e != hipSuccess) return e;
+  if (kch > 1) {
+    e = launch_reduce(parts, kch, (int64_t)c * c, K, nullptr, st);
+    if (e != hipSuccess) return e;
+  }
+  TT_LAUNCH((k_chol_inv<CM>), dim3(1), dim3(64), 0, st, K, Rinv, c, shift_factor);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  TT_LAUNCH((k_rows_rinv<CM>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, src_row_major, Rinv, dst,
+            dst_row_major, n, c);
+  return hipGetLastError();
+}
+
+template <int CM>
+hipError_t cholqr3(const double* M, double* X, int n, int c, double* scratch, hipStream_t st) {
+  double* Q1 = scratch;
+  double* Q2 = Q1 + (int64_t)n * c;
+  double* K = Q2 + (int64_t)n * c;
+  double* Rinv = K + (int64_t)c * c;
+  double* parts = Rinv + (int64_t)c * c;
+  const double shift = 11.0 * ((double)n * c + (double)c * (c + 1)) * ldexp(1.0, -53);
+  hipError_t e = cholqr_round<CM>(M, 0, Q1, 0, n, c, shift, K, Rinv, parts, st);
+  if (e == hipSuccess) e = cholqr_round<CM>(Q1, 0, Q2, 0, n, c, shift, K, Rinv, parts, st);
+  if (e == hipSuccess) e = cholqr_round<CM>(Q2, 0, X, 1, n, c, shift, K, Rinv, parts, st);
+  return e;
+}
+
+}  // namespace
+
+int64_t orth_cholqr_scratch(int n, int c) {
+  return 2 * (int64_t)n * c + 2 * (int64_t)c * c + (int64_t)atb_chunks(n, c, c) * c * c;
+}
+
+hipError_t launch_orth_cholqr(const double* M, double* X, int n, int c, double* scratch, int64_t scratch_len,
+                              hipStream_t st) {
+  if (n < 1 || c < 1 || c > kCMax || c > n) return hipErrorInvalidValue;
+  if (!scratch || scratch_len < orth_cholqr_scratch(n, c)) return hipErrorInvalidValue;
+  if (c <= 16) return cholqr3<16>(M, X, n, c, scratch, st);
+  if (c <= 32) return cholqr3<32>(M, X, n, c, scratch, st);
+  return cholqr3<64>(M, X, n, c, scratch, st);
+}
+
+}  // namespace ttutv

@@ -229,3 +229,17 @@ def test_noalloc_entry_rejects_on_host(lib):
     rc = lib.tt_utv_decompose_noalloc(fake, 0, 4, T._i64([16] * 4), T._i64([2, 4, 6, 4, 1]), -1.0, 0, 0,
                                       ctypes.byref(o), cores4, ctypes.byref(rep), None)
     assert rc == T.TT_EINVAL
+
+
+def test_orth_option_on_host(lib):
+    """opts.orth: Householder by default, CholeskyQR3 on request (its Gram,
+    factor and inverse take more workspace), other values refused."""
+    o = T.make_opts()[0]
+    assert o.orth == 0
+    base = _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=o)[1]
+    o1 = T.make_opts(orth="cholqr")[0]
+    rc, n1 = _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=o1)
+    assert rc == T.TT_OK and n1 >= base
+    o1.orth = 5
+    assert _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=o1)[0] == T.TT_EINVAL
+    assert "orth" in lib.tt_last_error().decode()
