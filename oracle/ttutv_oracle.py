@@ -3,7 +3,8 @@ for tensor-train decomposition via the UTV framework").
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
 baseline leg of the benchmark, never by the library.  Plain NumPy in float64;
-LAPACK QR and SVD (through numpy.linalg) are used as library steps.  Nothing
+LAPACK QR and SVD (through numpy.linalg, plus one batched QR through torch's
+CPU build for very wide unfoldings) are used as library steps.  Nothing
 here is blocked, fused or reordered beyond what the paper's algorithms state.
 
 Data model (paper Sec. 2.1): a tensor is a flat vector in reverse
@@ -382,26 +383,48 @@ def _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank):
     return cores, rep
 
 
-def _svd(M):
-    """Thin SVD M = U diag(s) Vt by LAPACK.  For a strongly rectangular M it is
-    taken through a QR factorisation first (the R-SVD: M^T = Q R or M = Q R,
-    then the SVD of the small triangle R), which is exact up to rounding and
-    much faster than a direct bidiagonalisation of the long matrix."""
+def _r_factor(T):
+    """An upper-triangular R with T = Q R for a tall T (m x n, m >= n).
+
+    Tree QR: the R of the stacked block triangles [R_1; R_2; ...] of row blocks
+    T_i = Q_i R_i is an R of T (exact up to rounding and the signs of R's rows,
+    which change no singular value or right singular vector).  The block QRs go
+    to LAPACK as one batched call on torch's CPU build, which spreads them over
+    the host threads; a single QR of a 4,096,000 x 160 matrix runs on one core
+    for minutes."""
+    m, n = T.shape
+    if m <= 8 * n:
+        return np.linalg.qr(T, mode="r")
+    import torch                       # CPU LAPACK only; no device is touched
+    b = max(2 * n, (1 << 19) // n)
+    nb = m // b
+    head = np.ascontiguousarray(T[: nb * b]).reshape(nb, b, n)
+    Rs = torch.linalg.qr(torch.from_numpy(head), mode="r")[1].numpy().reshape(nb * n, n)
+    if nb * b < m:
+        Rs = np.vstack([Rs, np.linalg.qr(T[nb * b:], mode="r")])
+    return _r_factor(Rs)
+
+
+def _svd_rows(M):
+    """Singular values s and left singular vectors U (n x min(n, m)) of M (n x m)
+    by LAPACK.  A strongly wide M goes through its R factor first (M^T = Q R,
+    so M = R^T Q^T and the left singular vectors of M are the right singular
+    vectors of the small triangle R: the R-SVD), which is exact up to rounding."""
     n, m = M.shape
     if m >= 4 * n:
-        Q, R = np.linalg.qr(M.T, mode="reduced")          # M = R^T Q^T
-        Ur, s, Vrt = np.linalg.svd(R.T, full_matrices=False)
-        return Ur, s, Vrt @ Q.T
-    if n >= 4 * m:
-        Q, R = np.linalg.qr(M, mode="reduced")            # M = Q R
-        Ur, s, Vrt = np.linalg.svd(R, full_matrices=False)
-        return Q @ Ur, s, Vrt
-    return np.linalg.svd(M, full_matrices=False)
+        _, s, Vt = np.linalg.svd(_r_factor(M.T), full_matrices=False)
+        return Vt.T, s
+    U, s, _ = np.linalg.svd(M, full_matrices=False)
+    return U, s
 
 
 def tt_svd(a, dims, ranks=None, eps=None, sweep="L2R", weights=None, max_rank=None):
     """TT-SVD (Oseledets 2011): the same sweeps with the exact truncated SVD of
-    every unfolding (LAPACK, through _svd); the rank rule is the one after Alg. 2."""
+    every unfolding (LAPACK, through _svd_rows); the rank rule is the one after
+    Alg. 2.  The core takes the r leading singular vectors on the core side of
+    the unfolding and the carry is the unfolding projected onto them, which is
+    the product of the r leading singular values and vectors on the other
+    side."""
     dims = [int(x) for x in dims]
     d = len(dims)
     a = _as_flat(a, dims)
@@ -417,18 +440,16 @@ def tt_svd(a, dims, ranks=None, eps=None, sweep="L2R", weights=None, max_rank=No
         if sweep == "L2R":
             n = r_carry * dims[k - 1]
             Cm = C.reshape(n, C.size // n, order="F")
-            U, s, Vt = _svd(Cm)
-            core_vecs, other = U, Vt.T
+            core_vecs, s = _svd_rows(Cm)
             target = fixed[k] if fixed else None
             ek = None if fixed else eps_k[k - 1]
         else:
             n = dims[k - 1] * r_carry
             Cm = C.reshape(C.size // n, n, order="F")
-            U, s, Vt = _svd(Cm)
-            core_vecs, other = Vt.T, U
+            core_vecs, s = _svd_rows(Cm.T)
             target = fixed[k - 1] if fixed else None
             ek = None if fixed else eps_k[k - 2]
-        normC2 = float(np.sum(Cm * Cm))
+        normC2 = float(C @ C)
         if target is not None:
             r = min(target, len(s))
         else:
@@ -438,16 +459,15 @@ def tt_svd(a, dims, ranks=None, eps=None, sweep="L2R", weights=None, max_rank=No
                 rep["rank_rule_met"] = False
         sg = canonical_signs(core_vecs[:, :r])
         cv = core_vecs[:, :r] * sg[None, :]
-        ov = other[:, :r] * sg[None, :]
         dk = math.sqrt(max(float(np.sum(s[r:] ** 2)), 0.0))
         if sweep == "L2R":
             cores[k - 1] = cv.reshape(r_carry, dims[k - 1], r, order="F")
-            C = (s[:r, None] * ov.T).reshape(-1, order="F")
+            C = (cv.T @ Cm).reshape(-1, order="F")
             rep["ranks"][k] = r
             rep["delta"].append(dk); rep["normC"].append(math.sqrt(normC2)); rep["s"].append(s)
         else:
             cores[k - 1] = cv.T.reshape(r, dims[k - 1], r_carry, order="F")
-            C = (ov * s[None, :r]).reshape(-1, order="F")
+            C = (Cm @ cv).reshape(-1, order="F")
             rep["ranks"][k - 1] = r
             rep["delta"].insert(0, dk); rep["normC"].insert(0, math.sqrt(normC2)); rep["s"].insert(0, s)
         r_carry = r

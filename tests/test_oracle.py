@@ -318,8 +318,6 @@ def test_rank_rule_reads_frobenius_energy():
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("TTUTV_SLOW") != "1",
-                    reason="5.2 GB tensor, ~15 min of LAPACK on 8 cores; set TTUTV_SLOW=1")
 def test_table_beps_ttsvd_ranks():
     """Example 2 (160^4): the TT-SVD ranks printed in Table "Beps"."""
     a = ttgen.sin_norm_tensor(4, 160)

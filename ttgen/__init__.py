@@ -66,16 +66,28 @@ def inverse_sum_tensor(d, n, dtype=np.float32):
 
 
 def sin_norm_tensor(d, n):
-    """B(i_1..i_d) = sin(sqrt(sum_k ((i_k-1)/(n-1))^2)), i_k = 1..n (float64)."""
+    """B(i_1..i_d) = sin(sqrt(sum_k ((i_k-1)/(n-1))^2)), i_k = 1..n (float64).
+
+    The squares are summed in index order k = 1..d; the slabs of the last
+    index are filled on a thread pool (the ufuncs release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
     x2 = (np.arange(n, dtype=np.float64) / (n - 1)) ** 2
-    s = np.zeros((n,) * d)
-    for k in range(d):
-        shape = [1] * d
+    head = np.zeros((n,) * (d - 1), order="F")
+    for k in range(d - 1):
+        shape = [1] * (d - 1)
         shape[k] = n
-        s += x2.reshape(shape)
-    np.sqrt(s, out=s)
-    np.sin(s, out=s)
-    return s.reshape(-1, order="F")
+        head += x2.reshape(shape)
+    out = np.empty((n,) * d, order="F")
+
+    def slab(j):
+        v = out[..., j]
+        np.add(head, x2[j], out=v)
+        np.sqrt(v, out=v)
+        np.sin(v, out=v)
+
+    with ThreadPoolExecutor(max_workers=min(8, n)) as pool:
+        list(pool.map(slab, range(n)))
+    return out.reshape(-1, order="F")
 
 
 def random_indices(dims, count, seed):
