@@ -12,8 +12,8 @@ roofline of the dominant kernel class (its launches timed with HIP events on
 the launch stream during the timed steps), the FP64 oracle timed on the host
 cores on a 40^5 instance of the same recipe (and on one thread on 40^4), the
 mixed-precision form on the same tensor and on the 8^8 function tensor at
-eps = 1e-6, the fixed-rank 32^5 FP64 decomposition, and the train
-contractions.
+eps = 1e-6, the fixed-rank 32^5 FP64 decomposition, the train contractions,
+and Examples 1 and 2 of the paper at 160^4 (SNR, rank and tolerance sweeps).
 """
 import argparse
 import json
@@ -162,6 +162,90 @@ def mixed_vs_fp64(steps):
                    "low-precision product runs, the mixed form differs only in the FP32 storage of the carries, "
                    "and both forms are bound by the same single-workgroup factorisations (ceiling 1.0x)")
     return res
+
+
+# Sec. 4.1: Example 1 sweeps SNR 0..30 dB at TT-ranks (20,20,20) and the ranks (r,r,r), r = 2..20, at
+# 30 dB; Example 2 takes the tolerances of Table "Beps", whose TT-SVD column is quoted here for comparison
+EX1_SNR = (0, 5, 10, 15, 20, 25, 30)
+EX1_RANKS = (2, 4, 6, 8, 10, 12, 14, 16, 18, 20)
+BEPS_TTSVD_RANKS = {1e-2: [2, 2, 2], 1e-3: [3, 3, 3], 1e-4: [5, 5, 5], 1e-5: [7, 7, 6]}
+EXAMPLE_FORMS = (("R2L", "URV"), ("L2R", "ULV"))
+
+
+def paper_examples(T, reps):
+    """Examples 1 and 2 of Sec. 4.1 at the paper's size on the GPU, each
+    decomposition timed over `reps` calls after one untimed call, for TT-URV
+    right to left (Alg. 3) and TT-ULV left to right (Alg. 1/2), q = 1, p = 8.
+    Example 1: 160^4 FP64 (5.2 GB), A = P + beta N with P contracted from
+    Gaussian cores of TT-ranks 20 and N Gaussian, beta set by the SNR
+    10 log10(||P||^2 / ||beta N||^2); SNR sweep at ranks (20,20,20) and rank
+    sweep at 30 dB.  Example 2: the 160^4 FP64 tensor sin(sqrt(sum x_k^2)) at
+    the tolerances of Table "Beps"."""
+    import torch
+
+    import ttgen
+
+    def run(A, dims, kw):
+        dec = T.Decomposer(dims, A.dtype, **kw)
+        dec(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dec(A)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        rep = dec.report()
+        rse = relative_error(T, dec.cores(), A)
+        del dec
+        torch.cuda.empty_cache()
+        gbs = A.numel() * A.element_size() / (ms * 1e-3) / 1e9
+        return {"ms": round(ms, 3), "GB/s": round(gbs, 1), "rse": rse, "ranks": rep["ranks"][1:-1],
+                "err_bound_rel": rep["err_bound"] / rep["norm_A"]}
+
+    dims = [160] * 4
+    out = {"reps": reps}
+    ex1 = {"workload": "160^4 FP64 (5.2 GB): Gaussian-TT cores of ranks 20 plus Gaussian noise at the given SNR "
+                       "(Sec. 4.1, Example 1); fixed TT-ranks, q=1, p=8",
+           "snr_sweep": [], "rank_sweep": []}
+    for snr in EX1_SNR:
+        noise = 10.0 ** (-snr / 20.0)
+        A = ttgen.gaussian_tt_tensor_device(dims, [20] * 3, noise, 1, dtype="float64", device="cuda")
+        row = {"snr_db": snr, "noise_rel_to_signal": noise}
+        for sweep, variant in EXAMPLE_FORMS:
+            row[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[20] * 3, sweep=sweep, variant=variant, q=1,
+                                                          oversample=8, seed=1))
+        log(f"bench: example 1 SNR {snr:2d} dB, ranks 20: " + ", ".join(
+            f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in row.items() if isinstance(v, dict)))
+        ex1["snr_sweep"].append(row)
+        if snr == 30:
+            for r in EX1_RANKS:
+                rrow = {"rank": r}
+                for sweep, variant in EXAMPLE_FORMS:
+                    rrow[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[r] * 3, sweep=sweep, variant=variant,
+                                                                   q=1, oversample=8, seed=1))
+                log(f"bench: example 1 SNR 30 dB, ranks {r:2d}: " + ", ".join(
+                    f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in rrow.items() if isinstance(v, dict)))
+                ex1["rank_sweep"].append(rrow)
+        del A
+        torch.cuda.empty_cache()
+    out["example1"] = ex1
+    ex2 = {"workload": "160^4 FP64 (5.2 GB) sin(sqrt(sum_k ((i_k-1)/159)^2)) (Sec. 4.1, Example 2); prescribed "
+                       "accuracy, q=1, p=8; ttsvd_ranks_paper is the TT-SVD column of Table \"Beps\"",
+           "eps_sweep": []}
+    B = ttgen.sin_norm_tensor_device(4, 160, device="cuda")
+    for eps, svd_ranks in BEPS_TTSVD_RANKS.items():
+        row = {"eps": eps, "ttsvd_ranks_paper": svd_ranks}
+        for sweep, variant in EXAMPLE_FORMS:
+            row[f"{variant}_{sweep}"] = run(B, dims, dict(eps=eps, sweep=sweep, variant=variant, q=1, oversample=8,
+                                                          seed=2))
+        log(f"bench: example 2 eps {eps:g}: TT-SVD (paper) {svd_ranks}, " + ", ".join(
+            f"{k} ranks {v['ranks']} {v['ms']:.2f} ms RSE {v['rse']:.3e}" for k, v in row.items()
+            if isinstance(v, dict)))
+        ex2["eps_sweep"].append(row)
+    del B
+    torch.cuda.empty_cache()
+    out["example2"] = ex2
+    return out
 
 
 def decomposer_kw(W):
@@ -362,6 +446,9 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--no-c2", action="store_true", help="skip the fixed-rank 32^5 FP64 decomposition")
     ap.add_argument("--c2-steps", type=int, default=20)
+    ap.add_argument("--no-examples", action="store_true",
+                    help="skip Examples 1 and 2 of the paper at 160^4 (SNR, rank and tolerance sweeps)")
+    ap.add_argument("--example-reps", type=int, default=3)
     ap.add_argument("--no-contractions", action="store_true",
                     help="skip the timing of reconstruction, sampling and its backward")
     ap.add_argument("--copy-probe", action="store_true",
@@ -471,6 +558,8 @@ def main():
             del A2
         contr = contractions(T, c2_cores)
 
+    examples = None if args.no_examples else paper_examples(T, args.example_reps)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     out = {
@@ -479,7 +568,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "ranks": rep["ranks"], "rse": rse, "err_bound_rel": bound},
         "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed, "c2_order5_32_fp64": c2,
-        "contractions": contr,
+        "contractions": contr, "paper_examples": examples,
     }
     print(json.dumps(out), flush=True)
 

@@ -147,7 +147,10 @@ def check_indices(idx, dims, device=None):
     """Validate sampling indices before they reach a kernel: an (N, d) int64
     tensor with 0 <= idx[:, k] < dims[k] (one min/max reduction per mode; the
     kernels use the indices as addresses), on `device` when given.  Returns
-    the contiguous int64 tensor."""
+    the contiguous int64 tensor.  A tensor that passed is marked with its
+    version counter and the dims, so the reductions are not repeated for the
+    same unchanged indices (a completion loop samples the same mask every
+    step); any in-place change bumps the version and forces a new check."""
     d = len(dims)
     if device is not None and (not idx.is_cuda or idx.device != device):
         raise ValueError(f"idx must be a tensor on {device}, got {idx.device}")
@@ -156,12 +159,16 @@ def check_indices(idx, dims, device=None):
     if idx.dtype.is_floating_point or idx.dtype.is_complex or idx.dtype == torch.bool:
         raise ValueError(f"idx must hold integers, got {idx.dtype}")
     idx = idx.contiguous().to(torch.int64)
+    key = (idx._version, tuple(int(x) for x in dims))
+    if getattr(idx, "_ttutv_checked", None) == key:
+        return idx
     if idx.shape[0] > 0:
         lo = idx.amin(dim=0).tolist()
         hi = idx.amax(dim=0).tolist()
         for k in range(d):
             if lo[k] < 0 or hi[k] >= dims[k]:
                 raise ValueError(f"idx[:, {k}] spans [{lo[k]}, {hi[k]}], outside [0, {dims[k] - 1}]")
+    idx._ttutv_checked = key
     return idx
 
 

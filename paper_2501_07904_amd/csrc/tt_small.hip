@@ -1246,13 +1246,16 @@ __global__ __launch_bounds__(256) void k_rows_rinv(const double* __restrict__ M,
   double m[CM];
 #pragma unroll
   for (int j = 0; j < CM; ++j) m[j] = (j < c) ? M[m_row_major ? r * c + j : r + (int64_t)n * j] : 0.0;
+  // fully unrolled (constant indices keep m in registers); columns past c
+  // are skipped, not broken out of
 #pragma unroll
   for (int j = 0; j < CM; ++j) {
-    if (j >= c) break;
-    double v = 0.0;
+    if (j < c) {
+      double v = 0.0;
 #pragma unroll
-    for (int i = 0; i <= j; ++i) v = fma(m[i], sI[i][j], v);
-    X[x_row_major ? r * c + j : r + (int64_t)n * j] = v;
+      for (int i = 0; i <= j; ++i) v = fma(m[i], sI[i][j], v);
+      X[x_row_major ? r * c + j : r + (int64_t)n * j] = v;
+    }
   }
 }
 

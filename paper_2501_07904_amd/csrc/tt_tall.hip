@@ -60,15 +60,14 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 constexpr int kAxKC = 64;
 constexpr int kAxSplitTiles = 128;   // A*W splits its k range when A has fewer 64-row tiles
 
-// Loads of one kAxKC-column chunk of A for the MFMA operand of this lane:
-// a[ss*8 + s8] = A(row, k0 + 32 ss + 8 g + s8), zero outside the matrix; ssa
-// collects the squares.
-template <typename TA, int LY>
+// Loads of one KC-column chunk of A for the MFMA operand of this lane:
+// a[ss*8 + s8] = A(row, k0 + 32 ss + 8 g + s8), zero outside the matrix.
+template <typename TA, int LY, int KC>
 __device__ __forceinline__ void ax_load_chunk(const TA* __restrict__ A, int64_t m, int n, int64_t row, bool rok,
                                               int k0, int k_end, double* a) {
   const int g = (threadIdx.x & 63) >> 4;
 #pragma unroll
-  for (int ss = 0; ss < kAxKC / 32; ++ss) {
+  for (int ss = 0; ss < KC / 32; ++ss) {
     const int kb = k0 + 32 * ss + 8 * g;
     const TA* p = (LY == ROW) ? A + row * n + kb : A + row + (int64_t)kb * m;
 #pragma unroll
@@ -83,52 +82,55 @@ __device__ __forceinline__ void ax_load_chunk(const TA* __restrict__ A, int64_t 
 // of A into acc; ssa collects the sum of squares of the A entries read.  The
 // chunk loop is software-pipelined: the loads of chunk k+1 of A (registers)
 // and of W (into the other half of the double-buffered sW) are in flight
-// while chunk k runs on the matrix cores; one barrier per chunk.
-template <typename TA, int NT, int LY>
+// while chunk k runs on the matrix cores; one barrier per chunk.  KC = 32
+// for the wider W operands (NT >= 3) and for column-major A (one address per
+// loaded column) keeps the two A buffers, the W staging and the accumulators
+// in registers.
+template <typename TA, int NT, int LY, int KC>
 __device__ __forceinline__ void ax_accumulate(const TA* __restrict__ A, const double* __restrict__ W,
-                                              double (*sW)[kAxKC][NT * 16 + 1], int64_t m, int n, int c,
+                                              double (*sW)[KC][NT * 16 + 1], int64_t m, int n, int c,
                                               int64_t tile, int k_begin, int k_end, d4* acc, double& ssa) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row = tile * 64 + 16 * w + li;
   const bool rok = row < m;
-  constexpr int NA = kAxKC / 4;   // A values per lane per chunk
-  constexpr int NWS = (kAxKC * NT * 16 + kThreads - 1) / kThreads;
+  constexpr int NA = KC / 4;   // A values per lane per chunk
+  constexpr int NWS = (KC * NT * 16 + kThreads - 1) / kThreads;
   if (k_begin >= k_end) return;
   double a[NA], an[NA], wn[NWS];
   auto load_w = [&](int k0, double* dst) {
-    const int kc = min(kAxKC, k_end - k0);
+    const int kc = min(KC, k_end - k0);
 #pragma unroll
     for (int u = 0; u < NWS; ++u) {
       const int e = threadIdx.x + kThreads * u;
       const int kk = e / (NT * 16), cc = e % (NT * 16);
-      dst[u] = (e < kAxKC * NT * 16 && kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
+      dst[u] = (e < KC * NT * 16 && kk < kc && cc < c) ? W[(int64_t)(k0 + kk) * c + cc] : 0.0;
     }
   };
   auto store_w = [&](const double* src, int buf) {
 #pragma unroll
     for (int u = 0; u < NWS; ++u) {
       const int e = threadIdx.x + kThreads * u;
-      if (e < kAxKC * NT * 16) sW[buf][e / (NT * 16)][e % (NT * 16)] = src[u];
+      if (e < KC * NT * 16) sW[buf][e / (NT * 16)][e % (NT * 16)] = src[u];
     }
   };
   __syncthreads();   // sW may still be read by a previous tile
   load_w(k_begin, wn);
-  ax_load_chunk<TA, LY>(A, m, n, row, rok, k_begin, k_end, a);
+  ax_load_chunk<TA, LY, KC>(A, m, n, row, rok, k_begin, k_end, a);
   store_w(wn, 0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = k_begin; k0 < k_end; k0 += kAxKC) {
-    const int k1 = k0 + kAxKC;
+  for (int k0 = k_begin; k0 < k_end; k0 += KC) {
+    const int k1 = k0 + KC;
     const bool more = k1 < k_end;
     if (more) {
       load_w(k1, wn);
-      ax_load_chunk<TA, LY>(A, m, n, row, rok, k1, k_end, an);
+      ax_load_chunk<TA, LY, KC>(A, m, n, row, rok, k1, k_end, an);
     }
 #pragma unroll
     for (int u = 0; u < NA; ++u) ssa = fma(a[u], a[u], ssa);
 #pragma unroll
-    for (int ss = 0; ss < kAxKC / 32; ++ss) {
+    for (int ss = 0; ss < KC / 32; ++ss) {
       const int kb = 32 * ss + 8 * g;
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8)
@@ -150,7 +152,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax(const TA* __restrict__ A, co
                                                  TY* __restrict__ Y, int64_t m, int n, int c,
                                                  double* __restrict__ sumsqA,
                                                  double* __restrict__ sumsqY, double* __restrict__ rerr) {
-  __shared__ double sW[2][kAxKC][NT * 16 + 1];
+  constexpr int KC = (NT >= 3 || LY == COL) ? 32 : kAxKC;
+  __shared__ double sW[2][KC][NT * 16 + 1];
   __shared__ double sh[8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_ax(const TA* __restrict__ A, co
     d4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    ax_accumulate<TA, NT, LY>(A, W, sW, m, n, c, tile, 0, n, acc, ssa);
+    ax_accumulate<TA, NT, LY, KC>(A, W, sW, m, n, c, tile, 0, n, acc, ssa);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -431,10 +434,12 @@ __global__ __launch_bounds__(kThreads) void k_ax_narrow(const TA* __restrict__ A
     for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s4 = 0; s4 < NK; ++s4) {
-      if (4 * s4 >= n) break;   // k-steps past the last column only add zeros
-      ssa = fma(a[s4], a[s4], ssa);
+      if (4 * s4 < n) {   // k-steps past the last column only add zeros (skipped, not broken out of:
+                          // a break keeps the loop rolled and wr, a in scratch memory)
+        ssa = fma(a[s4], a[s4], ssa);
 #pragma unroll
-      for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[s4], wr[s4][q], acc[q]);
+        for (int q = 0; q < NT; ++q) acc[q] = mfma_f64(a[s4], wr[s4][q], acc[q]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < NT; ++q)

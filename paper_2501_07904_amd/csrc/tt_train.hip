@@ -380,7 +380,7 @@ __device__ __forceinline__ void step_right(const SmpTrain& T, const double* sh, 
 
 // copy the cores marked for LDS into their padded layout
 template <int NTH>
-__device__ void stage_cores(const SmpTrain& T, double* sh) {
+__device__ __forceinline__ void stage_cores(const SmpTrain& T, double* sh) {
   for (int k = 0; k < T.d; ++k) {
     for (int side = 0; side < 2; ++side) {
       const int off = side ? T.roff[k] : T.loff[k];
@@ -425,7 +425,8 @@ __global__ __launch_bounds__(NTH) void k_sample_t(SmpTrain T, const int64_t* __r
 // Interface products of samples s0 .. s0+nb-1 (one per thread): for every
 // core k, L_k[s] = gout[s] * G_1[i_1] ... G_{k-1}[i_{k-1}] (r_{k-1} entries,
 // left cores) and R_k[s] = G_{k+1}[i_{k+1}] ... G_d[i_d] (r_k entries, right
-// cores), stored sample-major at ws + lo[k] and ws + ro[k].
+// cores), stored entry-major at ws + lo[k] and ws + ro[k]: entry a of sample
+// q at a * nb + q, so the 64 samples of a wave write 512 contiguous bytes.
 struct IfaceOut {
   int64_t lo[kSmpMaxD], ro[kSmpMaxD];
 };
@@ -446,10 +447,10 @@ __global__ __launch_bounds__(NTH) void k_sample_iface(SmpTrain T, const int64_t*
     for (int a = 0; a < RM; ++a) v[a] = a == 0 ? 1.0 : 0.0;
     for (int k = 0; k < d; ++k) {
       const int ra = T.ranks[k];
-      double* L = ws + O.lo[k] + q * ra;
+      double* L = ws + O.lo[k] + q;
 #pragma unroll
       for (int a = 0; a < RM; ++a)
-        if (a < ra) L[a] = w * v[a];
+        if (a < ra) L[(int64_t)a * nb] = w * v[a];
       if (k + 1 < d) {
         step_left<RM>(T, sh, k, ix[k], v, nv);
 #pragma unroll
@@ -460,10 +461,10 @@ __global__ __launch_bounds__(NTH) void k_sample_iface(SmpTrain T, const int64_t*
     for (int a = 0; a < RM; ++a) v[a] = a == 0 ? 1.0 : 0.0;
     for (int k = d - 1; k >= 0; --k) {
       const int rb = T.ranks[k + 1];
-      double* R = ws + O.ro[k] + q * rb;
+      double* R = ws + O.ro[k] + q;
 #pragma unroll
       for (int b = 0; b < RM; ++b)
-        if (b < rb) R[b] = v[b];
+        if (b < rb) R[(int64_t)b * nb] = v[b];
       if (k > 0) {
         step_right<RM>(T, sh, k, ix[k], v, nv);
 #pragma unroll
@@ -540,12 +541,12 @@ __global__ __launch_bounds__(NTH) void k_grad_mfma(AccDesc A, const int64_t* __r
   int pi = 0;
   auto fetch = [&](int64_t q0) {
 #pragma unroll
-    for (int u = 0; u < NPF; ++u) {
+    for (int u = 0; u < NPF; ++u) {   // entry e / kAccSB of staged sample e % kAccSB
       const int e = t + NTH * u;
-      const int q = e / ra, a = e % ra;
-      pl[u] = (e < kAccSB * ra && q0 + q < q_end) ? L[(q0 + q) * ra + a] : 0.0;
-      const int qb = e / rb, b = e % rb;
-      pr[u] = (e < kAccSB * rb && q0 + qb < q_end) ? Rv[(q0 + qb) * rb + b] : 0.0;
+      const int q = e % kAccSB, a = e / kAccSB;
+      const bool in = q0 + q < q_end;
+      pl[u] = (a < ra && in) ? L[(int64_t)a * nb + q0 + q] : 0.0;
+      pr[u] = (a < rb && in) ? Rv[(int64_t)a * nb + q0 + q] : 0.0;
     }
     pi = (t < kAccSB && q0 + t < q_end) ? (int)idx[(s0 + q0 + t) * d + k] : -1;
   };
@@ -555,8 +556,9 @@ __global__ __launch_bounds__(NTH) void k_grad_mfma(AccDesc A, const int64_t* __r
 #pragma unroll
     for (int u = 0; u < NPF; ++u) {
       const int e = t + NTH * u;
-      if (e < kAccSB * ra) stl[(e / ra) * lda + e % ra] = pl[u];
-      if (e < kAccSB * rb) str[(e / rb) * lda + e % rb] = pr[u];
+      const int q = e % kAccSB, a = e / kAccSB;
+      if (a < ra) stl[q * lda + a] = pl[u];
+      if (a < rb) str[q * lda + a] = pr[u];
     }
     if (t < kAccSB) sti[t] = pi;
     __syncthreads();

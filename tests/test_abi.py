@@ -182,6 +182,19 @@ def test_binding_rejects_bad_indices_and_gradients():
     # a host tensor is refused where a device is required
     with pytest.raises(ValueError, match="tensor on"):
         T.check_indices(good, dims, torch.device("cuda", 0))
+    # a passed check is remembered per version and dims: an in-place change or
+    # other dims are checked again
+    idx = torch.tensor([[0, 0, 0], [2, 3, 4]], dtype=torch.int64)
+    assert T.check_indices(idx, dims) is idx
+    assert T.check_indices(idx, dims) is idx
+    with pytest.raises(ValueError, match="outside"):
+        T.check_indices(idx, [3, 3, 5])
+    idx[1, 2] = 5
+    with pytest.raises(ValueError, match="outside"):
+        T.check_indices(idx, dims)
+    idx[1].fill_(-1)
+    with pytest.raises(ValueError, match="outside"):
+        T.check_indices(idx, dims)
     assert T.check_gout(torch.ones(2), 2).dtype == torch.float64
     with pytest.raises(ValueError, match="elements"):
         T.check_gout(torch.ones(3), 2)

@@ -18,6 +18,7 @@ available):
   gaussian_tt_tensor_device -- the Example 1 recipe built on the GPU with
                          PyTorch (tensors of many GB: 40^6 FP32), split as
                          (left half-train) x (right half-train) + noise.
+  sin_norm_tensor_device -- the Example 2 tensor built on the GPU.
 """
 import numpy as np
 
@@ -156,3 +157,20 @@ def gaussian_tt_tensor_device(dims, ranks, noise_rel, seed, dtype="float32", dev
         P.add_(N, alpha=beta)
         del N
     return P
+
+
+def sin_norm_tensor_device(d, n, device="cuda"):
+    """sin_norm_tensor built with PyTorch on `device` (float64): the squares are
+    summed in index order k = 1..d by broadcasting, then sqrt and sin in place.
+    The device's sqrt and sin may round differently from the host's by an ulp."""
+    import torch
+
+    x2 = (torch.arange(n, dtype=torch.float64, device=device) / (n - 1)) ** 2
+    s = x2
+    for k in range(1, d):
+        # s holds modes 1..k (mode 1 fastest); mode k+1 becomes the new slowest axis
+        s = s.reshape((1,) + tuple(s.shape)) + x2.reshape((n,) + (1,) * s.dim())
+    s = s.reshape(-1)
+    s.sqrt_()
+    s.sin_()
+    return s
