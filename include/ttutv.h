@@ -263,11 +263,12 @@ int tt_sample_backward_workspace(int d, const int64_t* dims, const int64_t* rank
  * gcores[k] (device, same type, layout and size as core k) is overwritten.
  * The interface products of each sample are recomputed from the cores (not
  * kept from a forward call) into `work` (tt_sample_backward_workspace bytes,
- * in blocks of at most 2^20 samples); each of 256 workgroups sums the products
- * of its share of the samples in LDS, every gradient entry owned by one
- * thread that adds in sample order, and the workgroups' partials are summed
- * in a fixed order: the result is bitwise reproducible.  Trains with a rank
- * above 32 use FP64 atomics instead (not reproducible bitwise; work unused).
+ * in blocks of at most 2^20 samples); each of 256 workgroups takes a
+ * contiguous share of the samples, every 16 x 16 tile of a gradient slice is
+ * owned by one wave, which feeds it the samples of that slice in sample order,
+ * four per FP64 matrix-core step, and the workgroups' partials are summed in a
+ * fixed order: the result is bitwise reproducible.  Trains with a rank above
+ * 32 use FP64 atomics instead (not reproducible bitwise; work unused).
  * Enqueues only. */
 int tt_sample_backward(int d, const int64_t* dims, const int64_t* ranks,
                        const void* const* cores, tt_dtype core_dtype, const int64_t* idx, int64_t N,
