@@ -289,6 +289,59 @@ int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks,
 
 const char* tt_last_error(void);
 
+/* ---- Completion steps on TT cores (Sec. 4.3, "MRI data completion") ------
+ * Vectors are device arrays of FP64; `work` is caller-owned device memory of
+ * at least TT_REDUCE_WORK_BYTES bytes (partial sums); every sum is a sum of
+ * per-workgroup partials in a fixed order (bitwise reproducible); each call
+ * only enqueues work on `stream` and results stay on the device.
+ * Errors: TT_EINVAL (N < 0, a NULL pointer where data is needed, a bad train
+ * description), TT_ENOSPC (work smaller than TT_REDUCE_WORK_BYTES),
+ * TT_EUNSUPPORTED (a rank above 64). */
+#define TT_REDUCE_WORK_BYTES 4096
+
+/* z = pred - vals over N sampled entries and f[0] = sum_s z_s^2 / 2: the
+ * residual and objective of the completion problem f = 1/2 ||P_Omega(X - M)||^2.
+ * z may alias pred. */
+int tt_residual(int64_t N, const double* pred, const double* vals, double* z, double* f, void* work,
+                size_t work_bytes, void* stream);
+
+/* out[0] = alpha = <p, z> / <p, p> (0 when p = 0), out[1] = <p, z>,
+ * out[2] = <p, p>: the exact minimiser of 1/2 ||z - alpha p||^2, i.e. of f on
+ * the line X - alpha xi whose sampled direction is p = P_Omega(xi) (the step
+ * size of the Riemannian gradient iteration, and of gradient descent on the
+ * cores with p the sampled directional derivative). */
+int tt_line_step(int64_t N, const double* p, const double* z, double* out, void* work, size_t work_bytes,
+                 void* stream);
+
+/* y += a * s * x over n entries, with s = *a_dev when a_dev is not NULL (a
+ * scalar computed on the device, such as out[0] of tt_line_step) and s = 1
+ * otherwise. */
+int tt_axpy(int64_t n, double a, const double* a_dev, const double* x, double* y, void* stream);
+
+/* Projection onto the tangent space of the manifold of trains of fixed ranks
+ * at X = U_1 ... U_d, where U_1 .. U_{d-1} are left-orthogonal (Def. 2.2), of
+ * the core gradients G_k taken at the mixed-canonical points of X
+ * (tt_sample_backward_mixed with the left- and right-orthogonal forms): on
+ * the left unfoldings ((r_{k-1} I_k) x r_k), dC_k = (I - U_k U_k^T) G_k for
+ * k < d, and dC_d = G_d.  All cores FP64, column-major (r_{k-1}, I_k, r_k),
+ * device; dC[k] may not alias G[k] or U[k].  Ranks <= 64. */
+int tt_tangent_project(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                       const double* const* G, double* const* dC, void* stream);
+
+/* Cores of t xi (with_base = 0) or of X + t xi (with_base = 1), where
+ * xi = sum_k U_1..U_{k-1} dC_k V_{k+1}..V_d is the tangent vector of
+ * tt_tangent_project and V the right-orthogonal form of X: ranks
+ * (1, 2 r_1, ..., 2 r_{d-1}, 1), first core [t dC_1, U_1], interior cores
+ * [[V_k, 0], [t dC_k, U_k]], last core [[V_d], [t dC_d (+ U_d)]] (blocks
+ * stacked along the rank indices).  t = t_host * (*t_dev) when t_dev is not
+ * NULL, else t_host.  W[k] (device, FP64, column-major) holds
+ * w_{k-1} I_k w_k doubles with w = (1, 2 r_1, ..., 2 r_{d-1}, 1).  Ranks <= 64
+ * (the tangent train's, up to 128, are not checked: it is consumed by the
+ * caller). */
+int tt_tangent_train(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                     const double* const* V, const double* const* dC, double t_host, const double* t_dev,
+                     int with_base, double* const* W, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@ TT_OK, TT_EINVAL, TT_ENOSPC, TT_ERANK, TT_ENONFINITE, TT_EHIP, TT_EUNSUPPORTED =
 TT_MAX_D = 32
 TT_MAX_ELL = 64
 TT_NOALLOC_SCRATCH_BYTES = 64 << 20
+TT_REDUCE_WORK_BYTES = 4096
 SWEEPS = {"L2R": 0, "R2L": 1}
 VARIANTS = {"ULV": 0, "URV": 1, "SVD": 2}
 DTYPES = {torch.float64: 0, torch.float32: 1}
@@ -25,7 +26,8 @@ EXPORTS = ["tt_default_opts", "tt_utv_workspace", "tt_utv_core_capacity", "tt_ut
            "tt_utv_decompose_noalloc",
            "tt_reconstruct_workspace", "tt_reconstruct", "tt_reconstruct_backward_workspace",
            "tt_reconstruct_backward", "tt_sample", "tt_sample_backward_workspace", "tt_sample_backward",
-           "tt_sample_backward_mixed",
+           "tt_sample_backward_mixed", "tt_residual", "tt_line_step", "tt_axpy", "tt_tangent_project",
+           "tt_tangent_train",
            "tt_last_error", "tt_kernel_class_name"]
 
 
@@ -101,10 +103,18 @@ def load_library(path=LIB_PATH):
     lib.tt_sample_backward_mixed.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                              ctypes.c_int, vp, ctypes.c_int64, vp, ctypes.POINTER(vp), vp,
                                              ctypes.c_size_t, vp]
+    lib.tt_residual.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.tt_line_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.tt_axpy.argtypes = [ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp]
+    lib.tt_tangent_project.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), vp]
+    lib.tt_tangent_train.argtypes = [ctypes.c_int, i64p, i64p, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), ctypes.c_double, vp, ctypes.c_int, ctypes.POINTER(vp), vp]
     for name in ("tt_utv_workspace", "tt_utv_core_capacity", "tt_utv_decompose", "tt_utv_decompose_noalloc",
                  "tt_reconstruct_workspace",
                  "tt_reconstruct", "tt_reconstruct_backward_workspace", "tt_reconstruct_backward", "tt_sample",
-                 "tt_sample_backward_workspace", "tt_sample_backward", "tt_sample_backward_mixed"):
+                 "tt_sample_backward_workspace", "tt_sample_backward", "tt_sample_backward_mixed", "tt_residual",
+                 "tt_line_step", "tt_axpy", "tt_tangent_project", "tt_tangent_train"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -458,6 +468,109 @@ def tt_sample_backward_mixed(left_cores, right_cores, idx, gout, stream=None):
                                         ctypes.c_void_p(idx.data_ptr()), N, ctypes.c_void_p(gout.data_ptr()),
                                         _ptrs(gflat), ctypes.c_void_p(work.data_ptr()), nbytes, _stream(stream)))
     return [_core_view(gflat[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
+
+
+def _vec64(x, n, device, name):
+    if not x.is_cuda or x.device != device:
+        raise ValueError(f"{name} must be a tensor on {device}, got {x.device}")
+    if x.numel() != n:
+        raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
+    return x.contiguous().reshape(-1).to(torch.float64)
+
+
+def _reduce_work(device):
+    return torch.empty(TT_REDUCE_WORK_BYTES, dtype=torch.uint8, device=device)
+
+
+def tt_residual(pred, vals, stream=None):
+    """(z, f): z = pred - vals (FP64, N) and f = sum z^2 / 2 as a one-element
+    device tensor (Sec. 4.3: the completion objective at the sampled entries)."""
+    lib = load_library()
+    n = pred.numel()
+    dev = pred.device
+    pred = _vec64(pred, n, dev, "pred")
+    vals = _vec64(vals, n, dev, "vals")
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    work = _reduce_work(dev)
+    _check(lib.tt_residual(n, ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                           ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                           ctypes.c_void_p(work.data_ptr()), TT_REDUCE_WORK_BYTES, _stream(stream)))
+    return z, f
+
+
+def tt_line_step(p, z, stream=None):
+    """Device tensor (alpha, <p, z>, <p, p>) with alpha = <p, z> / <p, p> (0 for
+    p = 0): the exact minimiser of 1/2 ||z - alpha p||^2."""
+    lib = load_library()
+    n = z.numel()
+    dev = z.device
+    p = _vec64(p, n, dev, "p")
+    z = _vec64(z, n, dev, "z")
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    work = _reduce_work(dev)
+    _check(lib.tt_line_step(n, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()), TT_REDUCE_WORK_BYTES,
+                            _stream(stream)))
+    return out
+
+
+def tt_axpy(y, x, a=1.0, a_dev=None, stream=None):
+    """y += a * s * x in place (y and x contiguous FP64 device tensors of one
+    size), s = a_dev[0] (a device scalar) when given, else 1.  Returns y."""
+    lib = load_library()
+    if y.dtype != torch.float64 or not y.is_contiguous() or not y.is_cuda:
+        raise ValueError("y must be a contiguous float64 device tensor")
+    x = _vec64(x, y.numel(), y.device, "x")
+    ap = None
+    if a_dev is not None:
+        if not a_dev.is_cuda or a_dev.dtype != torch.float64 or a_dev.numel() < 1:
+            raise ValueError("a_dev must be a float64 device tensor")
+        ap = ctypes.c_void_p(a_dev.data_ptr())
+    _check(lib.tt_axpy(y.numel(), float(a), ap, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                       _stream(stream)))
+    return y
+
+
+def _same_train(a, b, name):
+    if len(a) != len(b) or any(tuple(x.shape) != tuple(y.shape) for x, y in zip(a, b)):
+        raise ValueError(f"{name} must have the shapes of the first train")
+
+
+def tt_tangent_project(U, G, stream=None):
+    """dC_k = (I - U_k U_k^T) G_k on the left unfoldings for k < d, dC_d = G_d
+    (U_1..U_{d-1} left-orthogonal; G the core gradients at the mixed-canonical
+    points).  Returns the list of (r0, I, r1) float64 device cores."""
+    lib = load_library()
+    _same_train(U, G, "G")
+    dims, ranks = _train_shape(U)
+    ub, gb = _core_buffers(U), _core_buffers(G)
+    out = [torch.empty_like(b) for b in ub]
+    _check(lib.tt_tangent_project(len(dims), _i64(dims), _i64(ranks), _ptrs(ub), _ptrs(gb), _ptrs(out),
+                                  _stream(stream)))
+    return [_core_view(out[k], ranks[k], dims[k], ranks[k + 1]) for k in range(len(dims))]
+
+
+def tt_tangent_train(U, V, dC, t=1.0, t_dev=None, base=False, stream=None):
+    """Cores of t*xi (or X + t*xi with base) for the tangent vector
+    xi = sum_k U_<k dC_k V_>k at X = U_1..U_d; t = t * t_dev[0] when t_dev (a
+    device scalar) is given.  Ranks (1, 2 r_1, ..., 2 r_{d-1}, 1)."""
+    lib = load_library()
+    _same_train(U, V, "V")
+    _same_train(U, dC, "dC")
+    dims, ranks = _train_shape(U)
+    d = len(dims)
+    w = [1] + [2 * r for r in ranks[1:-1]] + [1]
+    ub, vb, cb = _core_buffers(U), _core_buffers(V), _core_buffers(dC)
+    out = [torch.empty(w[k] * dims[k] * w[k + 1], dtype=torch.float64, device=U[0].device) for k in range(d)]
+    tp = None
+    if t_dev is not None:
+        if not t_dev.is_cuda or t_dev.dtype != torch.float64 or t_dev.numel() < 1:
+            raise ValueError("t_dev must be a float64 device tensor")
+        tp = ctypes.c_void_p(t_dev.data_ptr())
+    _check(lib.tt_tangent_train(d, _i64(dims), _i64(ranks), _ptrs(ub), _ptrs(vb), _ptrs(cb), float(t), tp,
+                                1 if base else 0, _ptrs(out), _stream(stream)))
+    return [_core_view(out[k], w[k], dims[k], w[k + 1]) for k in range(d)]
 
 
 class TTSample(torch.autograd.Function):

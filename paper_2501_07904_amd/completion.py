@@ -22,10 +22,18 @@ alpha = <e, J g> / ||J g||^2 with J g the sampled directional derivative
 (d more sampling passes, one per core).  The initial cores are the TT-UTV
 decomposition of the zero-filled observed tensor scaled by 1/(observed
 fraction) (a spectral initialisation).
+
+Every arithmetic step of both iterations runs in the library's kernels: the
+residual and f (tt_residual), the step size (tt_line_step), the core update
+and the accumulation of directional derivatives (tt_axpy), the tangent
+projection (tt_tangent_project) and the cores of the tangent vector and of
+the stepped point (tt_tangent_train); f and alpha are read back once per step.
 """
 import torch
 
-from . import tt_reconstruct, tt_sample, tt_sample_backward, tt_sample_backward_mixed, tt_utv_decompose
+from . import (_core_buffers, _core_view, tt_axpy, tt_line_step, tt_reconstruct, tt_residual, tt_sample,
+               tt_sample_backward, tt_sample_backward_mixed, tt_tangent_project, tt_tangent_train,
+               tt_utv_decompose)
 
 
 def flat_index(idx, dims):
@@ -51,16 +59,21 @@ def spectral_init(dims, idx, vals, ranks, q=1, oversample=8, seed=0):
 
 
 def completion_step(cores, idx, vals):
-    """One gradient step; returns (new cores, f before the step, alpha)."""
-    e = tt_sample(cores, idx) - vals.to(torch.float64)
-    f = 0.5 * float(torch.dot(e, e))
-    g = tt_sample_backward(cores, idx, e)
-    jg = torch.zeros_like(e)
-    for k in range(len(cores)):
-        jg += tt_sample(cores[:k] + [g[k]] + cores[k + 1:], idx)
-    den = float(torch.dot(jg, jg))
-    alpha = float(torch.dot(e, jg)) / den if den > 0 else 0.0
-    return [c - alpha * gk for c, gk in zip(cores, g)], f, alpha
+    """One gradient step; returns (new cores, f before the step, alpha).  The
+    residual, the directional derivative's accumulation, the step size and the
+    core update run in the library's kernels; f and alpha are read back once."""
+    z, f = tt_residual(tt_sample(cores, idx), vals)
+    g = tt_sample_backward(cores, idx, z)
+    jg = tt_sample([g[0]] + cores[1:], idx)
+    for k in range(1, len(cores)):
+        tt_axpy(jg, tt_sample(cores[:k] + [g[k]] + cores[k + 1:], idx))
+    st = tt_line_step(jg, z)
+    new = []
+    for c, gk in zip(cores, g):
+        flat = _core_buffers([c])[0].clone()
+        tt_axpy(flat, _core_buffers([gk])[0], a=-1.0, a_dev=st[0:1])
+        new.append(_core_view(flat, *c.shape))
+    return new, float(f[0]), float(st[0])
 
 
 def complete(dims, idx, vals, ranks, steps, cores=None, seed=0):
@@ -73,38 +86,6 @@ def complete(dims, idx, vals, ranks, steps, cores=None, seed=0):
         cores, f, _ = completion_step(cores, idx, vals)
         hist.append(f)
     return cores, hist
-
-
-def _left_unfold(g):
-    """Left unfolding (r0 I) x r1 of a logical (r0, I, r1) core, r0 index fastest."""
-    r0, n, r1 = g.shape
-    return g.permute(1, 0, 2).reshape(n * r0, r1)
-
-
-def _fold_left(m, r0, n, r1):
-    return m.reshape(n, r0, r1).permute(1, 0, 2)
-
-
-def _tangent_train(U, V, dC, t, base):
-    """Cores of t*xi (base False) or X + t*xi (base True), xi = sum_k U_<k dC_k V_>k,
-    X = U_1..U_d: first core [t dC_1, U_1], interior [[V_k, 0], [t dC_k, U_k]],
-    last [[V_d], [t dC_d (+ U_d)]]."""
-    d = len(U)
-    W = []
-    for k in range(d):
-        if k == 0:
-            W.append(torch.cat([t * dC[0], U[0]], dim=2))
-        elif k < d - 1:
-            r0, n, r1 = U[k].shape
-            blk = torch.zeros((2 * r0, n, 2 * r1), dtype=torch.float64, device=U[k].device)
-            blk[:r0, :, :r1] = V[k]
-            blk[r0:, :, :r1] = t * dC[k]
-            blk[r0:, :, r1:] = U[k]
-            W.append(blk)
-        else:
-            last = t * dC[k] + U[k] if base else t * dC[k]
-            W.append(torch.cat([V[k], last], dim=0))
-    return W
 
 
 def rgrad_step(cores, idx, vals, q=1, oversample=8, seed=0, left_orthogonal=False):
@@ -125,20 +106,13 @@ def rgrad_step(cores, idx, vals, q=1, oversample=8, seed=0, left_orthogonal=Fals
     V, _ = tt_utv_decompose(full, dims, ranks=ranks, sweep="R2L", variant="URV", **kw)
     V = [g.clone() for g in V]
     del full
-    z = tt_sample(U, idx) - vals.to(torch.float64)
-    f = 0.5 * float(torch.dot(z, z))
+    z, f = tt_residual(tt_sample(U, idx), vals)
     G = tt_sample_backward_mixed(U, V, idx, z)
-    dC = []
-    for k in range(len(dims) - 1):
-        u, g = _left_unfold(U[k]), _left_unfold(G[k])
-        dC.append(_fold_left(g - u @ (u.T @ g), *U[k].shape))
-    dC.append(G[-1])
-    pxi = tt_sample(_tangent_train(U, V, dC, 1.0, False), idx)
-    den = float(torch.dot(pxi, pxi))
-    alpha = float(torch.dot(pxi, z)) / den if den > 0 else 0.0
-    xhat = tt_reconstruct(_tangent_train(U, V, dC, -alpha, True))
+    dC = tt_tangent_project(U, G)
+    st = tt_line_step(tt_sample(tt_tangent_train(U, V, dC, 1.0), idx), z)
+    xhat = tt_reconstruct(tt_tangent_train(U, V, dC, -1.0, t_dev=st[0:1], base=True))
     new, _ = tt_utv_decompose(xhat, dims, ranks=ranks, sweep="L2R", variant="ULV", **kw)
-    return [g.clone() for g in new], f, alpha
+    return [g.clone() for g in new], float(f[0]), float(st[0])
 
 
 def complete_rgrad(dims, idx, vals, ranks, steps, cores=None, seed=0):

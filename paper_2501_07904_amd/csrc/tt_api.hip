@@ -1167,4 +1167,70 @@ int tt_sample_backward_mixed(int d, const int64_t* dims, const int64_t* ranks, c
                     stream);
 }
 
+// ---- completion steps (Sec. 4.3) -------------------------------------------
+static_assert(TT_REDUCE_WORK_BYTES >= 2 * 256 * sizeof(double), "partials of the reductions");
+
+static int reduce_checks(int64_t N, const void* work, size_t work_bytes) {
+  if (N < 0) return fail(TT_EINVAL, "N < 0");
+  if (!work || work_bytes < TT_REDUCE_WORK_BYTES || work_bytes < reduce_workspace_bytes())
+    return fail(TT_ENOSPC, "work %zu bytes < %d needed", work_bytes, TT_REDUCE_WORK_BYTES);
+  return TT_OK;
+}
+
+int tt_residual(int64_t N, const double* pred, const double* vals, double* z, double* f, void* work,
+                size_t work_bytes, void* stream) {
+  int rc = reduce_checks(N, work, work_bytes);
+  if (rc) return rc;
+  if (!f) return fail(TT_EINVAL, "f is NULL");
+  if (N > 0 && (!pred || !vals || !z)) return fail(TT_EINVAL, "pred/vals/z is NULL");
+  HIP_OK(launch_residual(pred, vals, N, z, f, (double*)work, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_line_step(int64_t N, const double* p, const double* z, double* out, void* work, size_t work_bytes,
+                 void* stream) {
+  int rc = reduce_checks(N, work, work_bytes);
+  if (rc) return rc;
+  if (!out) return fail(TT_EINVAL, "out is NULL");
+  if (N > 0 && (!p || !z)) return fail(TT_EINVAL, "p/z is NULL");
+  HIP_OK(launch_line_step(p, z, N, out, (double*)work, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_axpy(int64_t n, double a, const double* a_dev, const double* x, double* y, void* stream) {
+  if (n < 0) return fail(TT_EINVAL, "n < 0");
+  if (n > 0 && (!x || !y)) return fail(TT_EINVAL, "x/y is NULL");
+  HIP_OK(launch_axpy(n, a, a_dev, x, y, (hipStream_t)stream));
+  return TT_OK;
+}
+
+static int manifold_checks(int d, const int64_t* dims, const int64_t* ranks, const double* const* a,
+                           const double* const* b, const double* const* c, double* const* out) {
+  int rc = train_checks(d, dims, ranks, TT_F64);
+  if (rc) return rc;
+  if (!a || !b || !out) return fail(TT_EINVAL, "a core list is NULL");
+  for (int k = 0; k < d; ++k)
+    if (!a[k] || !b[k] || !out[k] || (c && !c[k])) return fail(TT_EINVAL, "core pointer %d is NULL", k);
+  return TT_OK;
+}
+
+int tt_tangent_project(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                       const double* const* G, double* const* dC, void* stream) {
+  int rc = manifold_checks(d, dims, ranks, U, G, nullptr, dC);
+  if (rc) return rc;
+  HIP_OK(launch_tangent_project(d, dims, ranks, U, G, dC, (hipStream_t)stream));
+  return TT_OK;
+}
+
+int tt_tangent_train(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                     const double* const* V, const double* const* dC, double t_host, const double* t_dev,
+                     int with_base, double* const* W, void* stream) {
+  if (!dC) return fail(TT_EINVAL, "dC is NULL");
+  int rc = manifold_checks(d, dims, ranks, U, V, dC, W);
+  if (rc) return rc;
+  HIP_OK(launch_tangent_train(d, dims, ranks, U, V, dC, t_host, t_dev, with_base ? 1 : 0, W,
+                              (hipStream_t)stream));
+  return TT_OK;
+}
+
 }  // extern "C"

@@ -173,4 +173,17 @@ hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
                              const double* const* cores, const double* const* right_cores, const int64_t* idx,
                              int64_t N, const double* gout, double* const* gcores, hipStream_t st);
 
+// ---- completion steps (tt_manifold.hip) ------------------------------------
+size_t reduce_workspace_bytes();
+hipError_t launch_residual(const double* pred, const double* vals, int64_t n, double* z, double* f, double* work,
+                           hipStream_t st);
+hipError_t launch_line_step(const double* p, const double* z, int64_t n, double* out3, double* work,
+                            hipStream_t st);
+hipError_t launch_axpy(int64_t n, double a, const double* a_dev, const double* x, double* y, hipStream_t st);
+hipError_t launch_tangent_project(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                                  const double* const* G, double* const* dC, hipStream_t st);
+hipError_t launch_tangent_train(int d, const int64_t* dims, const int64_t* ranks, const double* const* U,
+                                const double* const* V, const double* const* dC, double t, const double* t_dev,
+                                int base, double* const* W, hipStream_t st);
+
 }  // namespace ttutv

@@ -612,12 +612,26 @@ struct GradOut {
   int d;
   int f32;
 };
+// A block sums 16 consecutive entries: thread (g, j) adds partials
+// g*per .. g*per+per-1 of entry j in order, then the 16 group sums are added
+// in group order (a fixed order; 16 groups keep enough loads in flight).
+constexpr int kRedEntries = 16, kRedGroups = kThreads / kRedEntries;
 __global__ __launch_bounds__(kThreads) void k_grad_reduce(const double* __restrict__ partials, int nparts,
                                                           int64_t total, GradOut G) {
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= total) return;
+  __shared__ double sh[kRedGroups][kRedEntries];
+  const int j = threadIdx.x % kRedEntries, g = threadIdx.x / kRedEntries;
+  const int64_t e = (int64_t)blockIdx.x * kRedEntries + j;
+  const int per = (nparts + kRedGroups - 1) / kRedGroups;
   double s = 0.0;
-  for (int w = 0; w < nparts; ++w) s += partials[(int64_t)w * total + e];
+  if (e < total) {
+    const int w1 = min(nparts, (g + 1) * per);
+    for (int w = g * per; w < w1; ++w) s += partials[(int64_t)w * total + e];
+  }
+  sh[g][j] = s;
+  __syncthreads();
+  if (g != 0 || e >= total) return;
+  s = sh[0][j];
+  for (int q = 1; q < kRedGroups; ++q) s += sh[q][j];
   int k = 0;
   while (k + 1 < G.d && e >= G.coff[k + 1]) ++k;
   const int64_t o = e - G.coff[k];
@@ -900,8 +914,8 @@ hipError_t launch_sample_bwd2(int d, const int64_t* dims, const int64_t* ranks, 
       }
     }
   }
-  TT_LAUNCH(k_grad_reduce, dim3((unsigned)((P.total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, partials,
-            kSmpGroups, P.total, G);
+  TT_LAUNCH(k_grad_reduce, dim3((unsigned)((P.total + kRedEntries - 1) / kRedEntries)), dim3(kThreads), 0, st,
+            partials, kSmpGroups, P.total, G);
   return hipGetLastError();
 }
 

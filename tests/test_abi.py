@@ -256,3 +256,35 @@ def test_orth_option_on_host(lib):
     o1.orth = 5
     assert _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=o1)[0] == T.TT_EINVAL
     assert "orth" in lib.tt_last_error().decode()
+
+
+def test_completion_step_entry_points_reject_bad_arguments_on_the_host(lib):
+    """tt_residual / tt_line_step / tt_axpy / tt_tangent_project /
+    tt_tangent_train: argument errors are reported before any work is
+    enqueued (the pointers below are never dereferenced)."""
+    fake = ctypes.c_void_p(0x1000)
+    W = T.TT_REDUCE_WORK_BYTES
+    assert lib.tt_residual(-1, fake, fake, fake, fake, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_residual(10, fake, fake, fake, fake, fake, W - 8, None) == T.TT_ENOSPC
+    assert lib.tt_residual(10, fake, fake, fake, fake, None, W, None) == T.TT_ENOSPC
+    assert lib.tt_residual(10, None, fake, fake, fake, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_residual(10, fake, fake, fake, None, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_line_step(-1, fake, fake, fake, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_line_step(10, fake, fake, None, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_line_step(10, fake, None, fake, fake, W, None) == T.TT_EINVAL
+    assert lib.tt_line_step(10, fake, fake, fake, fake, 16, None) == T.TT_ENOSPC
+    assert lib.tt_axpy(-1, 1.0, None, fake, fake, None) == T.TT_EINVAL
+    assert lib.tt_axpy(10, 1.0, None, None, fake, None) == T.TT_EINVAL
+    vp3 = (ctypes.c_void_p * 3)(fake, fake, fake)
+    nul3 = (ctypes.c_void_p * 3)(fake, None, fake)
+    dims = T._i64([4, 5, 6])
+    assert lib.tt_tangent_project(3, dims, T._i64([1, 2, 3, 1]), vp3, vp3, nul3, None) == T.TT_EINVAL
+    assert lib.tt_tangent_project(3, dims, T._i64([2, 2, 3, 1]), vp3, vp3, vp3, None) == T.TT_EINVAL
+    assert lib.tt_tangent_project(3, dims, T._i64([1, 65, 3, 1]), vp3, vp3, vp3, None) == T.TT_EUNSUPPORTED
+    assert lib.tt_tangent_project(1, dims, T._i64([1, 1]), vp3, vp3, vp3, None) == T.TT_EINVAL
+    assert lib.tt_tangent_train(3, dims, T._i64([1, 2, 3, 1]), vp3, vp3, None, 1.0, None, 0, vp3,
+                                None) == T.TT_EINVAL
+    assert lib.tt_tangent_train(3, dims, T._i64([1, 2, 3, 1]), vp3, nul3, vp3, 1.0, None, 0, vp3,
+                                None) == T.TT_EINVAL
+    assert lib.tt_tangent_train(3, dims, T._i64([1, 2, 3, 2]), vp3, vp3, vp3, 1.0, None, 1, vp3,
+                                None) == T.TT_EINVAL
