@@ -85,6 +85,18 @@ typedef struct {
   int32_t orth;             /* tt_orth: orthonormaliser of the intermediate power
                                iterates (the last one before the Rayleigh-Ritz step
                                always takes Householder QR) */
+  int32_t separate_sketch;  /* 0 (default): in the right-to-left sweep, when a step
+                               in Gram mode (n <= 64) is followed by a sketched step,
+                               the carry pass also forms the next step's first
+                               sketch product Y = A_next G (A_next = the carry,
+                               reshaped) from the same reading of the unfolding,
+                               through Y = sum_i A_i (V1 G_i) over the row slabs A_i;
+                               the next step then starts from Y instead of reading
+                               the carry once more (carry rank <= 32, sketch width
+                               <= 48, n <= 48 in the FP64 form / 64 in the mixed
+                               form; otherwise, or with the BF16 or one-pass power
+                               products, the passes stay separate).  1: always a
+                               separate sketch pass. */
 } tt_opts;
 
 /* TT_ORTH_HOUSEHOLDER: Householder QR (one workgroup, or a tree of block QRs
@@ -153,7 +165,7 @@ const char* tt_kernel_class_name(int c);
 
 /* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
  * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64,
- * fuse_ata = 0, orth = TT_ORTH_HOUSEHOLDER. */
+ * fuse_ata = 0, orth = TT_ORTH_HOUSEHOLDER, separate_sketch = 0. */
 void tt_default_opts(tt_opts* opts);
 
 /* Device bytes of workspace tt_utv_decompose needs for this problem.

@@ -41,7 +41,8 @@ class tt_opts(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("max_rank", ctypes.c_int32), ("exact_delta", ctypes.c_int32),
                 ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("fuse_ata", ctypes.c_int32), ("orth", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("fuse_ata", ctypes.c_int32), ("orth", ctypes.c_int32),
+                ("separate_sketch", ctypes.c_int32)]
 
 
 TT_NKCLASS = 8
@@ -205,7 +206,7 @@ ORTHS = {"householder": 0, "cholqr": 1}
 
 
 def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-              prec="fp64", fuse_ata=False, orth="householder"):
+              prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
     o = tt_opts()
     load_library().tt_default_opts(ctypes.byref(o))
     o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
@@ -214,6 +215,7 @@ def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=
     o.prec = PRECS[prec]
     o.fuse_ata = int(bool(fuse_ata))
     o.orth = ORTHS[orth]
+    o.separate_sketch = int(bool(separate_sketch))
     keep = None
     if weights is not None:
         keep = (ctypes.c_double * len(weights))(*[float(w) for w in weights])
@@ -238,7 +240,7 @@ def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dty
 
 
 def _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
-                    fuse_ata, orth="householder"):
+                    fuse_ata, orth="householder", separate_sketch=False):
     if not (A.is_cuda and A.is_contiguous()):
         raise ValueError("A must be a contiguous device tensor")
     if A.dtype not in DTYPES:
@@ -247,7 +249,8 @@ def _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_de
     _check_tensor_size(A, dims)
     if (ranks is None) == (eps is None):
         raise ValueError("give exactly one of ranks and eps")
-    o, keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata, orth)
+    o, keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata, orth,
+                        separate_sketch)
     rk = None if ranks is None else _i64(_full_ranks(ranks, len(dims)))
     epsv = -1.0 if eps is None else float(eps)
     return dims, o, keep, rk, epsv
@@ -285,13 +288,13 @@ def core_buffers_for(dims, ranks=None, eps=None, q=1, oversample=8, max_rank=0, 
 
 def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
                      max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
-                     profile=False, prec="fp64", fuse_ata=False, orth="householder"):
+                     profile=False, prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
     """TT-UTV of the device tensor A (float64/float32, flat in ivec order, i1
     fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
     float64 view of a column-major device buffer."""
     lib = load_library()
     dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
-                                               weights, profile, prec, fuse_ata, orth)
+                                               weights, profile, prec, fuse_ata, orth, separate_sketch)
     d = len(dims)
     nbytes = ctypes.c_size_t(0)
     _check(lib.tt_utv_workspace(d, _i64(dims), rk, epsv, SWEEPS[sweep], VARIANTS[variant], DTYPES[A.dtype],
@@ -313,7 +316,8 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
 
 def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                              oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, stream=None,
-                             allow_rank_miss=False, prec="fp64", fuse_ata=False, orth="householder"):
+                             allow_rank_miss=False, prec="fp64", fuse_ata=False, orth="householder",
+                             separate_sketch=False):
     """tt_utv_decompose on the library's static device scratch (no workspace
     argument): for problems whose workspace fits TT_NOALLOC_SCRATCH_BYTES.
     core_flats: caller-allocated flat float64 device buffers, one per core, at
@@ -321,7 +325,7 @@ def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L
     device memory.  Returns (cores, report) with cores viewing core_flats."""
     lib = load_library()
     dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
-                                               weights, False, prec, fuse_ata, orth)
+                                               weights, False, prec, fuse_ata, orth, separate_sketch)
     d = len(dims)
     if len(core_flats) != d:
         raise ValueError(f"need {d} core buffers, got {len(core_flats)}")
@@ -613,7 +617,7 @@ class Decomposer:
 
     def __init__(self, dims, dtype=torch.float64, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                  oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-                 device="cuda", prec="fp64", fuse_ata=False, orth="householder"):
+                 device="cuda", prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
         lib = load_library()
         self.lib = lib
         self.dims = [int(x) for x in dims]
@@ -623,7 +627,7 @@ class Decomposer:
         self.dtype = dtype
         self.profile = profile
         self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
-                                          fuse_ata, orth)
+                                          fuse_ata, orth, separate_sketch)
         self._dims = _i64(self.dims)
         self._ranks = None if ranks is None else _i64(_full_ranks(ranks, d))
         self.eps = -1.0 if eps is None else float(eps)

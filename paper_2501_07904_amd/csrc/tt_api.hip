@@ -275,6 +275,8 @@ struct Work {
   double* W;
   double* normA2;
   double* cpart;   // a carry's per-workgroup sums of squares, summed by the next step's solve
+  double* fold;    // H_i = V1 G_i of a carry pass that also forms the next sketch
+  int64_t fold_len;
   StepRec* recs;
   size_t bytes;
 };
@@ -284,17 +286,21 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int kCarryParts = 8192;   // bound on the per-workgroup partials of one A*W pass
 
 struct Sizes {
-  int64_t carry, Y, U, X, part, V1;
+  int64_t carry, Y, U, X, part, V1, fold;
 };
 
 // Upper bounds over every step (and every ell a prescribed-accuracy step may grow to).
 Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
-  Sizes z{1, 1, 1, 1, 1, 1};
+  Sizes z{1, 1, 1, 1, 1, 1, 1};
   for (size_t i = 0; i < S.size(); ++i) {
     const Step& s = S[i];
     const int64_t lim = std::min<int64_t>(std::min<int64_t>(s.n, s.m), TT_MAX_ELL);
     const int ellmax = P.fixed ? step_ell(P, s, 0) : (int)lim;
     if (i + 1 < S.size()) z.carry = std::max(z.carry, s.m * (int64_t)s.r);
+    // H_i = V1 G_i for a carry pass that forms the next step's first sketch (right-to-left,
+    // a step with n <= 64 before a sketched one; sketch width <= 48)
+    if (i + 1 < S.size() && P.sweep == TT_R2L && !P.alg4 && !P.o.separate_sketch)
+      z.fold = std::max(z.fold, (int64_t)S[i + 1].n_mode * std::min<int64_t>(s.n, kGramMax) * 48);
     z.V1 = std::max(z.V1, (int64_t)s.n * s.r);
     const int c = std::max(1, std::min(ellmax, (int)kCMax));
     if (step_gram(P, s)) {
@@ -347,6 +353,8 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.W = (double*)take((size_t)kCMax * kCMax * 8);
   W.normA2 = (double*)take(64);
   W.cpart = (double*)take((size_t)kCarryParts * 8);
+  W.fold = (double*)take(z.fold * 8);
+  W.fold_len = z.fold;
   W.recs = (StepRec*)take(sizeof(StepRec) * (size_t)d);
   W.bytes = off;
   return off;
@@ -382,8 +390,8 @@ hipError_t orth_iterate(const Problem& P, bool intermediate, double* M, double* 
   return launch_orth(M, X, n, c, W.part, W.part_len, st);
 }
 
-int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
-             StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF, bool retry) {
+// The fields of a step's solve arguments that define its test matrix.
+SolveArgs sketch_args(const Problem& P, const Step& s, int ell) {
   SolveArgs a{};
   a.n = s.n;
   a.ell = ell;
@@ -393,6 +401,16 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   a.n_mode = s.n_mode;
   a.n_rank = s.n_rank;
   a.mode_fastest = s.mode_fastest;
+  return a;
+}
+
+// sketch_ready: the previous carry pass already wrote this step's test matrix
+// to W.X and the first product A X to W.Y (used unless this is a retry with a
+// wider sketch)
+int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
+             StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF, bool retry,
+             bool sketch_ready = false) {
+  SolveArgs a = sketch_args(P, s, ell);
   a.r_fixed = P.fixed ? s.r : 0;
   const double wk = P.fixed ? 0.0 : P.w[s.unfolding - 1];
   a.eps_factor2 = wk * P.eps_rule * wk * P.eps_rule;
@@ -433,13 +451,15 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     const int c = ell;
     const int ach = ax_chunks(m, n, c);
     const double mc = (double)m * c;
-    LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
+    const bool have_y = sketch_ready && !retry;
+    if (!have_y) LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
     for (int it = 0; it <= P.o.q; ++it) {
       if (P.mixed) {
         // mixed precision: power products on FP32 (or BF16) operands with FP32
         // accumulation, FP32 iterate
-        LAUNCH(PF, KC_AX, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
-               launch_ax_lp(io.A, io.a_f32, W.X, (float*)W.Y, m, n, c, s.layout, P.bf16, st));
+        if (!(have_y && it == 0))
+          LAUNCH(PF, KC_AX, mn * sa + mc * 4 + (double)n * c * 8, 2.0 * mn * c,
+                 launch_ax_lp(io.A, io.a_f32, W.X, (float*)W.Y, m, n, c, s.layout, P.bf16, st));
         const int nch = atb_lp_chunks(m, n);
         double* dst = nch == 1 ? W.M : W.part;   // a single chunk is the sum itself
         if (P.bf16)
@@ -458,9 +478,10 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
         LAUNCH(PF, KC_REDUCE, (double)(fb + 1) * n * c * 8, (double)fb * n * c,
                launch_reduce(W.part, fb, (int64_t)n * c, W.M, nullptr, st));
       } else {
-        LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
-               launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
-                         (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
+        if (!(have_y && it == 0))
+          LAUNCH(PF, KC_AX, mn * sa + mc * 8 + (double)n * c * 8, 2.0 * mn * c,
+                 launch_ax(io.A, io.a_f32, W.X, W.Y, 0, m, n, c, s.layout, ach,
+                           (first && it == 0) ? W.part : nullptr, nullptr, nullptr, st));
         if (first && it == 0)
           LAUNCH(PF, KC_REDUCE, (double)ach * 8, ach, launch_reduce(W.part, ach, 1, W.normA2, nullptr, st));
         // a single chunk is the sum itself: written straight to M, no reduction
@@ -557,10 +578,22 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
 
 // defer_norm: leave ||carry||^2 as per-workgroup partials in W.cpart for the
 // next step's solve to reduce (*parts_out = their count, else 0).
+// The next step's first sketch product formed in this step's carry pass (see
+// tt_carry_sketch.hip): its slab height m2, slab count I (= the next mode's
+// extent), sketch width c and element size of Y.
+struct NextSketch {
+  bool on = false;
+  int64_t m2 = 0;
+  int I = 0, c = 0;
+  double sy = 8.0;
+};
+
 int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io, const Work& W,
-               StepRec* rec, hipStream_t st, Prof& PF, bool defer_norm, int* parts_out) {
+               StepRec* rec, hipStream_t st, Prof& PF, bool defer_norm, int* parts_out,
+               const NextSketch& nx = NextSketch()) {
   const int64_t m = s.m;
-  const int ach = step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r);
+  const int ach = nx.on ? carry_sketch_groups(nx.m2, io.a_f32, io.out_f32)
+                        : (step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r));
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double so = io.out_f32 ? 4.0 : 8.0;
   const double mr = (double)m * r;
@@ -568,7 +601,13 @@ int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io
   const bool defer = defer_norm && ach <= kCarryParts;
   double* nparts = defer ? W.cpart : W.part;
   *parts_out = defer ? ach : 0;
-  if (step_gram(P, s)) {
+  if (nx.on) {
+    const double mn = (double)m * s.n;
+    LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)nx.m2 * nx.c * nx.sy + (double)nx.I * s.n * nx.c * 8,
+           2.0 * mn * r + 2.0 * mn * nx.c,
+           launch_carry_sketch(io.A, io.a_f32, nx.m2, nx.I, s.n, W.V1, r, W.fold, nx.c, io.out, io.out_f32, W.Y,
+                               nparts, rerr, ach, st));
+  } else if (step_gram(P, s)) {
     const double mn = (double)m * s.n;
     LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)s.n * r * 8, 2.0 * mn * r,
            launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, nparts, rerr, st));
@@ -670,6 +709,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   int a_f32 = (dtype == TT_F32);
   int prev_r = 0;
   int prev_parts = 0;   // partials of the previous carry's ||.||^2 left for this step's solve
+  bool sketch_ready = false;   // the previous carry pass formed this step's first sketch product
   bool all_sat = true;
   std::vector<StepRec> host(nsteps);
   for (int si = 0; si < nsteps; ++si) {
@@ -692,7 +732,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     int r;
     bool retry = false;
     while (true) {
-      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, prev_parts, W, st, PF, retry);
+      rc = run_step(P, s, ell, si, first, io, si > 0 ? W.recs + (si - 1) : nullptr, prev_parts, W, st, PF, retry,
+                    sketch_ready);
       if (rc) return rc;
       // ||A||^2 is known after the first pass over A: a non-finite input stops
       // the sweep here instead of running every step on NaNs
@@ -725,9 +766,38 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       }
       ell = std::min(2 * ell, lim);
     }
+    // Right to left, a Gram-mode step before a sketched one: the carry pass also
+    // forms the next step's first sketch product (its test matrix is drawn now,
+    // with the width the next step will start from)
+    NextSketch nx;
+    if (!last && P.sweep == TT_R2L && !P.alg4 && !P.o.separate_sketch && !P.bf16 && step_gram(P, s)) {
+      int64_t r_next[TT_MAX_D + 1];
+      for (int k = 0; k <= d; ++k) r_next[k] = r_run[k];
+      r_next[s.core - 1] = r;
+      std::vector<Step> S3;
+      plan_steps(P, r_next, S3, nullptr);
+      const Step& s2 = S3[si + 1];
+      int ell2 = step_ell(P, s2, r + P.o.oversample);
+      ell2 = std::max(1, std::min(ell2, TT_MAX_ELL));
+      const int I = s2.n_mode;
+      const bool ata = P.o.fuse_ata && fused_ata_ok(io.out_f32, s2.m, s2.n, ell2, s2.layout);
+      if (!step_gram(P, s2) && !ata && s2.m * I == s.m && (int64_t)s2.n == (int64_t)I * r &&
+          W.fold_len >= (int64_t)I * s.n * ell2 &&
+          carry_sketch_ok(io.A, io.a_f32, io.out, io.out_f32, W.Y, s2.m, I, s.n, r, ell2)) {
+        const SolveArgs a2 = sketch_args(P, s2, ell2);
+        LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a2, st));
+        LAUNCH(PF, KC_SMALL, 0, 0, launch_sketch_fold(W.V1, W.X, W.fold, I, s.n, r, ell2, st));
+        nx.on = true;
+        nx.m2 = s2.m;
+        nx.I = I;
+        nx.c = ell2;
+        nx.sy = io.out_f32 ? 4.0 : 8.0;
+      }
+    }
     // the last carry's norm is reduced at once (no later solve reads it)
-    rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF, !last, &prev_parts);
+    rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF, !last, &prev_parts, nx);
     if (rc) return rc;
+    sketch_ready = nx.on;
     ells[si] = ell;
     rs[si] = r;
     // rank of the bond this step decided

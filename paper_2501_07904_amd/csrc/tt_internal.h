@@ -173,6 +173,21 @@ hipError_t launch_sample_bwd(int d, const int64_t* dims, const int64_t* ranks,
                              const double* const* cores, const double* const* right_cores, const int64_t* idx,
                              int64_t N, const double* gout, double* const* gcores, hipStream_t st);
 
+// ---- carry pass that also forms the next step's first sketch (tt_carry_sketch.hip)
+// H (I x n1 x c) = V1 G_i for every slab i; V1 (n1 x r) and G (I r x c) k-major.
+hipError_t launch_sketch_fold(const double* V1, const double* G, double* H, int I, int n1, int r, int c,
+                              hipStream_t st);
+// Workgroups of the fused pass (<= 2048; one per-workgroup partial each).
+int carry_sketch_groups(int64_t m2, int a_f32, int c_f32);
+// Shapes and alignments the fused pass handles (column-major A of m2 I rows and n1
+// columns, carry C of r columns, Y of m2 x c; FP64 carry and Y, or FP32 both).
+bool carry_sketch_ok(const void* A, int a_f32, const void* C, int c_f32, const void* Y, int64_t m2, int I, int n1,
+                     int r, int c);
+// C = A V1 and Y = sum_i A_i H_i; sumsqC[b] (and rerr[b] for an FP32 carry) per workgroup.
+hipError_t launch_carry_sketch(const void* A, int a_f32, int64_t m2, int I, int n1, const double* V1, int r,
+                               const double* H, int c, void* C, int c_f32, void* Y, double* sumsqC, double* rerr,
+                               int groups, hipStream_t st);
+
 // ---- completion steps (tt_manifold.hip) ------------------------------------
 size_t reduce_workspace_bytes();
 hipError_t launch_residual(const double* pred, const double* vals, int64_t n, double* z, double* f, double* work,
