@@ -36,6 +36,10 @@ from . import (_core_buffers, _core_view, tt_axpy, tt_line_step, tt_reconstruct,
                tt_utv_decompose)
 
 
+# largest rank the sampling and reconstruction kernels take (TT_MAX_ELL)
+TANGENT_TRAIN_MAX_RANK = 64
+
+
 def flat_index(idx, dims):
     """Flat (i_1 fastest) position of every row of idx (N x d)."""
     stride, flat = 1, torch.zeros(idx.shape[0], dtype=torch.int64, device=idx.device)
@@ -109,8 +113,21 @@ def rgrad_step(cores, idx, vals, q=1, oversample=8, seed=0, left_orthogonal=Fals
     z, f = tt_residual(tt_sample(U, idx), vals)
     G = tt_sample_backward_mixed(U, V, idx, z)
     dC = tt_tangent_project(U, G)
-    st = tt_line_step(tt_sample(tt_tangent_train(U, V, dC, 1.0), idx), z)
-    xhat = tt_reconstruct(tt_tangent_train(U, V, dC, -1.0, t_dev=st[0:1], base=True))
+    if 2 * max(ranks) <= TANGENT_TRAIN_MAX_RANK:
+        # the tangent vector and the stepped point as trains of ranks 2 r_k
+        st = tt_line_step(tt_sample(tt_tangent_train(U, V, dC, 1.0), idx), z)
+        xhat = tt_reconstruct(tt_tangent_train(U, V, dC, -1.0, t_dev=st[0:1], base=True))
+    else:
+        # ranks above half the sampling kernels' limit: xi term by term, each term
+        # U_<k dC_k V_>k a train of the point's own ranks
+        terms = [U[:k] + [dC[k]] + V[k + 1:] for k in range(len(dims))]
+        pxi = tt_sample(terms[0], idx)
+        for tk in terms[1:]:
+            tt_axpy(pxi, tt_sample(tk, idx))
+        st = tt_line_step(pxi, z)
+        xhat = tt_reconstruct(U)
+        for tk in terms:
+            tt_axpy(xhat, tt_reconstruct(tk), a=-1.0, a_dev=st[0:1])
     new, _ = tt_utv_decompose(xhat, dims, ranks=ranks, sweep="L2R", variant="ULV", **kw)
     return [g.clone() for g in new], float(f[0]), float(st[0])
 
