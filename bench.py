@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of a kernel class, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over each
 # workload scaled by the copy-probe factors (profiles/); empty whenever the class's kernels changed
 # after the counters were taken
-MEASURED_TRAFFIC = {"order6_40_fp32_eps": {"tall_atb": 8851.09e6},
+MEASURED_TRAFFIC = {"order6_40_fp32_eps": {"tall_ax": 5208.95e6, "tall_atb": 8838.73e6},
                     "order5_32_fp64": {"tall_ax": 49.03e6, "tall_atb": 75.59e6}}
 FP64_PEAK_TFLOPS = 78.6
 
