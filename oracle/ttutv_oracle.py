@@ -20,6 +20,19 @@ re-orthonormalisation after every product, then a triangular factorisation of
 the projected matrix and an SVD of its ell x ell triangle to rank-reveal it
 (the SVD is the UTV whose middle factor is diagonal, Sec. 2.2).
 
+Deflation inner kernel (inner="deflation").  The paper's fastest variant,
+TT-ULV with USV-plus (Sec. 3.3, Sec. 4), estimates singular vectors of the
+unfolding one at a time by power iteration and stops once the latest estimate
+is small enough.  The reading here: on the tall orientation A (m x n) of the
+unfolding, vector j starts from column j of the same Gaussian test matrix
+with the vectors already found projected out, takes q power steps
+x <- P(A^T A x) / ||P(A^T A x)|| (P: projection onto the complement of the
+earlier vectors, two Gram-Schmidt rounds), and its energy ||A v_j||^2 joins
+the kept energy; the search stops at the fixed rank, or at the first j where
+||C||^2 minus the kept energy is within eps_k^2 (the rank rule after
+Alg. 2).  The vectors are orthonormal, so the step error is exactly
+sqrt(||C||^2 - ||A V||^2), as for the sketched factorisation.
+
 Function -> passage -> pin (see tests/test_oracle.py):
   splitmix64         SplitMix64 (Steele, Lea & Flood 2014)   published outputs
   sketch_gaussian    counter-based Gaussian test matrix         moments, KS test
@@ -27,6 +40,9 @@ Function -> passage -> pin (see tests/test_oracle.py):
   tt_utv URV  R2L    Alg. 3 (+ its prescribed-accuracy form)    same
   tt_utv URV  L2R    index-reversal remark after Thm. 3.2       equals the reversed R2L sweep
   tt_utv ULV  R2L    Alg. 4 (appendix)                          Prop. A.1 sum bound
+  tt_utv inner="deflation"  the USV-plus inner kernel of Sec. 3.3 / Sec. 4 (one vector at a time)
+                                                                 exact-rank recon, converged = SVD, Pythagoras,
+                                                                 converged eps ranks = TT-SVD ranks
   tt_svd             TT-SVD (Oseledets 2011)                     Table "Beps" ranks, Eckart-Young
   tt_reconstruct     Eq. (TT)                                    closed-form rank-2 TT of a sum
   tt_sample          Eq. (TT) at given multi-indices             equals reconstruct at those entries
@@ -236,7 +252,7 @@ def _truncate(U, T, V, r):
 
 
 def tt_utv(a, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, p=8,
-           seed=0, weights=None, max_rank=None, _labels=None):
+           seed=0, weights=None, max_rank=None, inner="sketch", _labels=None):
     """TT-UTV of the tensor `a` (flat, i1 fastest) with dims I_1..I_d.
 
     sweep/variant: ("L2R","ULV") Alg. 1/2; ("R2L","URV") Alg. 3 and its
@@ -244,6 +260,9 @@ def tt_utv(a, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, p=8,
     reversal + Alg. 3; variant "SVD" is TT-SVD in the given direction.
     Fixed ranks: `ranks` = r_0..r_d (or r_1..r_{d-1}); prescribed accuracy:
     `eps` (relative), eps_k = w_k eps ||A||_F.
+    inner: "sketch" (the randomized power-iteration factorisation) or
+    "deflation" (one vector at a time, the USV-plus reading; ULV/URV sweeps
+    that keep the core side orthonormal, not Alg. 4).
     Returns (cores, report).  cores[k-1] has shape (r_{k-1}, I_k, r_k).
     """
     dims = [int(x) for x in dims]
@@ -253,8 +272,12 @@ def tt_utv(a, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, p=8,
     a = _as_flat(a, dims)
     if variant == "SVD":
         return tt_svd(a, dims, ranks=ranks, eps=eps, sweep=sweep, weights=weights, max_rank=max_rank)
+    if inner not in ("sketch", "deflation"):
+        raise ValueError("unknown inner factorisation")
+    if inner == "deflation" and sweep == "R2L" and variant == "ULV":
+        raise ValueError("the deflation inner kernel keeps the core side orthonormal; Alg. 4 does not")
     if sweep == "L2R" and variant == "URV":
-        return _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank)
+        return _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank, inner)
     labels = list(range(1, d + 1)) if _labels is None else list(_labels)
     normA = math.sqrt(float(a @ a))
     sum_bound = (sweep == "R2L" and variant == "ULV")
@@ -271,13 +294,20 @@ def tt_utv(a, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, p=8,
             n = r_prev * dims[k - 1]
             m = C.size // n
             Cm = C.reshape(n, m, order="F")      # reshape to [r_{k-1} I_k, rest]
-            U1, s_r, V1, s_all, ell, dk, nC = _step(
-                Cm, "ulv_wide", fixed[k] if fixed else None, eps_k[k - 1] if fixed is None else None,
-                q, p, seed, labels[k - 1], dims[k - 1], r_prev, False, k == 1,
-                rep["ranks"][k - 1] if k > 1 else None, max_rank, rep)
+            if inner == "deflation":
+                U1, carry_t, s_all, dk, nC = _deflation_step(
+                    Cm.T, q, seed, labels[k - 1], dims[k - 1], r_prev, False,
+                    fixed[k] if fixed else None, eps_k[k - 1] if fixed is None else None, max_rank, rep)
+                ell = U1.shape[1]
+                C = carry_t.T.reshape(-1, order="F")                             # C = U1^T C_k = L11 V1^T
+            else:
+                U1, s_r, V1, s_all, ell, dk, nC = _step(
+                    Cm, "ulv_wide", fixed[k] if fixed else None, eps_k[k - 1] if fixed is None else None,
+                    q, p, seed, labels[k - 1], dims[k - 1], r_prev, False, k == 1,
+                    rep["ranks"][k - 1] if k > 1 else None, max_rank, rep)
+                C = (s_r[:, None] * V1.T).reshape(-1, order="F")                 # C = L11 V1^T
             r = U1.shape[1]
             cores[k - 1] = U1.reshape(r_prev, dims[k - 1], r, order="F")   # core from U1
-            C = (s_r[:, None] * V1.T).reshape(-1, order="F")                 # C = L11 V1^T
             rep["ranks"][k] = r
             rep["delta"].append(dk); rep["normC"].append(nC); rep["ell"].append(ell); rep["s"].append(s_all)
             r_prev = r
@@ -291,13 +321,20 @@ def tt_utv(a, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, p=8,
             n = dims[k - 1] * r_next
             m = C.size // n
             Cm = C.reshape(m, n, order="F")      # reshape to [I_1..I_{k-1}, I_k r_k]
-            U1, s_r, V1, s_all, ell, dk, nC = _step(
-                Cm, kind, fixed[k - 1] if fixed else None, eps_k[k - 2] if fixed is None else None,
-                q, p, seed, labels[k - 1], dims[k - 1], r_next, True, k == d,
-                rep["ranks"][k] if k < d else None, max_rank, rep)
+            if inner == "deflation":
+                V1, carry, s_all, dk, nC = _deflation_step(
+                    Cm, q, seed, labels[k - 1], dims[k - 1], r_next, True,
+                    fixed[k - 1] if fixed else None, eps_k[k - 2] if fixed is None else None, max_rank, rep)
+                ell = V1.shape[1]
+                C = carry.reshape(-1, order="F")                                  # C = C_k V1 = U1 R11
+            else:
+                U1, s_r, V1, s_all, ell, dk, nC = _step(
+                    Cm, kind, fixed[k - 1] if fixed else None, eps_k[k - 2] if fixed is None else None,
+                    q, p, seed, labels[k - 1], dims[k - 1], r_next, True, k == d,
+                    rep["ranks"][k] if k < d else None, max_rank, rep)
+                C = (U1 * s_r[None, :]).reshape(-1, order="F")                    # C = U1 R11 (Alg. 4: U^ L11)
             r = V1.shape[1]
             cores[k - 1] = V1.T.reshape(r, dims[k - 1], r_next, order="F")  # core from V1^T
-            C = (U1 * s_r[None, :]).reshape(-1, order="F")                    # C = U1 R11 (Alg. 4: U^ L11)
             rep["ranks"][k - 1] = r
             rep["delta"].insert(0, dk); rep["normC"].insert(0, nC); rep["ell"].insert(0, ell); rep["s"].insert(0, s_all)
             r_next = r
@@ -356,12 +393,80 @@ def _step(Cm, kind, r_fixed, eps_k, q, p, seed, label, n_mode, n_rank, mode_fast
     return U1, s_r, V1, s_all, ell, dk, math.sqrt(normC2)
 
 
+def _project_out(V, x):
+    """x less its components along the orthonormal columns of V: two rounds of
+    classical Gram-Schmidt (the second removes what rounding left after the
+    first)."""
+    for _ in range(2):
+        x = x - V @ (V.T @ x)
+    return x
+
+
+def _deflation_basis(A, G, q, r_want, eps_k):
+    """Core-side basis of the tall A (m x n), one vector at a time.
+
+    Vector j starts from column j of G with the vectors found so far projected
+    out, takes q power steps x <- P(A^T (A x)) normalised (a step whose product
+    vanishes keeps x), and adds its energy ||A v_j||^2 to the kept energy.
+    Stops after r_want vectors (fixed rank), or at the first j with
+    ||A||^2 - kept <= eps_k^2, or when G's columns run out.
+    Returns V (n x r, orthonormal columns), the energies, whether the rule was
+    met, and ||A||_F^2."""
+    n = A.shape[1]
+    normC2 = float(np.sum(A * A))
+    V = np.zeros((n, 0))
+    e = []
+    kept = 0.0
+    sat = r_want is not None
+    for j in range(G.shape[1]):
+        x = _project_out(V, G[:, j])
+        x = x / np.linalg.norm(x)
+        for _ in range(q):
+            z = _project_out(V, A.T @ (A @ x))
+            nz = np.linalg.norm(z)
+            if nz > 0.0:
+                x = z / nz
+        V = np.column_stack([V, x])
+        y = A @ x
+        e.append(float(y @ y))
+        kept += e[-1]
+        if r_want is not None:
+            if V.shape[1] == r_want:
+                break
+        elif normC2 - kept <= eps_k * eps_k:
+            sat = True
+            break
+    return V, np.array(e), sat, normC2
+
+
+def _deflation_step(A, q, seed, label, n_mode, n_rank, mode_fastest, r_fixed, eps_k, max_rank, rep):
+    """One step with the deflation inner kernel on the tall A (m x n): the basis
+    V1 (n x r, signs canonical), the carry A V1 (m x r), the estimated singular
+    values sqrt(energy), the step error ||A - A V1 V1^T||_F (measured directly)
+    and ||A||_F."""
+    m, n = A.shape
+    if r_fixed is not None:
+        r_want = min(r_fixed, n, m)
+        cap = r_want
+    else:
+        r_want = None
+        cap = min(n, m) if max_rank is None else min(n, m, max_rank)
+    G = sketch_gaussian(seed, label, n_mode, n_rank, cap, mode_fastest)
+    V, e, sat, normC2 = _deflation_basis(A, G, q, r_want, eps_k)
+    if not sat:
+        rep["rank_rule_met"] = False
+    V1 = V * canonical_signs(V)[None, :]
+    carry = A @ V1
+    dk = float(np.linalg.norm(A - carry @ V1.T))
+    return V1, carry, np.sqrt(e), dk, math.sqrt(normC2)
+
+
 def _reverse_modes(a, dims):
     t = np.asarray(a).reshape(dims, order="F")
     return np.transpose(t, tuple(range(len(dims) - 1, -1, -1))).reshape(-1, order="F")
 
 
-def _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank):
+def _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank, inner="sketch"):
     """TT-URV with left-orthogonal cores (remark after Thm. 3.2): reverse the
     index order, run the right-to-left URV sweep, reverse the cores back."""
     d = len(dims)
@@ -375,7 +480,7 @@ def _urv_l2r_by_reversal(a, dims, ranks, eps, q, p, seed, weights, max_rank):
     rw = None if weights is None else list(weights)[::-1]
     cores_b, rep = tt_utv(_reverse_modes(a, dims), rdims, ranks=rranks, eps=eps, sweep="R2L",
                           variant="URV", q=q, p=p, seed=seed, weights=rw, max_rank=max_rank,
-                          _labels=list(range(d, 0, -1)))
+                          inner=inner, _labels=list(range(d, 0, -1)))
     cores = [np.transpose(g, (2, 1, 0)) for g in cores_b[::-1]]
     rep["ranks"] = rep["ranks"][::-1]
     for key in ("delta", "normC", "ell", "s"):

@@ -483,3 +483,90 @@ def test_rgrad_step_minimises_f_on_its_line_and_recovers_a_low_rank_train():
     for _ in range(39):
         c, _, _ = oracle.rgrad_step(c, idx, vals, r)
     assert np.linalg.norm(oracle.tt_reconstruct(c) - a) <= 1e-7 * np.linalg.norm(a)
+
+
+# ---------------------------------------------------------------- deflation inner kernel
+DEFL_COMBOS = [("L2R", "ULV"), ("R2L", "URV"), ("L2R", "URV")]
+
+
+@pytest.mark.parametrize("sweep,variant", DEFL_COMBOS)
+def test_deflation_exact_tt_rank_reconstructs(sweep, variant):
+    """Thm. 3.1/3.2 with eps_k = 0 and the deflation inner kernel: after one
+    power step every vector lies in the row space of the tall unfolding, so r
+    orthonormal vectors span it and a tensor of exact TT-ranks is recovered."""
+    dims = [5, 6, 7, 5]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 0.0, 11)
+    cores, rep = oracle.tt_utv(a, dims, ranks=[3, 4, 3], sweep=sweep, variant=variant, q=1, seed=3,
+                               inner="deflation")
+    assert _rse(a, cores) < 1e-12
+    assert rep["ranks"] == [1, 3, 4, 3, 1]
+
+
+def test_deflation_converged_vectors_are_the_singular_vectors():
+    """d = 2 on a matrix of known, well separated spectrum: with many power steps
+    vector j converges to the j-th right singular vector and its energy to
+    sigma_j^2 (LAPACK SVD as the library reference).  Without the projection of
+    the earlier vectors every search would return the first one."""
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.standard_normal((60, 20)))
+    V, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    sig = 2.0 ** -np.arange(20)
+    M = (U * sig) @ V.T                           # 60 x 20
+    a = M.reshape(-1, order="F")
+    for sweep, variant in DEFL_COMBOS:
+        cores, rep = oracle.tt_utv(a, [60, 20], ranks=[6], sweep=sweep, variant=variant, q=80, seed=2,
+                                   inner="deflation")
+        s = rep["s"][0]
+        np.testing.assert_allclose(s, sig[:6], rtol=1e-12)
+        # the core side: the right singular vectors (R2L, n = 20) or the left ones (L2R, n = 60)
+        side = V[:, :6] if sweep == "R2L" and variant == "URV" else U[:, :6]
+        core = cores[1].reshape(6, 20).T if side.shape[0] == 20 else cores[0].reshape(60, 6)
+        assert np.max(np.abs(np.abs(core.T @ side) - np.eye(6))) < 1e-10
+        err = np.linalg.norm(oracle.tt_reconstruct(cores) - a)
+        assert err == pytest.approx(math.sqrt(np.sum(sig[6:] ** 2)), rel=1e-10)
+
+
+@pytest.mark.parametrize("sweep,variant", DEFL_COMBOS)
+def test_deflation_pythagoras_equality(sweep, variant):
+    """The deflation vectors are orthonormal and the carry is the exact
+    projection, so ||A - A_TT||^2 = sum delta_k^2 holds with equality, in both
+    rank modes; and the eps-mode error stays within eps."""
+    dims = [6, 7, 5, 6, 4]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 5, 5, 3], 1e-2, 21)
+    for kw in (dict(ranks=[3, 4, 4, 3]), dict(eps=3e-2)):
+        cores, rep = oracle.tt_utv(a, dims, sweep=sweep, variant=variant, q=1, seed=9, inner="deflation", **kw)
+        err2 = np.sum((oracle.tt_reconstruct(cores) - a) ** 2)
+        bound2 = np.sum(np.square(rep["delta"]))
+        assert err2 > 0
+        assert abs(err2 - bound2) <= 1e-9 * bound2
+        if "eps" in kw:
+            assert rep["rank_rule_met"]
+            assert math.sqrt(err2) <= 3e-2 * np.linalg.norm(a) * (1 + 1e-12)
+        # core-side orthogonality (Def. 2.2)
+        for g in (cores[:-1] if sweep == "L2R" else cores[1:]):
+            M = (g.reshape(-1, g.shape[2], order="F") if sweep == "L2R"
+                 else g.reshape(g.shape[0], -1, order="F").T)
+            assert np.max(np.abs(M.T @ M - np.eye(M.shape[1]))) < 1e-13
+
+
+def test_deflation_converged_eps_ranks_are_tt_svd_ranks():
+    """Prescribed accuracy on an Example-2 type tensor (smooth, 24^4): with
+    converged vectors the kept energies are the leading sigma_i^2, so the rank
+    rule picks the TT-SVD ranks at every tolerance (TT-SVD pinned above by
+    Eckart-Young and Table "Beps")."""
+    a = ttgen.sin_norm_tensor(4, 24)
+    dims = [24] * 4
+    for eps in (1e-2, 1e-3, 1e-4, 1e-6):
+        _, rs = oracle.tt_svd(a, dims, eps=eps, sweep="L2R")
+        for sweep, variant in (("L2R", "ULV"), ("R2L", "URV")):
+            cores, rep = oracle.tt_utv(a, dims, eps=eps, sweep=sweep, variant=variant, q=40, seed=1,
+                                       inner="deflation")
+            _, rsv = oracle.tt_svd(a, dims, eps=eps, sweep=sweep)
+            assert rep["ranks"] == rsv["ranks"], (eps, sweep, rep["ranks"], rsv["ranks"])
+            assert _rse(a, cores) <= eps * (1 + 1e-9)
+
+
+def test_deflation_rejects_alg4():
+    a = np.zeros(4 * 5)
+    with pytest.raises(ValueError):
+        oracle.tt_utv(a, [4, 5], ranks=[1], sweep="R2L", variant="ULV", inner="deflation")
