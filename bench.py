@@ -171,6 +171,11 @@ EX1_SNR = (0, 5, 10, 15, 20, 25, 30)
 EX1_RANKS = (2, 4, 6, 8, 10, 12, 14, 16, 18, 20)
 BEPS_TTSVD_RANKS = {1e-2: [2, 2, 2], 1e-3: [3, 3, 3], 1e-4: [5, 5, 5], 1e-5: [7, 7, 6]}
 EXAMPLE_FORMS = (("R2L", "URV"), ("L2R", "ULV"))
+# TT-ULV with the deflation inner kernel (the paper's "TT-ULV (USV-plus)" rows): left to right, q = 2 power
+# steps per vector; with a prescribed accuracy the rank cap 24 keeps every core side within the 4096 its
+# streaming pass takes (24 x 160)
+DEFL_KW = dict(sweep="L2R", variant="ULV", inner="deflation", q=2)
+DEFL_EPS_MAX_RANK = 24
 
 
 def paper_examples(T, reps):
@@ -206,7 +211,7 @@ def paper_examples(T, reps):
     dims = [160] * 4
     out = {"reps": reps}
     ex1 = {"workload": "160^4 FP64 (5.2 GB): Gaussian-TT cores of ranks 20 plus Gaussian noise at the given SNR "
-                       "(Sec. 4.1, Example 1); fixed TT-ranks, q=1, p=8",
+                       "(Sec. 4.1, Example 1); fixed TT-ranks, q=1, p=8 (sketch), q=2 per vector (deflation)",
            "snr_sweep": [], "rank_sweep": []}
     for snr in EX1_SNR:
         noise = 10.0 ** (-snr / 20.0)
@@ -215,6 +220,7 @@ def paper_examples(T, reps):
         for sweep, variant in EXAMPLE_FORMS:
             row[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[20] * 3, sweep=sweep, variant=variant, q=1,
                                                           oversample=8, seed=1))
+        row["ULV_L2R_deflation"] = run(A, dims, dict(ranks=[20] * 3, seed=1, **DEFL_KW))
         log(f"bench: example 1 SNR {snr:2d} dB, ranks 20: " + ", ".join(
             f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in row.items() if isinstance(v, dict)))
         ex1["snr_sweep"].append(row)
@@ -224,6 +230,7 @@ def paper_examples(T, reps):
                 for sweep, variant in EXAMPLE_FORMS:
                     rrow[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[r] * 3, sweep=sweep, variant=variant,
                                                                    q=1, oversample=8, seed=1))
+                rrow["ULV_L2R_deflation"] = run(A, dims, dict(ranks=[r] * 3, seed=1, **DEFL_KW))
                 log(f"bench: example 1 SNR 30 dB, ranks {r:2d}: " + ", ".join(
                     f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in rrow.items() if isinstance(v, dict)))
                 ex1["rank_sweep"].append(rrow)
@@ -231,7 +238,8 @@ def paper_examples(T, reps):
         torch.cuda.empty_cache()
     out["example1"] = ex1
     ex2 = {"workload": "160^4 FP64 (5.2 GB) sin(sqrt(sum_k ((i_k-1)/159)^2)) (Sec. 4.1, Example 2); prescribed "
-                       "accuracy, q=1, p=8; ttsvd_ranks_paper is the TT-SVD column of Table \"Beps\"",
+                       "accuracy, q=1, p=8 (sketch), q=2 per vector and rank cap 24 (deflation); "
+                       "ttsvd_ranks_paper is the TT-SVD column of Table \"Beps\"",
            "eps_sweep": []}
     B = ttgen.sin_norm_tensor_device(4, 160, device="cuda")
     for eps, svd_ranks in BEPS_TTSVD_RANKS.items():
@@ -239,6 +247,7 @@ def paper_examples(T, reps):
         for sweep, variant in EXAMPLE_FORMS:
             row[f"{variant}_{sweep}"] = run(B, dims, dict(eps=eps, sweep=sweep, variant=variant, q=1, oversample=8,
                                                           seed=2))
+        row["ULV_L2R_deflation"] = run(B, dims, dict(eps=eps, seed=2, max_rank=DEFL_EPS_MAX_RANK, **DEFL_KW))
         log(f"bench: example 2 eps {eps:g}: TT-SVD (paper) {svd_ranks}, " + ", ".join(
             f"{k} ranks {v['ranks']} {v['ms']:.2f} ms RSE {v['rse']:.3e}" for k, v in row.items()
             if isinstance(v, dict)))
@@ -543,9 +552,32 @@ def main():
         torch.cuda.synchronize()
         ms_q = (time.perf_counter() - t0) * 1e3 / args.c2_steps
         del dq
+        # the same ranks with the deflation inner kernel (one vector at a time, q = 1 power step each)
+        dd = T.Decomposer(W2["dims"], A2.dtype, inner="deflation", **decomposer_kw(W2))
+        for _ in range(3):
+            dd(A2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.c2_steps):
+            dd(A2)
+        torch.cuda.synchronize()
+        ms_d = (time.perf_counter() - t0) * 1e3 / args.c2_steps
+        rse_d = relative_error(T, dd.cores(), A2)
+        dd.set_profile(True)   # one more call with HIP events on every launch, for the pass durations
+        dd(A2)
+        torch.cuda.synchronize()
+        kd = dd.report()["kstat"]["defl_pass"]
+        del dd
+        defl = {"ms_per_step": round(ms_d, 5), "rse": rse_d,
+                "defl_pass_launches": kd["launches"],
+                "defl_pass_avg_us": round(kd["ms"] * 1e3 / max(kd["launches"], 1), 3),
+                "defl_pass_GB/s": round(kd["bytes"] / max(kd["ms"], 1e-9) / 1e6, 1),
+                "note": "pass figures from one extra call with HIP events on every launch"}
+        log(f"bench: 32^5 deflation inner kernel: {ms_d:.4f} ms/step, RSE {rse_d:.3e}, {kd['launches']} passes at "
+            f"{defl['defl_pass_avg_us']:.1f} us = {defl['defl_pass_GB/s']:.0f} GB/s")
         c2 = {"workload": W2["desc"], "value": round(v2, 2), "unit": "GB/s", "ms_per_step": round(tm2["ms"], 5),
               "steps": args.c2_steps, "ranks": c2_ranks, "rse": rse2, "roofline": roof2,
-              "ms_per_step_orth_cholqr": round(ms_q, 5)}
+              "ms_per_step_orth_cholqr": round(ms_q, 5), "deflation": defl}
         log(f"bench: 32^5 FP64 fixed rank: {tm2['ms']:.4f} ms/step, {v2:.1f} GB/s swept, RSE {rse2:.3e}, "
             f"{roof2['kernel']} {roof2['frac']:.1%} of peak, whole step {roof2['step_frac']:.1%}")
         del A2

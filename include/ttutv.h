@@ -97,7 +97,26 @@ typedef struct {
                                form; otherwise, or with the BF16 or one-pass power
                                products, the passes stay separate).  1: always a
                                separate sketch pass. */
+  int32_t inner;            /* tt_inner: the truncated factorisation of each step */
 } tt_opts;
+
+/* TT_INNER_SKETCH: the randomized power-iteration factorisation (a Gaussian
+ * test matrix of ell = r + p columns, q power steps, Rayleigh-Ritz).
+ * TT_INNER_DEFLATION: one core-side vector at a time, the paper's USV-plus
+ * based TT-ULV (Sec. 3.3 cost model 4 m n (k+1) q; Sec. 4): on the tall
+ * orientation A (m x n) of the unfolding, vector j starts from column j of the
+ * same Gaussian test matrix with the vectors already found projected out (two
+ * rounds of classical Gram-Schmidt), takes q >= 1 power steps
+ * x <- P(A^T A x) / ||P(A^T A x)||, and adds ||A v_j||^2 to the kept energy;
+ * the search stops at the fixed rank, or at the first j with
+ * ||C||^2 - kept <= eps_k^2 (the rank rule after Alg. 2), or after
+ * min(n, m, max_rank or TT_MAX_ELL) vectors.  The vectors are orthonormal, so
+ * delta_k^2 = ||C||^2 - ||carry||^2 as with the sketch.  Steps with n <= 64
+ * form A^T A in one pass and search on it in one workgroup; wider steps read A
+ * once per power step (class "defl_pass", n <= 4096).  FP64 form only; not
+ * with Alg. 4 (TT_ULV + TT_R2L) or TT_SVD (TT_EINVAL); report.ell holds the
+ * number of vectors kept and report.sweeps 0. */
+typedef enum { TT_INNER_SKETCH = 0, TT_INNER_DEFLATION = 1 } tt_inner;
 
 /* TT_ORTH_HOUSEHOLDER: Householder QR (one workgroup, or a tree of block QRs
  * for iterates taller than one workgroup holds).
@@ -136,7 +155,7 @@ typedef enum { TT_ORTH_HOUSEHOLDER = 0, TT_ORTH_CHOLQR = 1 } tt_orth;
 typedef enum { TT_PREC_FP64 = 0, TT_PREC_MIXED = 1, TT_PREC_MIXED_BF16 = 2 } tt_prec;
 
 /* Kernel classes of the profile (tt_kernel_class_name gives their names). */
-#define TT_NKCLASS 8
+#define TT_NKCLASS 9
 #define TT_PROFILE_ALL ((1 << TT_NKCLASS) - 1)
 typedef struct {
   int64_t launches;
@@ -165,7 +184,8 @@ const char* tt_kernel_class_name(int c);
 
 /* Fills opts with q = 1, oversample = 8, seed = 0, max_rank = 0,
  * exact_delta = 0, weights = NULL, profile = 0, prec = TT_PREC_FP64,
- * fuse_ata = 0, orth = TT_ORTH_HOUSEHOLDER, separate_sketch = 0. */
+ * fuse_ata = 0, orth = TT_ORTH_HOUSEHOLDER, separate_sketch = 0,
+ * inner = TT_INNER_SKETCH. */
 void tt_default_opts(tt_opts* opts);
 
 /* Device bytes of workspace tt_utv_decompose needs for this problem.

@@ -42,10 +42,10 @@ class tt_opts(ctypes.Structure):
                 ("max_rank", ctypes.c_int32), ("exact_delta", ctypes.c_int32),
                 ("weights", ctypes.POINTER(ctypes.c_double)), ("profile", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("fuse_ata", ctypes.c_int32), ("orth", ctypes.c_int32),
-                ("separate_sketch", ctypes.c_int32)]
+                ("separate_sketch", ctypes.c_int32), ("inner", ctypes.c_int32)]
 
 
-TT_NKCLASS = 8
+TT_NKCLASS = 9
 TT_PROFILE_ALL = (1 << TT_NKCLASS) - 1
 
 
@@ -203,10 +203,11 @@ def _full_ranks(ranks, d):
 
 PRECS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 ORTHS = {"householder": 0, "cholqr": 1}
+INNERS = {"sketch": 0, "deflation": 1}
 
 
 def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-              prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
+              prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False, inner="sketch"):
     o = tt_opts()
     load_library().tt_default_opts(ctypes.byref(o))
     o.q, o.oversample, o.seed, o.max_rank, o.exact_delta = q, oversample, seed, max_rank, int(bool(exact_delta))
@@ -216,6 +217,7 @@ def make_opts(q=1, oversample=8, seed=0, max_rank=0, exact_delta=False, weights=
     o.fuse_ata = int(bool(fuse_ata))
     o.orth = ORTHS[orth]
     o.separate_sketch = int(bool(separate_sketch))
+    o.inner = INNERS[inner]
     keep = None
     if weights is not None:
         keep = (ctypes.c_double * len(weights))(*[float(w) for w in weights])
@@ -240,7 +242,7 @@ def tt_utv_workspace(dims, ranks=None, eps=None, sweep="L2R", variant="ULV", dty
 
 
 def _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
-                    fuse_ata, orth="householder", separate_sketch=False):
+                    fuse_ata, orth="householder", separate_sketch=False, inner="sketch"):
     if not (A.is_cuda and A.is_contiguous()):
         raise ValueError("A must be a contiguous device tensor")
     if A.dtype not in DTYPES:
@@ -250,7 +252,7 @@ def _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_de
     if (ranks is None) == (eps is None):
         raise ValueError("give exactly one of ranks and eps")
     o, keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec, fuse_ata, orth,
-                        separate_sketch)
+                        separate_sketch, inner)
     rk = None if ranks is None else _i64(_full_ranks(ranks, len(dims)))
     epsv = -1.0 if eps is None else float(eps)
     return dims, o, keep, rk, epsv
@@ -288,13 +290,14 @@ def core_buffers_for(dims, ranks=None, eps=None, q=1, oversample=8, max_rank=0, 
 
 def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1, oversample=8, seed=0,
                      max_rank=0, exact_delta=False, weights=None, work=None, stream=None, allow_rank_miss=False,
-                     profile=False, prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
+                     profile=False, prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False,
+                     inner="sketch"):
     """TT-UTV of the device tensor A (float64/float32, flat in ivec order, i1
     fastest).  Returns (cores, report); cores[k] is a (r_{k-1}, I_k, r_k)
     float64 view of a column-major device buffer."""
     lib = load_library()
     dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
-                                               weights, profile, prec, fuse_ata, orth, separate_sketch)
+                                               weights, profile, prec, fuse_ata, orth, separate_sketch, inner)
     d = len(dims)
     nbytes = ctypes.c_size_t(0)
     _check(lib.tt_utv_workspace(d, _i64(dims), rk, epsv, SWEEPS[sweep], VARIANTS[variant], DTYPES[A.dtype],
@@ -317,7 +320,7 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
 def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                              oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, stream=None,
                              allow_rank_miss=False, prec="fp64", fuse_ata=False, orth="householder",
-                             separate_sketch=False):
+                             separate_sketch=False, inner="sketch"):
     """tt_utv_decompose on the library's static device scratch (no workspace
     argument): for problems whose workspace fits TT_NOALLOC_SCRATCH_BYTES.
     core_flats: caller-allocated flat float64 device buffers, one per core, at
@@ -325,7 +328,7 @@ def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L
     device memory.  Returns (cores, report) with cores viewing core_flats."""
     lib = load_library()
     dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
-                                               weights, False, prec, fuse_ata, orth, separate_sketch)
+                                               weights, False, prec, fuse_ata, orth, separate_sketch, inner)
     d = len(dims)
     if len(core_flats) != d:
         raise ValueError(f"need {d} core buffers, got {len(core_flats)}")
@@ -617,7 +620,8 @@ class Decomposer:
 
     def __init__(self, dims, dtype=torch.float64, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                  oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, profile=False,
-                 device="cuda", prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False):
+                 device="cuda", prec="fp64", fuse_ata=False, orth="householder", separate_sketch=False,
+                 inner="sketch"):
         lib = load_library()
         self.lib = lib
         self.dims = [int(x) for x in dims]
@@ -627,7 +631,7 @@ class Decomposer:
         self.dtype = dtype
         self.profile = profile
         self.opts, self._keep = make_opts(q, oversample, seed, max_rank, exact_delta, weights, profile, prec,
-                                          fuse_ata, orth, separate_sketch)
+                                          fuse_ata, orth, separate_sketch, inner)
         self._dims = _i64(self.dims)
         self._ranks = None if ranks is None else _i64(_full_ranks(ranks, d))
         self.eps = -1.0 if eps is None else float(eps)

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libttutv.so")
-SOURCES = ["tt_tall.hip", "tt_small.hip", "tt_train.hip", "tt_manifold.hip", "tt_carry_sketch.hip", "tt_api.hip"]
+SOURCES = ["tt_tall.hip", "tt_small.hip", "tt_train.hip", "tt_manifold.hip", "tt_carry_sketch.hip", "tt_deflation.hip",
+           "tt_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

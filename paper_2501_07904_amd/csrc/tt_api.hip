@@ -35,9 +35,9 @@ int fail(int code, const char* fmt, ...) {
 
 // ---- optional per-launch timing with HIP events on the caller's stream ----
 enum KClass { KC_ATB = 0, KC_AX = 1, KC_GRAM_Y = 2, KC_CARRY = 3, KC_RESID = 4, KC_REDUCE = 5, KC_SMALL = 6,
-              KC_ATA = 7 };
+              KC_ATA = 7, KC_DEFL = 8 };
 const char* const kClassNames[TT_NKCLASS] = {"tall_atb", "tall_ax", "gram_y", "carry", "resid", "reduce", "small",
-                                             "tall_ata"};
+                                             "tall_ata", "defl_pass"};
 
 thread_local std::vector<hipEvent_t> g_events;
 }  // namespace
@@ -115,6 +115,7 @@ struct Problem {
   bool alg4;
   bool mixed;   // carries and power iterates stored in FP32
   int bf16;     // mixed form with BF16 power products
+  bool defl;    // deflation inner kernel (one core-side vector at a time)
 };
 
 int64_t prod(const int64_t* v, int a, int b) {  // v[a] * ... * v[b-1]
@@ -147,12 +148,22 @@ int check_args(int d, const int64_t* dims, const int64_t* ranks, double eps, tt_
   if (P.o.fuse_ata != 0 && P.o.fuse_ata != 1) return fail(TT_EINVAL, "fuse_ata = %d is not 0 or 1", P.o.fuse_ata);
   if (P.o.orth != TT_ORTH_HOUSEHOLDER && P.o.orth != TT_ORTH_CHOLQR)
     return fail(TT_EINVAL, "orth = %d is not a tt_orth value", P.o.orth);
+  if (P.o.inner != TT_INNER_SKETCH && P.o.inner != TT_INNER_DEFLATION)
+    return fail(TT_EINVAL, "inner = %d is not a tt_inner value", P.o.inner);
   P.mixed = (P.o.prec != TT_PREC_FP64);
   P.bf16 = (P.o.prec == TT_PREC_MIXED_BF16) ? 1 : 0;
   P.sweep = sweep;
   P.variant = variant;
   P.dtype = dtype;
   P.alg4 = (sweep == TT_R2L && variant == TT_ULV);
+  P.defl = (P.o.inner == TT_INNER_DEFLATION);
+  if (P.defl) {
+    if (P.alg4 || variant == TT_SVD)
+      return fail(TT_EINVAL, "the deflation inner kernel keeps the core side orthonormal: not with %s",
+                  P.alg4 ? "Alg. 4 (ULV right to left)" : "TT_SVD");
+    if (P.mixed) return fail(TT_EINVAL, "the deflation inner kernel runs in the FP64 form only");
+    if (P.o.q < 1) return fail(TT_EINVAL, "the deflation inner kernel needs q >= 1 power steps per vector");
+  }
   P.fixed = ranks != nullptr;
   if (P.fixed) {
     if (ranks[0] != 1 || ranks[d] != 1) return fail(TT_EINVAL, "ranks must have r_0 = r_d = 1");
@@ -252,6 +263,9 @@ int plan_steps(const Problem& P, const int64_t* rk /* r_0..r_d to assume */, std
 int step_ell(const Problem& P, const Step& s, int ell_hint) {
   const int64_t lim = std::min<int64_t>(s.n, s.m);
   int64_t ell;
+  // the deflation search: the fixed rank, or at most TT_MAX_ELL vectors (s.r is
+  // the cap in eps mode)
+  if (P.defl) return (int)std::min<int64_t>(std::min<int64_t>(s.r, lim), TT_MAX_ELL);
   if (P.variant == TT_SVD) ell = lim;
   else if (P.fixed) ell = std::min<int64_t>((int64_t)s.r + P.o.oversample, lim);
   else ell = std::min<int64_t>(ell_hint, lim);
@@ -278,6 +292,7 @@ struct Work {
   double* fold;    // H_i = V1 G_i of a carry pass that also forms the next sketch
   int64_t fold_len;
   StepRec* recs;
+  DeflState* dstate;
   size_t bytes;
 };
 
@@ -303,7 +318,12 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
       z.fold = std::max(z.fold, (int64_t)S[i + 1].n_mode * std::min<int64_t>(s.n, kGramMax) * 48);
     z.V1 = std::max(z.V1, (int64_t)s.n * s.r);
     const int c = std::max(1, std::min(ellmax, (int)kCMax));
-    if (step_gram(P, s)) {
+    if (P.defl && !step_gram(P, s)) {
+      // the deflation search: V (n x cap) and the iterate in X, the reduced pass
+      // [z, ||A x||^2, ||A w||^2, ||A||^2] in M, per-workgroup pass partials in part
+      z.X = std::max(z.X, (int64_t)s.n * (c + 1) + 3);
+      z.part = std::max(z.part, (int64_t)defl_pass_groups(s.m, s.n) * (s.n + 3));
+    } else if (step_gram(P, s)) {
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, s.n) * s.n * s.n);
     } else {
       z.Y = std::max(z.Y, s.m * (int64_t)c);
@@ -356,12 +376,20 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
   W.fold = (double*)take(z.fold * 8);
   W.fold_len = z.fold;
   W.recs = (StepRec*)take(sizeof(StepRec) * (size_t)d);
+  W.dstate = (DeflState*)take(sizeof(DeflState));
   W.bytes = off;
   return off;
 }
 
 int check_limits(const Problem& P, const std::vector<Step>& S) {
   for (const Step& s : S) {
+    if (P.defl) {
+      if (P.fixed && s.r > TT_MAX_ELL)
+        return fail(TT_EUNSUPPORTED, "step for core %d asks for rank %d > %d", s.core, s.r, TT_MAX_ELL);
+      if (s.n > kGramMax && s.n > kDeflMaxN)
+        return fail(TT_EUNSUPPORTED, "deflation step for core %d: core side n = %d > %d", s.core, s.n, kDeflMaxN);
+      continue;
+    }
     const int ell = P.fixed ? step_ell(P, s, 0) : std::min<int64_t>(TT_MAX_ELL, std::min<int64_t>(s.n, s.m));
     if (P.fixed && ell > TT_MAX_ELL)
       return fail(TT_EUNSUPPORTED, "step for core %d needs ell = %d > %d (n = %d, m = %lld)", s.core,
@@ -407,6 +435,9 @@ SolveArgs sketch_args(const Problem& P, const Step& s, int ell) {
 // sketch_ready: the previous carry pass already wrote this step's test matrix
 // to W.X and the first product A X to W.Y (used unless this is a retry with a
 // wider sketch)
+int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, bool first, const StepIO& io,
+                  StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF);
+
 int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const StepIO& io,
              StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF, bool retry,
              bool sketch_ready = false) {
@@ -435,6 +466,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
 
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double mn = (double)m * n;
+  if (P.defl) return run_step_defl(P, s, ell, a, first, io, prev, prev_parts, W, st, PF);
   if (step_gram(P, s)) {
     // H = A^T A in one pass, then everything else on n x n (a retry with a wider
     // sketch reuses H: it does not depend on ell)
@@ -576,6 +608,77 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
   return TT_OK;
 }
 
+// One step with the deflation inner kernel.  n <= kGramMax: H = A^T A in one
+// pass and the whole search on H in one workgroup.  Otherwise one pass over A
+// per power step, each followed by the fixed-order reduction of its partials
+// and a one-workgroup update (projection, normalisation, bookkeeping); the pass
+// of vector j's first power step also measures the energy of vector j - 1, and
+// a last pass that of the final vector.  With a prescribed accuracy the host
+// reads the search state after every vector and stops launching once the rank
+// rule is met (later launches of a finished search would do nothing).
+// ||C||^2 of the step is measured on A itself (trace of H, or the first pass).
+int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, bool first, const StepIO& io,
+                  StepRec* prev, int prev_parts, const Work& W, hipStream_t st, Prof& PF) {
+  const int64_t m = s.m;
+  const int n = s.n;
+  const double sa = io.a_f32 ? 4.0 : 8.0;
+  const double mn = (double)m * n;
+  SolveArgs b = a;
+  b.nc_parts = nullptr;
+  b.nc_n = 0;
+  b.nc_out = nullptr;
+  if (!first && prev_parts > 0)   // the previous carry's ||.||^2 is still in partials
+    LAUNCH(PF, KC_REDUCE, (double)prev_parts * 8, prev_parts,
+           launch_reduce(W.cpart, prev_parts, 1, &prev->carry2, nullptr, st));
+  if (step_gram(P, s)) {
+    const int nch = atb_chunks(m, n, n);
+    LAUNCH(PF, KC_ATB, mn * sa + (double)n * n * 8, 2.0 * mn * n,
+           launch_atb(io.A, io.a_f32, io.A, io.a_f32, m, n, n, s.layout, W.part, nch, st));
+    LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * n * 8, (double)nch * n * n,
+           launch_reduce(W.part, nch, (int64_t)n * n, W.H, nullptr, st));
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_gram(W.H, b, cap, st));
+    return TT_OK;
+  }
+  DeflArgs D;
+  D.a = b;
+  D.cap = cap;
+  D.V = W.X;
+  D.x = W.X + (int64_t)n * cap;
+  D.st = W.dstate;
+  const int ng = defl_pass_groups(m, n);
+  const double pb = mn * sa + (double)ng * (n + 3) * 8;   // A once, the partials written
+  LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_start(D, st));
+  bool done = false;
+  for (int j = 0; j < cap && !done; ++j) {
+    for (int it = 0; it < P.o.q; ++it) {
+      const bool hw = (it == 0 && j > 0), fp = (j == 0 && it == 0);
+      LAUNCH(PF, KC_DEFL, pb + (hw ? 2.0 : 1.0) * n * 8, (hw ? 6.0 : 4.0) * mn,
+             launch_defl_pass(io.A, io.a_f32, m, n, s.layout, D.x, hw ? D.V + (int64_t)(j - 1) * n : nullptr,
+                              fp ? 1 : 0, W.part, ng, st));
+      LAUNCH(PF, KC_REDUCE, (double)(ng + 1) * (n + 3) * 8, (double)ng * (n + 3),
+             launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_update(W.M, D, j, hw ? 1 : 0, it == P.o.q - 1 ? 1 : 0, fp ? 1 : 0, st));
+    }
+    if (!P.fixed) {
+      DeflState hs;
+      HIP_OK(hipMemcpyAsync(&hs, W.dstate, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      done = hs.done != 0 || !std::isfinite(hs.normC2);   // a non-finite input stops the search
+    }
+  }
+  if (!done) {
+    // the energy of the last vector
+    LAUNCH(PF, KC_DEFL, pb + (double)n * 8, 2.0 * mn,
+           launch_defl_pass(io.A, io.a_f32, m, n, s.layout, nullptr, D.V + (int64_t)(cap - 1) * n, 0, W.part, ng,
+                            st));
+    LAUNCH(PF, KC_REDUCE, (double)(ng + 1) * (n + 3) * 8, (double)ng * (n + 3),
+           launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st));
+    LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_last(W.M, D, st));
+  }
+  LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_finish(D, st));
+  return TT_OK;
+}
+
 // defer_norm: leave ||carry||^2 as per-workgroup partials in W.cpart for the
 // next step's solve to reduce (*parts_out = their count, else 0).
 // The next step's first sketch product formed in this step's carry pass (see
@@ -592,8 +695,9 @@ int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io
                StepRec* rec, hipStream_t st, Prof& PF, bool defer_norm, int* parts_out,
                const NextSketch& nx = NextSketch()) {
   const int64_t m = s.m;
+  const bool direct = step_gram(P, s) || P.defl;   // carry = A V1 (else Y W from the Rayleigh-Ritz pass)
   const int ach = nx.on ? carry_sketch_groups(nx.m2, io.a_f32, io.out_f32)
-                        : (step_gram(P, s) ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r));
+                        : (direct ? ax_chunks(m, s.n, r) : ax_chunks(m, ell, r));
   const double sa = io.a_f32 ? 4.0 : 8.0;
   const double so = io.out_f32 ? 4.0 : 8.0;
   const double mr = (double)m * r;
@@ -607,7 +711,7 @@ int carry_step(const Problem& P, const Step& s, int ell, int r, const StepIO& io
            2.0 * mn * r + 2.0 * mn * nx.c,
            launch_carry_sketch(io.A, io.a_f32, nx.m2, nx.I, s.n, W.V1, r, W.fold, nx.c, io.out, io.out_f32, W.Y,
                                nparts, rerr, ach, st));
-  } else if (step_gram(P, s)) {
+  } else if (direct) {
     const double mn = (double)m * s.n;
     LAUNCH(PF, KC_CARRY, mn * sa + mr * so + (double)s.n * r * 8, 2.0 * mn * r,
            launch_ax(io.A, io.a_f32, W.V1, io.out, io.out_f32, m, s.n, r, s.layout, ach, nullptr, nparts, rerr, st));
@@ -770,7 +874,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     // forms the next step's first sketch product (its test matrix is drawn now,
     // with the width the next step will start from)
     NextSketch nx;
-    if (!last && P.sweep == TT_R2L && !P.alg4 && !P.o.separate_sketch && !P.bf16 && step_gram(P, s)) {
+    if (!last && P.sweep == TT_R2L && !P.alg4 && !P.defl && !P.o.separate_sketch && !P.bf16 && step_gram(P, s)) {
       int64_t r_next[TT_MAX_D + 1];
       for (int k = 0; k <= d; ++k) r_next[k] = r_run[k];
       r_next[s.core - 1] = r;
@@ -798,7 +902,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     rc = carry_step(P, s, ell, r, io, W, W.recs + si, st, PF, !last, &prev_parts, nx);
     if (rc) return rc;
     sketch_ready = nx.on;
-    ells[si] = ell;
+    ells[si] = P.defl ? r : ell;
     rs[si] = r;
     // rank of the bond this step decided
     if (P.sweep == TT_L2R) r_run[s.core] = r; else r_run[s.core - 1] = r;

@@ -1,0 +1,175 @@
+// The streaming pass of the deflation inner kernel (one core-side vector at a
+// time, the USV-plus reading of Sec. 3.3 / Sec. 4): for the tall A (m x n) of
+// a step and the current iterate x, z = A^T (A x) and ||A x||^2, together with
+// the energy ||A w||^2 of the vector finished last and, on a step's first pass,
+// ||A||_F^2 -- all from one read of A.  Each power step of the search costs one
+// such pass (HBM-bound: 4 m n flops on m n elements).
+//
+// Each workgroup owns a contiguous band of rows and holds its share of z in
+// registers: thread t keeps the columns t + 256 u (u < NC), so z needs no
+// reduction inside the band.  A band is read in chunks of RC rows (RC NC = 16
+// elements per thread); the chunk's row products y = A x and A w need a sum
+// over the workgroup, done for all 2 RC values together by a halving butterfly
+// (each exchange step halves the values a lane holds) and four wave partials
+// added in a fixed order, so every thread applies the same y.
+#include "tt_internal.h"
+
+namespace ttutv {
+
+namespace {
+
+constexpr int kPT = 256;       // threads per workgroup
+constexpr int kPerThread = 16; // elements of A per thread and chunk
+
+// Sums the V values of every lane over the 64 lanes of a wave.  Each halving
+// step at lane distance O pairs a lane with lane ^ O: the lane without bit O
+// keeps the sums of the lower half of its values, its partner those of the
+// upper half; once one value is left, plain exchange steps finish the sum.  On
+// return lane l holds the sum of value l >> (6 - log2 V) (the lanes holding one
+// value hold bitwise-equal sums).
+template <int CNT, int O, int V>
+__device__ __forceinline__ void wave_multi_sum_step(double (&v)[V], int lane) {
+  if constexpr (O >= 1) {
+    if constexpr (CNT > 1) {
+      constexpr int h = CNT / 2;
+      const bool up = (lane & O) != 0;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const double send = up ? v[k] : v[k + h];
+        const double keep = up ? v[k + h] : v[k];
+        v[k] = keep + __shfl_xor(send, O, 64);
+      }
+      wave_multi_sum_step<h, O / 2, V>(v, lane);
+    } else {
+      v[0] += __shfl_xor(v[0], O, 64);
+      wave_multi_sum_step<1, O / 2, V>(v, lane);
+    }
+  }
+}
+
+template <int V>
+__device__ __forceinline__ double wave_multi_sum(double (&v)[V], int lane) {
+  wave_multi_sum_step<V, 32, V>(v, lane);
+  return v[0];
+}
+
+template <int V>
+constexpr int log2c() {
+  return V <= 1 ? 0 : 1 + log2c<V / 2>();
+}
+
+template <typename TA, int LY, int NC>
+__global__ __launch_bounds__(kPT) void k_defl_pass(const TA* __restrict__ A, int64_t m, int n,
+                                                   const double* __restrict__ x, const double* __restrict__ w,
+                                                   int want_sq, int64_t band, double* __restrict__ part) {
+  constexpr int RC = kPerThread / NC;   // rows per chunk
+  constexpr int NV = 2 * RC;            // row products per chunk: A x and A w
+  constexpr int SH = 6 - log2c<NV>();   // lanes per reduced value = 1 << SH
+  __shared__ double sred[kPT / 64][NV];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const bool hx = x != nullptr, hw = w != nullptr;
+  double xv[NC], wvv[NC], z[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int col = t + kPT * u;
+    xv[u] = (hx && col < n) ? x[col] : 0.0;
+    wvv[u] = (hw && col < n) ? w[col] : 0.0;
+    z[u] = 0.0;
+  }
+  double ex = 0.0, ew = 0.0, sq = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * band;
+  const int64_t r1 = (r0 + band < m) ? r0 + band : m;
+  for (int64_t i0 = r0; i0 < r1; i0 += RC) {
+    double a[RC][NC];
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int64_t i = i0 + rr;
+        const int col = t + kPT * u;
+        a[rr][u] = (i < r1 && col < n) ? (double)A[LY == COL ? i + (int64_t)col * m : i * n + col] : 0.0;
+      }
+    }
+    double v[NV];
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      double px = 0.0, pw = 0.0;
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        px = fma(a[rr][u], xv[u], px);
+        pw = fma(a[rr][u], wvv[u], pw);
+        if (want_sq) sq = fma(a[rr][u], a[rr][u], sq);
+      }
+      v[rr] = px;
+      v[RC + rr] = pw;
+    }
+    const double s = wave_multi_sum<NV>(v, lane);
+    if ((lane & ((1 << SH) - 1)) == 0) sred[wv][lane >> SH] = s;
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      const double y = ((sred[0][rr] + sred[1][rr]) + sred[2][rr]) + sred[3][rr];
+      const double yw = ((sred[0][RC + rr] + sred[1][RC + rr]) + sred[2][RC + rr]) + sred[3][RC + rr];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) z[u] = fma(a[rr][u], y, z[u]);
+      ex = fma(y, y, ex);
+      ew = fma(yw, yw, ew);
+    }
+    __syncthreads();   // sred is rewritten by the next chunk
+  }
+  double* out = part + (int64_t)blockIdx.x * (n + 3);
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int col = t + kPT * u;
+    if (col < n) out[col] = hx ? z[u] : 0.0;
+  }
+  // ||A||^2 over the band: wave sums, then the four in order
+  for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if (lane == 0) sred[wv][0] = sq;
+  __syncthreads();
+  if (t == 0) {
+    out[n] = ex;
+    out[n + 1] = ew;
+    out[n + 2] = ((sred[0][0] + sred[1][0]) + sred[2][0]) + sred[3][0];
+  }
+}
+
+template <typename TA, int LY>
+hipError_t pass_nc(const TA* A, int64_t m, int n, const double* x, const double* w, int want_sq, double* part,
+                   int groups, int64_t band, hipStream_t st) {
+  const dim3 g((unsigned)groups), b(kPT);
+  if (n <= kPT) TT_LAUNCH((k_defl_pass<TA, LY, 1>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
+  else if (n <= 2 * kPT) TT_LAUNCH((k_defl_pass<TA, LY, 2>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
+  else if (n <= 4 * kPT) TT_LAUNCH((k_defl_pass<TA, LY, 4>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
+  else if (n <= 8 * kPT) TT_LAUNCH((k_defl_pass<TA, LY, 8>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
+  else TT_LAUNCH((k_defl_pass<TA, LY, 16>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
+  return hipGetLastError();
+}
+
+int64_t pass_band(int64_t m, int groups) {
+  const int64_t b = (m + groups - 1) / groups;
+  return b < 1 ? 1 : b;
+}
+
+}  // namespace
+
+int defl_pass_groups(int64_t m, int n) {
+  (void)n;
+  int64_t g = (m + 63) / 64;   // at least 64 rows per workgroup
+  if (g > 1024) g = 1024;
+  return g < 1 ? 1 : (int)g;
+}
+
+hipError_t launch_defl_pass(const void* A, int a_f32, int64_t m, int n, int layout, const double* x,
+                            const double* w, int want_sq, double* part, int groups, hipStream_t st) {
+  if (!A || m < 1 || n < 1 || n > kDeflMaxN || groups < 1 || !part) return hipErrorInvalidValue;
+  const int64_t band = pass_band(m, groups);   // trailing bands may be empty: they write zero partials
+  if (a_f32) {
+    if (layout == COL) return pass_nc<float, COL>((const float*)A, m, n, x, w, want_sq, part, groups, band, st);
+    return pass_nc<float, ROW>((const float*)A, m, n, x, w, want_sq, part, groups, band, st);
+  }
+  if (layout == COL) return pass_nc<double, COL>((const double*)A, m, n, x, w, want_sq, part, groups, band, st);
+  return pass_nc<double, ROW>((const double*)A, m, n, x, w, want_sq, part, groups, band, st);
+}
+
+}  // namespace ttutv

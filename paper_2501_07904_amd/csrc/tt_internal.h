@@ -140,6 +140,44 @@ hipError_t launch_alg4_basis(const double* K, double* T, int ell, hipStream_t st
 // carry weights W_r S_r (ell x r k-major, carry = U W).
 hipError_t launch_alg4_solve(const double* E, const double* Bt, const SolveArgs& a, hipStream_t st);
 
+// ---- deflation inner kernel (tt_small.hip, tt_deflation.hip) ---------------
+// One core-side vector at a time (the USV-plus reading of the paper's fastest
+// TT-ULV variant): vector j starts from column j of the step's test matrix with
+// the earlier vectors projected out (two classical Gram-Schmidt rounds), takes
+// q power steps x <- P(A^T A x) / ||P(A^T A x)||, and adds ||A v_j||^2 to the
+// kept energy; the search ends at the fixed rank, at the first j meeting the
+// rank rule, or after cap vectors.
+struct DeflState {
+  double normC2;   // ||C||_F^2 of the step (from the first pass over A)
+  double kept;     // sum of the energies of the vectors kept so far
+  int32_t r;       // vectors kept
+  int32_t sat;     // rank rule met (1 for fixed ranks)
+  int32_t done;    // search ended: later launches of the step do nothing
+  int32_t pad;
+};
+struct DeflArgs {
+  SolveArgs a;     // n, q, generator, rank target, core / V1 / record outputs
+  int cap;         // vectors at most (the fixed rank, or the eps-mode cap)
+  double* V;       // n x cap, column j at V + j n
+  double* x;       // the vector being iterated (n)
+  DeflState* st;
+};
+// Gram mode (n <= kGramMax): the whole search on H = A^T A in one workgroup,
+// then the core, V1 and the step record.
+hipError_t launch_defl_gram(const double* H, const SolveArgs& a, int cap, hipStream_t st);
+// Tall mode: zr = [z (n), ||A x||^2, ||A w||^2, ||A||_F^2] from one pass.
+hipError_t launch_defl_start(const DeflArgs& d, hipStream_t st);
+hipError_t launch_defl_update(const double* zr, const DeflArgs& d, int j, int has_w, int finish, int first_pass,
+                              hipStream_t st);
+hipError_t launch_defl_last(const double* zr, const DeflArgs& d, hipStream_t st);
+hipError_t launch_defl_finish(const DeflArgs& d, hipStream_t st);
+// The pass: per workgroup, z = A^T (A x) over its rows, ||A x||^2, ||A w||^2 and
+// (want_sq) ||A||_F^2, into part[g * (n + 3) ..]; x and w may be NULL.
+constexpr int kDeflMaxN = 4096;
+int defl_pass_groups(int64_t m, int n);
+hipError_t launch_defl_pass(const void* A, int a_f32, int64_t m, int n, int layout, const double* x,
+                            const double* w, int want_sq, double* part, int groups, hipStream_t st);
+
 // ---- train contractions (tt_train.hip) ------------------------------------
 // C (M x N) = A (M x K) B (K x N), all column-major, K <= kCMax; C is double or float.
 hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f32, int64_t M,

@@ -1016,7 +1016,338 @@ __global__ __launch_bounds__(kRRThreads) void k_alg4_solve(const double* __restr
   for (int i = t; i < kCMax; i += kRRThreads) a.rec->lam[i] = (i < L) ? lam[i] : 0.0;
 }
 
+// --------------------------------------------------------------------------
+// Deflation inner kernel: one core-side vector at a time (the USV-plus reading
+// of the paper's fastest TT-ULV variant, Sec. 3.3 / Sec. 4).  Vector j starts
+// from column j of the step's Gaussian test matrix with the vectors found so
+// far projected out, takes q power steps x <- P(A^T A x) / ||P(A^T A x)|| (a
+// step whose product vanishes keeps x), and adds its energy ||A v_j||^2 to the
+// kept energy; the search ends at the fixed rank, at the first j with
+// ||C||^2 - kept <= eps_k^2 (the rank rule after Alg. 2), or after cap vectors.
+// P is two rounds of classical Gram-Schmidt, z <- z - V (V^T z).
+
+// z <- z - V (V^T z) over the first j columns of V (LDS, column l at V + l kLd),
+// n <= 64, two rounds.  cbuf holds kCMax coefficients.
+__device__ __forceinline__ void defl_project_lds(double* z, const double* V, int n, int j, double* cbuf) {
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int row = t >> 4, p = t & 15;
+  for (int round = 0; round < 2 && j > 0; ++round) {
+    for (int l = wv; l < j; l += kThreads / 64) {
+      const double v = lane < n ? V[lane + l * kLd] * z[lane] : 0.0;
+      const double c = group_sum(v, 64);
+      if (lane == 0) cbuf[l] = c;
+    }
+    __syncthreads();
+    double sacc = 0.0;
+    if (row < n)
+      for (int l = p; l < j; l += 16) sacc = fma(V[row + l * kLd], cbuf[l], sacc);
+    sacc = row16_sum(sacc);
+    if (row < n && p == 0) z[row] -= sacc;   // z's readers above finished at the barrier
+    __syncthreads();
+  }
+}
+
+// ||z||^2 for z in LDS, n <= 64: the same value in every thread.
+__device__ __forceinline__ double defl_norm2_lds(const double* z, int n, double* sh) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const double v = t < n ? z[t] * z[t] : 0.0;
+    const double s2 = group_sum(v, 64);
+    if (t == 0) sh[0] = s2;
+  }
+  __syncthreads();
+  const double s2 = sh[0];
+  __syncthreads();
+  return s2;
+}
+
+// y = H x, H held in registers: thread (row, p) keeps H(row, p + 16 u), u < 4.
+__device__ __forceinline__ void defl_matvec(const double (&h)[4], const double* x, double* y, int n) {
+  const int t = threadIdx.x, row = t >> 4, p = t & 15;
+  double sacc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = p + 16 * u;
+    if (k < n) sacc = fma(h[u], x[k], sacc);
+  }
+  sacc = row16_sum(sacc);
+  if (row < n && p == 0) y[row] = sacc;
+  __syncthreads();
+}
+
+// Column j of the step's test matrix with the first j columns of V projected
+// out, normalised, into x (LDS).
+__device__ __forceinline__ void defl_start_lds(const SolveArgs& a, int j, double* x, const double* V, int n,
+                                               double* cbuf, double* sh) {
+  if (threadIdx.x < n) x[threadIdx.x] = sketch_row_entry(a, threadIdx.x, j);
+  __syncthreads();
+  defl_project_lds(x, V, n, j, cbuf);
+  const double nx = sqrt(defl_norm2_lds(x, n, sh));
+  if (threadIdx.x < n && nx > 0.0) x[threadIdx.x] = x[threadIdx.x] / nx;
+  __syncthreads();
+}
+
+// Writes V1 = V[:, :r] with canonical column signs (k-major, i r + c) and the
+// core in its layout; V (column-major, column stride ldv) may be in LDS or
+// global memory.
+__device__ __forceinline__ void defl_write_basis(const SolveArgs& a, const double* V, int64_t ldv, int n, int r,
+                                                 double* sg) {
+  canonical_signs<kThreads>(V, 1, ldv, n, r, sg);
+  const int64_t nr = (int64_t)n * r;
+  for (int64_t e = threadIdx.x; e < nr; e += kThreads) {
+    const int i = (int)(e / r), c = (int)(e % r);
+    const double v = V[i + c * ldv] * sg[c];
+    a.V1[e] = v;
+    if (a.core) {
+      if (a.core_layout == 0) a.core[i + (int64_t)n * c] = v;
+      else a.core[c + (int64_t)r * i] = v;
+    }
+  }
+}
+
+// Gram mode: H = A^T A (n x n column-major, n <= 64), the whole search in one
+// workgroup; ||C||^2 = trace(H).
+__global__ __launch_bounds__(kThreads) void k_defl_gram(const double* __restrict__ H, SolveArgs a, int cap) {
+  __shared__ double sV[kCMax * kLd];
+  __shared__ double sx[kCMax], sz[kCMax], cbuf[kCMax], lam[kCMax], sg[kCMax], sh[32];
+  __shared__ double snc2;
+  const int t = threadIdx.x, n = a.n;
+  const int row = t >> 4, p = t & 15;
+  double h[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = p + 16 * u;
+    h[u] = (row < n && k < n) ? H[row + (int64_t)n * k] : 0.0;
+  }
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += H[i + (int64_t)n * i];
+    snc2 = tr;
+    if (a.first) *a.normA2 = tr;
+  }
+  __syncthreads();
+  const double normC2 = snc2;
+  const double eps2 = a.eps_factor2 * (a.first ? normC2 : *a.normA2);
+  double kept = 0.0;
+  int r = 0, sat = a.r_fixed > 0 ? 1 : 0;
+  for (int j = 0; j < cap; ++j) {
+    defl_start_lds(a, j, sx, sV, n, cbuf, sh);
+    for (int it = 0; it < a.q; ++it) {
+      defl_matvec(h, sx, sz, n);
+      defl_project_lds(sz, sV, n, j, cbuf);
+      const double nz = sqrt(defl_norm2_lds(sz, n, sh));
+      if (t < n && nz > 0.0) sx[t] = sz[t] / nz;
+      __syncthreads();
+    }
+    if (t < n) sV[t + j * kLd] = sx[t];
+    // energy x^T H x
+    defl_matvec(h, sx, sz, n);
+    if (t < 64) {
+      const double v = t < n ? sx[t] * sz[t] : 0.0;
+      const double e = group_sum(v, 64);
+      if (t == 0) lam[j] = e;
+    }
+    __syncthreads();
+    kept += lam[j];   // every thread keeps the same running sum
+    r = j + 1;
+    const bool stop = (a.r_fixed > 0) ? (r >= a.r_fixed) : (normC2 - kept <= eps2);
+    if (stop) {
+      if (a.r_fixed <= 0) sat = 1;
+      break;
+    }
+  }
+  __syncthreads();
+  defl_write_basis(a, sV, kLd, n, r, sg);
+  if (t == 0) {
+    StepRec* rec = a.rec;
+    rec->normC2 = normC2;
+    rec->kept2 = kept;
+    rec->r = r;
+    rec->sat = sat;
+    rec->ell = r;
+    rec->resid2 = -1.0;
+    rec->rho2 = 0.0;
+    rec->sweeps = 0;
+  }
+  for (int i = t; i < kCMax; i += kThreads) a.rec->lam[i] = (i < r) ? lam[i] : 0.0;
+}
+
+// ---- tall mode: V (n x cap) and x in global memory, n <= 4096 -------------
+// z <- z - V (V^T z) over the first j columns (z in LDS), two rounds.
+__device__ __forceinline__ void defl_project_global(double* z, const double* V, int n, int j, double* cbuf) {
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  for (int round = 0; round < 2 && j > 0; ++round) {
+    for (int l = wv; l < j; l += kThreads / 64) {
+      const double* v = V + (int64_t)l * n;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i0 = lane; i0 < n; i0 += 256) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < n) acc[u] = fma(v[i], z[i], acc[u]);
+        }
+      }
+      const double c = group_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), 64);
+      if (lane == 0) cbuf[l] = c;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kThreads) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int l = 0;
+      for (; l + 4 <= j; l += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(V[i + (int64_t)(l + u) * n], cbuf[l + u], acc[u]);
+      }
+      for (; l < j; ++l) acc[0] = fma(V[i + (int64_t)l * n], cbuf[l], acc[0]);
+      z[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double defl_norm2_global(const double* z, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v = fma(z[i], z[i], v);
+  return block_sum(v, sh);
+}
+
+// x <- column j of the test matrix, projected and normalised (LDS staging zs).
+__device__ __forceinline__ void defl_start_global(const DeflArgs& d, int j, double* zs, double* cbuf, double* sh) {
+  const int n = d.a.n;
+  for (int i = threadIdx.x; i < n; i += kThreads) zs[i] = sketch_row_entry(d.a, i, j);
+  __syncthreads();
+  defl_project_global(zs, d.V, n, j, cbuf);
+  const double nx = sqrt(defl_norm2_global(zs, n, sh));
+  for (int i = threadIdx.x; i < n; i += kThreads) d.x[i] = nx > 0.0 ? zs[i] / nx : zs[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_defl_start(DeflArgs d) {
+  __shared__ double zs[kDeflMaxN], cbuf[kCMax], sh[32];
+  if (threadIdx.x == 0) {
+    d.st->normC2 = 0.0;
+    d.st->kept = 0.0;
+    d.st->r = 0;
+    d.st->sat = d.a.r_fixed > 0 ? 1 : 0;
+    d.st->done = 0;
+  }
+  for (int i = threadIdx.x; i < kCMax; i += kThreads) d.a.rec->lam[i] = 0.0;
+  defl_start_global(d, 0, zs, cbuf, sh);
+}
+
+// The kept vectors' bookkeeping after the energy ||A v_{j-1}||^2 = e is known
+// (thread 0): returns whether the search ends here.
+__device__ __forceinline__ bool defl_account(const DeflArgs& d, int j, double e) {
+  DeflState* S = d.st;
+  const double kept = S->kept + e;
+  S->kept = kept;
+  S->r = j;
+  d.a.rec->lam[j - 1] = e;
+  const double eps2 = d.a.eps_factor2 * (*d.a.normA2);
+  const bool stop = (d.a.r_fixed > 0) ? (j >= d.a.r_fixed) : (S->normC2 - kept <= eps2);
+  if (stop || j >= d.cap) {
+    S->done = 1;
+    if (d.a.r_fixed <= 0) S->sat = stop ? 1 : 0;
+  }
+  return S->done != 0;
+}
+
+// After a pass over the iterate x (and, with has_w, over the finished vector
+// v_{j-1}): account v_{j-1}, then the power step of vector j; finish: vector j
+// is complete, stored, and vector j + 1 is started.
+__global__ __launch_bounds__(kThreads) void k_defl_update(const double* __restrict__ zr, DeflArgs d, int j, int has_w,
+                                                          int finish, int first_pass) {
+  __shared__ double zs[kDeflMaxN], cbuf[kCMax], sh[32];
+  __shared__ int sdone;
+  const int t = threadIdx.x, n = d.a.n;
+  if (t == 0) {
+    DeflState* S = d.st;
+    int done = S->done;
+    if (!done && first_pass) {
+      S->normC2 = zr[n + 2];
+      if (d.a.first) *d.a.normA2 = zr[n + 2];
+    }
+    if (!done && has_w) done = defl_account(d, j, zr[n + 1]);
+    sdone = done;
+  }
+  __syncthreads();
+  if (sdone) return;
+  for (int i = t; i < n; i += kThreads) zs[i] = zr[i];
+  __syncthreads();
+  defl_project_global(zs, d.V, n, j, cbuf);
+  const double nz = sqrt(defl_norm2_global(zs, n, sh));
+  double* vj = d.V + (int64_t)j * n;
+  for (int i = t; i < n; i += kThreads) {
+    const double xi = nz > 0.0 ? zs[i] / nz : d.x[i];
+    d.x[i] = xi;
+    if (finish) vj[i] = xi;
+  }
+  if (finish && j + 1 < d.cap) {
+    __threadfence_block();   // column j of V is written before the next start vector reads it
+    __syncthreads();
+    defl_start_global(d, j + 1, zs, cbuf, sh);
+  }
+}
+
+// The energy of the last vector (a pass over w = v_{cap-1} alone).
+__global__ void k_defl_last(const double* __restrict__ zr, DeflArgs d) {
+  if (threadIdx.x != 0 || d.st->done) return;
+  defl_account(d, d.cap, zr[d.a.n + 1]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_defl_finish(DeflArgs d) {
+  __shared__ double sg[kCMax];
+  const DeflState* S = d.st;
+  const int r = S->r;
+  defl_write_basis(d.a, d.V, d.a.n, d.a.n, r, sg);
+  if (threadIdx.x == 0) {
+    StepRec* rec = d.a.rec;
+    rec->normC2 = S->normC2;
+    rec->kept2 = S->kept;
+    rec->r = r;
+    rec->sat = S->sat;
+    rec->ell = r;
+    rec->resid2 = -1.0;
+    rec->rho2 = 0.0;
+    rec->sweeps = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_defl_gram(const double* H, const SolveArgs& a, int cap, hipStream_t st) {
+  if (a.n < 1 || a.n > kGramMax || cap < 1 || cap > a.n || cap > kCMax || a.q < 1) return hipErrorInvalidValue;
+  TT_LAUNCH(k_defl_gram, dim3(1), dim3(kThreads), 0, st, H, a, cap);
+  return hipGetLastError();
+}
+
+static bool defl_args_ok(const DeflArgs& d) {
+  return d.a.n >= 1 && d.a.n <= kDeflMaxN && d.cap >= 1 && d.cap <= kCMax && d.cap <= d.a.n && d.V && d.x && d.st;
+}
+
+hipError_t launch_defl_start(const DeflArgs& d, hipStream_t st) {
+  if (!defl_args_ok(d)) return hipErrorInvalidValue;
+  TT_LAUNCH(k_defl_start, dim3(1), dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_defl_update(const double* zr, const DeflArgs& d, int j, int has_w, int finish, int first_pass,
+                              hipStream_t st) {
+  if (!defl_args_ok(d) || j < 0 || j >= d.cap || (has_w && j < 1)) return hipErrorInvalidValue;
+  TT_LAUNCH(k_defl_update, dim3(1), dim3(kThreads), 0, st, zr, d, j, has_w, finish, first_pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_defl_last(const double* zr, const DeflArgs& d, hipStream_t st) {
+  if (!defl_args_ok(d)) return hipErrorInvalidValue;
+  TT_LAUNCH(k_defl_last, dim3(1), dim3(64), 0, st, zr, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_defl_finish(const DeflArgs& d, hipStream_t st) {
+  if (!defl_args_ok(d)) return hipErrorInvalidValue;
+  TT_LAUNCH(k_defl_finish, dim3(1), dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_gram_solve(const double* H, const SolveArgs& a, hipStream_t st) {
   if (a.n < 1 || a.n > kGramMax || a.ell < 1) return hipErrorInvalidValue;

@@ -83,7 +83,7 @@ def test_one_pass_option_on_host(lib):
     assert _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=1, opts=o1)[0] == T.TT_EINVAL
     assert "fuse_ata" in lib.tt_last_error().decode()
     names = [lib.tt_kernel_class_name(c).decode() for c in range(T.TT_NKCLASS)]
-    assert names[-1] == "tall_ata" and lib.tt_kernel_class_name(T.TT_NKCLASS) is None
+    assert names[7] == "tall_ata" and lib.tt_kernel_class_name(T.TT_NKCLASS) is None
 
 
 def test_decompose_rejects_on_host(lib):
@@ -288,3 +288,33 @@ def test_completion_step_entry_points_reject_bad_arguments_on_the_host(lib):
                                 None) == T.TT_EINVAL
     assert lib.tt_tangent_train(3, dims, T._i64([1, 2, 3, 2]), vp3, vp3, vp3, 1.0, None, 1, vp3,
                                 None) == T.TT_EINVAL
+
+
+def test_deflation_option_on_host(lib):
+    """opts.inner: the sketch by default; the deflation inner kernel on request
+    for the sweeps that keep the core side orthonormal, FP64 form, q >= 1, and
+    core sides up to 4096 outside Gram mode; everything else refused."""
+    o = T.make_opts()[0]
+    assert o.inner == 0
+    od = T.make_opts(inner="deflation")[0]
+    assert od.inner == 1
+    for sweep, variant in ((0, 0), (1, 1), (0, 1)):
+        rc, nb = _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=sweep, variant=variant, opts=od)
+        assert rc == T.TT_OK and nb > 0, (sweep, variant, lib.tt_last_error())
+    # Alg. 4 and TT-SVD
+    for variant in (0, 2):
+        rc, _ = _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=variant, opts=od)
+        assert rc == T.TT_EINVAL and "deflation" in lib.tt_last_error().decode()
+    od0 = T.make_opts(inner="deflation", q=0)[0]
+    assert _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=od0)[0] == T.TT_EINVAL
+    assert "q >= 1" in lib.tt_last_error().decode()
+    odm = T.make_opts(inner="deflation", prec="mixed")[0]
+    assert _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=odm)[0] == T.TT_EINVAL
+    # a core side of 80 x 64 = 5120 > 4096 outside Gram mode
+    rc, _ = _ws(lib, [80, 80, 80], [1, 64, 64, 1], sweep=1, variant=1, opts=od)
+    assert rc == T.TT_EUNSUPPORTED and "4096" in lib.tt_last_error().decode()
+    od.inner = 7
+    assert _ws(lib, [40, 40, 40], [1, 32, 32, 1], sweep=1, variant=1, opts=od)[0] == T.TT_EINVAL
+    assert "inner" in lib.tt_last_error().decode()
+    assert lib.tt_kernel_class_name(8).decode() == "defl_pass"
+    assert lib.tt_kernel_class_name(T.TT_NKCLASS) is None
