@@ -31,7 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # workload scaled by the copy-probe factors (profiles/); empty whenever the class's kernels changed
 # after the counters were taken
 MEASURED_TRAFFIC = {"order6_40_fp32_eps": {"tall_ax": 5208.95e6, "tall_atb": 8838.73e6},
-                    "order5_32_fp64": {"tall_ax": 49.03e6, "tall_atb": 75.59e6}}
+                    "order5_32_fp64": {"tall_ax": 49.03e6, "tall_atb": 75.59e6},
+                    "order4_160_fp64_defl": {"defl_pass": 1971.58e6}}
 FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
@@ -45,6 +46,13 @@ WORKLOADS = {
         sweep="R2L", variant="URV", dtype="float64", device_built=False,
         desc="order-5 32^5 FP64 (33.5M entries) Gaussian-TT ranks 16 + 1e-6 relative noise; "
              "TT-URV right-to-left, fixed rank 16, q=2, p=8"),
+    # Example 1 of Sec. 4.1 at 30 dB with the paper's "TT-ULV (USV-plus)" form: the deflation inner kernel
+    "order4_160_fp64_defl": dict(
+        dims=[160] * 4, gen_ranks=[20] * 3, noise=10.0 ** -1.5, seed=1, ranks=[20] * 3, q=2, oversample=8,
+        sweep="L2R", variant="ULV", inner="deflation", dtype="float64", device_built=True,
+        desc="order-4 160^4 FP64 (655M entries, 5.2 GB) Gaussian-TT ranks 20 + Gaussian noise at 30 dB SNR "
+             "(Example 1); TT-ULV left-to-right with the deflation inner kernel (one vector at a time), fixed "
+             "rank 20, q=2 power steps per vector"),
 }
 
 
@@ -259,7 +267,8 @@ def paper_examples(T, reps):
 
 
 def decomposer_kw(W):
-    kw = dict(sweep=W["sweep"], variant=W["variant"], q=W["q"], oversample=W["oversample"], seed=W["seed"])
+    kw = dict(sweep=W["sweep"], variant=W["variant"], q=W["q"], oversample=W["oversample"], seed=W["seed"],
+              inner=W.get("inner", "sketch"))
     if "ranks" in W:
         kw["ranks"] = W["ranks"]
     else:

@@ -8,7 +8,7 @@
 // Each workgroup owns a contiguous band of rows and holds its share of z in
 // registers: thread t keeps the columns t + 256 u (u < NC), so z needs no
 // reduction inside the band.  A band is read in chunks of RC rows (RC NC = 16
-// elements per thread); the chunk's row products y = A x and A w need a sum
+// elements per thread, one row at least); the chunk's row products y = A x and A w need a sum
 // over the workgroup, done for all 2 RC values together by a halving butterfly
 // (each exchange step halves the values a lane holds) and four wave partials
 // added in a fixed order, so every thread applies the same y.
@@ -19,7 +19,7 @@ namespace ttutv {
 namespace {
 
 constexpr int kPT = 256;       // threads per workgroup
-constexpr int kPerThread = 16; // elements of A per thread and chunk
+constexpr int kPerThread = 16; // elements of A per thread and chunk (at least one row)
 
 // Sums the V values of every lane over the 64 lanes of a wave.  Each halving
 // step at lane distance O pairs a lane with lane ^ O: the lane without bit O
@@ -58,14 +58,79 @@ constexpr int log2c() {
   return V <= 1 ? 0 : 1 + log2c<V / 2>();
 }
 
+// Rows [i0, i0 + RC) of the band (ending at r1 >= 1) into registers; rows past
+// the band and columns past n read as zero.  FULL: every row is inside the band,
+// so the loads are unconditional (the column is clamped into A and the value
+// masked), and all of a chunk's loads are issued before the first wait; the
+// band's last, partial chunk checks its rows.
+template <bool FULL, typename TA, int LY, int NC, int RC>
+__device__ __forceinline__ void pass_load(const TA* __restrict__ A, int64_t m, int n, int64_t i0, int64_t r1,
+                                          double (&a)[RC][NC]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int rr = 0; rr < RC; ++rr) {
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int64_t i = i0 + rr;
+      const int col = t + kPT * u;
+      const int cc = col < n ? col : n - 1;
+      if (FULL) {
+        const double v = (double)A[LY == COL ? i + (int64_t)cc * m : i * n + cc];
+        a[rr][u] = col < n ? v : 0.0;
+      } else {
+        a[rr][u] = (i < r1 && col < n) ? (double)A[LY == COL ? i + (int64_t)cc * m : i * n + cc] : 0.0;
+      }
+    }
+  }
+}
+
+// One chunk: the row products A x and A w summed over the workgroup (sred
+// buffer `buf`, one barrier), then z += A^T (A x) on the thread's columns and
+// the chunk's shares of ||A x||^2, ||A w||^2 and ||A||^2.
+template <int NC, int RC>
+__device__ __forceinline__ void pass_chunk(const double (&a)[RC][NC], const double (&xv)[NC], const double (&wvv)[NC],
+                                           double (&z)[NC], double& ex, double& ew, double& sq, int want_sq,
+                                           double (*sred)[2 * RC]) {
+  constexpr int NV = 2 * RC;
+  constexpr int SH = 6 - log2c<NV>();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double v[NV];
+#pragma unroll
+  for (int rr = 0; rr < RC; ++rr) {
+    double px = 0.0, pw = 0.0;
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      px = fma(a[rr][u], xv[u], px);
+      pw = fma(a[rr][u], wvv[u], pw);
+      if (want_sq) sq = fma(a[rr][u], a[rr][u], sq);
+    }
+    v[rr] = px;
+    v[RC + rr] = pw;
+  }
+  const double s = wave_multi_sum<NV>(v, lane);
+  if ((lane & ((1 << SH) - 1)) == 0) sred[wv][lane >> SH] = s;
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < RC; ++rr) {
+    const double y = ((sred[0][rr] + sred[1][rr]) + sred[2][rr]) + sred[3][rr];
+    const double yw = ((sred[0][RC + rr] + sred[1][RC + rr]) + sred[2][RC + rr]) + sred[3][RC + rr];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) z[u] = fma(a[rr][u], y, z[u]);
+    ex = fma(y, y, ex);
+    ew = fma(yw, yw, ew);
+  }
+}
+
 template <typename TA, int LY, int NC>
 __global__ __launch_bounds__(kPT) void k_defl_pass(const TA* __restrict__ A, int64_t m, int n,
                                                    const double* __restrict__ x, const double* __restrict__ w,
                                                    int want_sq, int64_t band, double* __restrict__ part) {
-  constexpr int RC = kPerThread / NC;   // rows per chunk
-  constexpr int NV = 2 * RC;            // row products per chunk: A x and A w
-  constexpr int SH = 6 - log2c<NV>();   // lanes per reduced value = 1 << SH
-  __shared__ double sred[kPT / 64][NV];
+  constexpr int RC = NC >= kPerThread ? 1 : kPerThread / NC;   // rows per chunk
+  constexpr int NV = 2 * RC;                                    // row products per chunk: A x and A w
+  // two buffers: a chunk's writes never meet the previous chunk's reads, so one
+  // barrier per chunk orders them (a thread passes chunk k + 1's barrier only
+  // after its own reads of chunk k)
+  __shared__ double sred[2][kPT / 64][NV];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const bool hx = x != nullptr, hw = w != nullptr;
   double xv[NC], wvv[NC], z[NC];
@@ -79,43 +144,20 @@ __global__ __launch_bounds__(kPT) void k_defl_pass(const TA* __restrict__ A, int
   double ex = 0.0, ew = 0.0, sq = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * band;
   const int64_t r1 = (r0 + band < m) ? r0 + band : m;
-  for (int64_t i0 = r0; i0 < r1; i0 += RC) {
+  // one chunk at a time: the workgroups resident on a CU keep each other's
+  // loads in flight
+  int buf = 0;
+  int64_t i0 = r0;
+  for (; i0 + RC <= r1; i0 += RC) {
     double a[RC][NC];
-#pragma unroll
-    for (int rr = 0; rr < RC; ++rr) {
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        const int64_t i = i0 + rr;
-        const int col = t + kPT * u;
-        a[rr][u] = (i < r1 && col < n) ? (double)A[LY == COL ? i + (int64_t)col * m : i * n + col] : 0.0;
-      }
-    }
-    double v[NV];
-#pragma unroll
-    for (int rr = 0; rr < RC; ++rr) {
-      double px = 0.0, pw = 0.0;
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        px = fma(a[rr][u], xv[u], px);
-        pw = fma(a[rr][u], wvv[u], pw);
-        if (want_sq) sq = fma(a[rr][u], a[rr][u], sq);
-      }
-      v[rr] = px;
-      v[RC + rr] = pw;
-    }
-    const double s = wave_multi_sum<NV>(v, lane);
-    if ((lane & ((1 << SH) - 1)) == 0) sred[wv][lane >> SH] = s;
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < RC; ++rr) {
-      const double y = ((sred[0][rr] + sred[1][rr]) + sred[2][rr]) + sred[3][rr];
-      const double yw = ((sred[0][RC + rr] + sred[1][RC + rr]) + sred[2][RC + rr]) + sred[3][RC + rr];
-#pragma unroll
-      for (int u = 0; u < NC; ++u) z[u] = fma(a[rr][u], y, z[u]);
-      ex = fma(y, y, ex);
-      ew = fma(yw, yw, ew);
-    }
-    __syncthreads();   // sred is rewritten by the next chunk
+    pass_load<true, TA, LY, NC, RC>(A, m, n, i0, r1, a);
+    pass_chunk<NC, RC>(a, xv, wvv, z, ex, ew, sq, want_sq, sred[buf]);
+    buf ^= 1;
+  }
+  if (i0 < r1) {
+    double a[RC][NC];
+    pass_load<false, TA, LY, NC, RC>(A, m, n, i0, r1, a);
+    pass_chunk<NC, RC>(a, xv, wvv, z, ex, ew, sq, want_sq, sred[buf]);
   }
   double* out = part + (int64_t)blockIdx.x * (n + 3);
 #pragma unroll
@@ -125,12 +167,13 @@ __global__ __launch_bounds__(kPT) void k_defl_pass(const TA* __restrict__ A, int
   }
   // ||A||^2 over the band: wave sums, then the four in order
   for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 64);
-  if (lane == 0) sred[wv][0] = sq;
+  __syncthreads();   // the last chunk's readers of sred are done
+  if (lane == 0) sred[0][wv][0] = sq;
   __syncthreads();
   if (t == 0) {
     out[n] = ex;
     out[n + 1] = ew;
-    out[n + 2] = ((sred[0][0] + sred[1][0]) + sred[2][0]) + sred[3][0];
+    out[n + 2] = ((sred[0][0][0] + sred[0][1][0]) + sred[0][2][0]) + sred[0][3][0];
   }
 }
 
