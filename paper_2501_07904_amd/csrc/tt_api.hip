@@ -322,7 +322,7 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
       // the deflation search: V (n x cap) and the iterate in X, the reduced pass
       // [z, ||A x||^2, ||A w||^2, ||A||^2] in M, per-workgroup pass partials in part
       z.X = std::max(z.X, (int64_t)s.n * (c + 1) + 3);
-      z.part = std::max(z.part, (int64_t)defl_pass_groups(s.m, s.n) * (s.n + 3));
+      z.part = std::max(z.part, (int64_t)defl_pass_groups(s.m, s.n, s.layout) * (s.n + 3));
     } else if (step_gram(P, s)) {
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, s.n) * s.n * s.n);
     } else {
@@ -645,7 +645,7 @@ int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, 
   D.V = W.X;
   D.x = W.X + (int64_t)n * cap;
   D.st = W.dstate;
-  const int ng = defl_pass_groups(m, n);
+  const int ng = defl_pass_groups(m, n, s.layout);
   const double pb = mn * sa + (double)ng * (n + 3) * 8;   // A once, the partials written
   LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_start(D, st));
   bool done = false;

@@ -20,6 +20,8 @@ namespace {
 
 constexpr int kPT = 256;       // threads per workgroup
 constexpr int kPerThread = 16; // elements of A per thread and chunk (at least one row)
+constexpr int kWaveMaxN = 512; // widest core side of the one-wave form (row-major A)
+constexpr int kWaveMaxNCol = 128; // (column-major A: each lane then reads runs of at least 8 rows)
 
 // Sums the V values of every lane over the 64 lanes of a wave.  Each halving
 // step at lane distance O pairs a lane with lane ^ O: the lane without bit O
@@ -177,10 +179,120 @@ __global__ __launch_bounds__(kPT) void k_defl_pass(const TA* __restrict__ A, int
   }
 }
 
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// The same pass with one wave per workgroup, for n <= 512 on row-major A and
+// n <= 128 on column-major A (lane l keeps the columns l + 64 u, u < NC): a
+// chunk's row products are summed by the wave's halving butterfly alone and
+// read back with v_readlane, so no barrier and no LDS; many small workgroups
+// keep the CUs' load queues full.  (Column-major A with wide n would leave each
+// lane reading 16-byte runs of one column.)
+template <typename TA, int LY, int NC>
+__global__ __launch_bounds__(64) void k_defl_pass_w(const TA* __restrict__ A, int64_t m, int n,
+                                                    const double* __restrict__ x, const double* __restrict__ w,
+                                                    int want_sq, int64_t band, double* __restrict__ part) {
+  constexpr int RC = NC >= kPerThread ? 1 : kPerThread / NC;
+  constexpr int NV = 2 * RC;
+  constexpr int SH = 6 - log2c<NV>();
+  const int lane = threadIdx.x;
+  const bool hx = x != nullptr, hw = w != nullptr;
+  double xv[NC], wvv[NC], z[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int col = lane + 64 * u;
+    xv[u] = (hx && col < n) ? x[col] : 0.0;
+    wvv[u] = (hw && col < n) ? w[col] : 0.0;
+    z[u] = 0.0;
+  }
+  double ex = 0.0, ew = 0.0, sq = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * band;
+  const int64_t r1 = (r0 + band < m) ? r0 + band : m;
+  auto chunk = [&](const double (&a)[RC][NC]) {
+    double v[NV];
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      double px = 0.0, pw = 0.0;
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        px = fma(a[rr][u], xv[u], px);
+        pw = fma(a[rr][u], wvv[u], pw);
+        if (want_sq) sq = fma(a[rr][u], a[rr][u], sq);
+      }
+      v[rr] = px;
+      v[RC + rr] = pw;
+    }
+    const double s = wave_multi_sum<NV>(v, lane);
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      const double y = readlane_d(s, rr << SH);
+      const double yw = readlane_d(s, (RC + rr) << SH);
+#pragma unroll
+      for (int u = 0; u < NC; ++u) z[u] = fma(a[rr][u], y, z[u]);
+      ex = fma(y, y, ex);
+      ew = fma(yw, yw, ew);
+    }
+  };
+  int64_t i0 = r0;
+  for (; i0 + RC <= r1; i0 += RC) {
+    double a[RC][NC];
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int64_t i = i0 + rr;
+        const int col = lane + 64 * u;
+        const int cc = col < n ? col : n - 1;
+        const double v = (double)A[LY == COL ? i + (int64_t)cc * m : i * n + cc];
+        a[rr][u] = col < n ? v : 0.0;
+      }
+    }
+    chunk(a);
+  }
+  if (i0 < r1) {
+    double a[RC][NC];
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int64_t i = i0 + rr;
+        const int col = lane + 64 * u;
+        const int cc = col < n ? col : n - 1;
+        a[rr][u] = (i < r1 && col < n) ? (double)A[LY == COL ? i + (int64_t)cc * m : i * n + cc] : 0.0;
+      }
+    }
+    chunk(a);
+  }
+  double* out = part + (int64_t)blockIdx.x * (n + 3);
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const int col = lane + 64 * u;
+    if (col < n) out[col] = hx ? z[u] : 0.0;
+  }
+  for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if (lane == 0) {
+    out[n] = ex;
+    out[n + 1] = ew;
+    out[n + 2] = sq;
+  }
+}
+
+bool one_wave(int n, int layout) { return n <= (layout == COL ? kWaveMaxNCol : kWaveMaxN); }
+
 template <typename TA, int LY>
 hipError_t pass_nc(const TA* A, int64_t m, int n, const double* x, const double* w, int want_sq, double* part,
                    int groups, int64_t band, hipStream_t st) {
-  const dim3 g((unsigned)groups), b(kPT);
+  const dim3 g((unsigned)groups), b(kPT), bw(64);
+  if (one_wave(n, LY)) {
+    if (n <= 64) TT_LAUNCH((k_defl_pass_w<TA, LY, 1>), g, bw, 0, st, A, m, n, x, w, want_sq, band, part);
+    else if (n <= 128) TT_LAUNCH((k_defl_pass_w<TA, LY, 2>), g, bw, 0, st, A, m, n, x, w, want_sq, band, part);
+    else if (n <= 256) TT_LAUNCH((k_defl_pass_w<TA, LY, 4>), g, bw, 0, st, A, m, n, x, w, want_sq, band, part);
+    else TT_LAUNCH((k_defl_pass_w<TA, LY, 8>), g, bw, 0, st, A, m, n, x, w, want_sq, band, part);
+    return hipGetLastError();
+  }
   if (n <= kPT) TT_LAUNCH((k_defl_pass<TA, LY, 1>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
   else if (n <= 2 * kPT) TT_LAUNCH((k_defl_pass<TA, LY, 2>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
   else if (n <= 4 * kPT) TT_LAUNCH((k_defl_pass<TA, LY, 4>), g, b, 0, st, A, m, n, x, w, want_sq, band, part);
@@ -196,10 +308,15 @@ int64_t pass_band(int64_t m, int groups) {
 
 }  // namespace
 
-int defl_pass_groups(int64_t m, int n) {
-  (void)n;
-  int64_t g = (m + 63) / 64;   // at least 64 rows per workgroup
-  if (g > 1024) g = 1024;
+int defl_pass_groups(int64_t m, int n, int layout) {
+  // one-wave workgroups: at least 16 rows each, up to 8192 (measured on a
+  // 4,096,000 x 160 row-major pass: 989 us at 8192 against 1141 us at 4096, whose
+  // partials reduce in 32 us instead of 59); four-wave workgroups: at least 64 rows
+  // each, up to 1024
+  const bool wave = one_wave(n, layout);
+  int64_t g = wave ? (m + 15) / 16 : (m + 63) / 64;
+  const int64_t cap = wave ? 8192 : 1024;
+  if (g > cap) g = cap;
   return g < 1 ? 1 : (int)g;
 }
 

@@ -174,7 +174,7 @@ hipError_t launch_defl_finish(const DeflArgs& d, hipStream_t st);
 // The pass: per workgroup, z = A^T (A x) over its rows, ||A x||^2, ||A w||^2 and
 // (want_sq) ||A||_F^2, into part[g * (n + 3) ..]; x and w may be NULL.
 constexpr int kDeflMaxN = 4096;
-int defl_pass_groups(int64_t m, int n);
+int defl_pass_groups(int64_t m, int n, int layout);
 hipError_t launch_defl_pass(const void* A, int a_f32, int64_t m, int n, int layout, const double* x,
                             const double* w, int want_sq, double* part, int groups, hipStream_t st);
 
