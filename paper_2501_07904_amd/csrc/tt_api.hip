@@ -322,7 +322,9 @@ Sizes size_bounds(const Problem& P, const std::vector<Step>& S) {
       // the deflation search: V (n x cap) and the iterate in X, the reduced pass
       // [z, ||A x||^2, ||A w||^2, ||A||^2] in M, per-workgroup pass partials in part
       z.X = std::max(z.X, (int64_t)s.n * (c + 1) + 3);
-      z.part = std::max(z.part, (int64_t)defl_pass_groups(s.m, s.n, s.layout) * (s.n + 3));
+      // (+ the first-stage stripes of their two-stage reduction), for any n up to
+      // the planned one
+      z.part = std::max(z.part, defl_pass_scratch(s.m, s.n, s.layout));
     } else if (step_gram(P, s)) {
       z.part = std::max(z.part, (int64_t)atb_chunks(s.m, s.n, s.n) * s.n * s.n);
     } else {
@@ -646,6 +648,10 @@ int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, 
   D.x = W.X + (int64_t)n * cap;
   D.st = W.dstate;
   const int ng = defl_pass_groups(m, n, s.layout);
+  double* stripes = W.part + (int64_t)ng * (n + 3);   // after the pass partials (sized for both)
+  if ((int64_t)(ng + kReduceStripes) * (n + 3) > W.part_len)
+    return fail(TT_EINVAL, "internal: deflation scratch %lld doubles > %lld", (long long)(ng + kReduceStripes) * (n + 3),
+                (long long)W.part_len);
   const double pb = mn * sa + (double)ng * (n + 3) * 8;   // A once, the partials written
   LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_start(D, st));
   bool done = false;
@@ -656,7 +662,7 @@ int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, 
              launch_defl_pass(io.A, io.a_f32, m, n, s.layout, D.x, hw ? D.V + (int64_t)(j - 1) * n : nullptr,
                               fp ? 1 : 0, W.part, ng, st));
       LAUNCH(PF, KC_REDUCE, (double)(ng + 1) * (n + 3) * 8, (double)ng * (n + 3),
-             launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st));
+             launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st, stripes));
       LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_update(W.M, D, j, hw ? 1 : 0, it == P.o.q - 1 ? 1 : 0, fp ? 1 : 0, st));
     }
     if (!P.fixed) {
@@ -672,7 +678,7 @@ int run_step_defl(const Problem& P, const Step& s, int cap, const SolveArgs& a, 
            launch_defl_pass(io.A, io.a_f32, m, n, s.layout, nullptr, D.V + (int64_t)(cap - 1) * n, 0, W.part, ng,
                             st));
     LAUNCH(PF, KC_REDUCE, (double)(ng + 1) * (n + 3) * 8, (double)ng * (n + 3),
-           launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st));
+           launch_reduce(W.part, ng, (int64_t)n + 3, W.M, nullptr, st, stripes));
     LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_last(W.M, D, st));
   }
   LAUNCH(PF, KC_SMALL, 0, 0, launch_defl_finish(D, st));

@@ -310,14 +310,33 @@ int64_t pass_band(int64_t m, int groups) {
 
 int defl_pass_groups(int64_t m, int n, int layout) {
   // one-wave workgroups: at least 16 rows each, up to 8192 (measured on a
-  // 4,096,000 x 160 row-major pass: 989 us at 8192 against 1141 us at 4096, whose
-  // partials reduce in 32 us instead of 59); four-wave workgroups: at least 64 rows
-  // each, up to 1024
+  // 4,096,000 x 160 row-major pass: 989 us at 8192 against 1141 us at 4096);
+  // four-wave workgroups: at least 64 rows each, up to 1024, and on a short A
+  // at least 16 rows each, up to 64
   const bool wave = one_wave(n, layout);
   int64_t g = wave ? (m + 15) / 16 : (m + 63) / 64;
   const int64_t cap = wave ? 8192 : 1024;
   if (g > cap) g = cap;
+  if (!wave && g < 64) {   // a short, wide A: bands of 16 rows, up to 64 workgroups
+    const int64_t g16 = (m + 15) / 16;
+    g = g16 < 64 ? g16 : 64;
+  }
   return g < 1 ? 1 : (int)g;
+}
+
+int64_t defl_pass_scratch(int64_t m, int n_max, int layout) {
+  // the pass partials for any core side n <= n_max (a prescribed-accuracy step
+  // learns its n at run time; the one-wave form, taken below a width threshold,
+  // has the most workgroups), plus the stripes of their two-stage reduction
+  const int thr = layout == COL ? kWaveMaxNCol : kWaveMaxN;
+  int64_t most = 0;
+  const int nw = n_max < thr ? n_max : thr;
+  if (nw >= 1) most = (int64_t)defl_pass_groups(m, nw, layout) * (nw + 3);
+  if (n_max > thr) {
+    const int64_t g4 = (int64_t)defl_pass_groups(m, n_max, layout) * (n_max + 3);
+    if (g4 > most) most = g4;
+  }
+  return most + (int64_t)kReduceStripes * (n_max + 3);
 }
 
 hipError_t launch_defl_pass(const void* A, int a_f32, int64_t m, int n, int layout, const double* x,

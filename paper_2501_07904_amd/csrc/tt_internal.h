@@ -85,9 +85,13 @@ hipError_t launch_atb2(const void* A, int a_f32, const void* Y, int y_f32, int64
 int resid_chunks(int64_t m);
 hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, const double* V1, int64_t m,
                         int n, int r, int layout, int nchunks, double* resid, hipStream_t st);
-// out[e] (+ out2[e] if out2) = sum_ch partials[ch*size + e], fixed order.
+// out[e] (+ out2[e] if out2) = sum_ch partials[ch*size + e], fixed order.  With
+// `stripes` (kReduceStripes * size doubles, not overlapping partials), many chunks
+// of a short vector are summed in two stages: stripes of consecutive chunks in
+// parallel, then the stripes in order.
+constexpr int kReduceStripes = 64;
 hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,
-                         double* out2, hipStream_t st);
+                         double* out2, hipStream_t st, double* stripes = nullptr);
 
 // ---- single-workgroup factorisations (tt_small.hip) -----------------------
 struct SolveArgs {
@@ -175,6 +179,9 @@ hipError_t launch_defl_finish(const DeflArgs& d, hipStream_t st);
 // (want_sq) ||A||_F^2, into part[g * (n + 3) ..]; x and w may be NULL.
 constexpr int kDeflMaxN = 4096;
 int defl_pass_groups(int64_t m, int n, int layout);
+// Doubles of scratch the passes of a step need for any core side up to n_max:
+// the per-workgroup partials and the stripes of their reduction.
+int64_t defl_pass_scratch(int64_t m, int n_max, int layout);
 hipError_t launch_defl_pass(const void* A, int a_f32, int64_t m, int n, int layout, const double* x,
                             const double* w, int want_sq, double* part, int groups, hipStream_t st);
 

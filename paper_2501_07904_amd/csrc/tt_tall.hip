@@ -1374,6 +1374,30 @@ __global__ __launch_bounds__(16 * SL) void k_reduce(const double* __restrict__ p
   }
 }
 
+// First stage of a two-stage fixed-order sum for many chunks of a short vector:
+// workgroup (b, s) sums chunks [s K, min((s + 1) K, nchunks)) of entries
+// 16 b .. 16 b + 15 into stripes[s size + e] (the order inside a stripe as in
+// k_reduce; the stripes are then summed in order by k_reduce).
+__global__ __launch_bounds__(16 * 16) void k_reduce_stripe(const double* __restrict__ partials, int nchunks,
+                                                           int per_stripe, int64_t size,
+                                                           double* __restrict__ stripes) {
+  __shared__ double red[16][17];
+  const int el = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + el;
+  const int c0 = blockIdx.y * per_stripe;
+  const int c1 = min(nchunks, c0 + per_stripe);
+  double s = 0.0;
+  if (e < size)
+    for (int ch = c0 + sl; ch < c1; ch += 16) s += partials[(int64_t)ch * size + e];
+  red[sl][el] = s;
+  __syncthreads();
+  if (sl == 0 && e < size) {
+    double tot = 0.0;
+    for (int k = 0; k < 16; ++k) tot += red[k][el];
+    stripes[(int64_t)blockIdx.y * size + e] = tot;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1564,13 +1588,21 @@ hipError_t launch_resid(const void* A, int a_f32, const void* Cr, int c_f32, con
 }
 
 hipError_t launch_reduce(const double* partials, int nchunks, int64_t size, double* out,
-                         double* out2, hipStream_t st) {
+                         double* out2, hipStream_t st, double* stripes) {
   if (size < 1 || nchunks < 1) return hipErrorInvalidValue;
   if (size == 1) {
     TT_LAUNCH(k_reduce_scalar, dim3(1), dim3(kThreads), 0, st, partials, nchunks, out, out2);
     return hipGetLastError();
   }
   const int64_t blocks = (size + 15) / 16;
+  if (stripes && nchunks >= 2048 && blocks < 128) {
+    // few workgroups over many chunks: two stages, kReduceStripes stripes first
+    const int per = (nchunks + kReduceStripes - 1) / kReduceStripes;
+    TT_LAUNCH(k_reduce_stripe, dim3((unsigned)blocks, (unsigned)kReduceStripes), dim3(16 * 16), 0, st, partials,
+              nchunks, per, size, stripes);
+    TT_LAUNCH(k_reduce<16>, dim3((unsigned)blocks), dim3(16 * 16), 0, st, stripes, kReduceStripes, size, out, out2);
+    return hipGetLastError();
+  }
   if (nchunks >= 256)
     TT_LAUNCH(k_reduce<64>, dim3((unsigned)blocks), dim3(16 * 64), 0, st, partials, nchunks, size, out, out2);
   else

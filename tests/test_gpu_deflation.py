@@ -164,3 +164,40 @@ def test_full_size_order5_32():
     _compare(cores, oc, "R2L")
     for x, y in zip(rep["delta"], orep["delta"]):
         assert abs(x * x - y * y) <= 1e-13 * orep["norm_A"] ** 2
+
+
+@pytest.mark.parametrize("sweep,variant", [("R2L", "URV"), ("L2R", "ULV")])
+def test_fixed_rank_above_the_true_rank(sweep, variant):
+    """Exact TT-ranks (3, 4, 3) asked for at ranks (5, 6, 5): after the true-rank
+    vectors every power product is rounding noise, so the extra vectors are
+    arbitrary unit directions orthogonal to the others (they differ from the
+    oracle's); the reconstruction is exact on both sides and the cores stay
+    orthonormal."""
+    dims = [6, 7, 8, 9]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4, 3], 0.0, 23)
+    print(f"deflation: ranks above the true rank, {sweep}", flush=True)
+    cores, rep = _run(a, dims, sweep, variant, ranks=[5, 6, 5])
+    oc, orep = oracle.tt_utv(a, dims, ranks=[5, 6, 5], sweep=sweep, variant=variant, q=1, seed=3, inner="deflation")
+    assert rep["ranks"] == orep["ranks"] == [1, 5, 6, 5, 1]
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    nrm = np.linalg.norm(a)
+    assert np.linalg.norm(rec - a) <= 1e-12 * nrm
+    assert np.linalg.norm(oracle.tt_reconstruct(oc) - a) <= 1e-12 * nrm
+    g = _np(cores)
+    for c in (g[:-1] if sweep == "L2R" else g[1:]):
+        M = c.reshape(-1, c.shape[2], order="F") if sweep == "L2R" else c.reshape(c.shape[0], -1, order="F").T
+        assert np.max(np.abs(M.T @ M - np.eye(M.shape[1]))) < 1e-13
+
+
+def test_zero_tolerance_runs_to_the_cap():
+    """eps = 0: the rule is met only by an exact fit, so on a noisy tensor every
+    step keeps max_rank vectors; the search stops there and reports the miss."""
+    dims = [8, 9, 10]
+    a, _ = ttgen.gaussian_tt_tensor(dims, [3, 4], 1e-2, 29)
+    print("deflation: eps = 0", flush=True)
+    cores, rep = _run(a, dims, "R2L", "URV", q=1, eps=0.0, max_rank=6, allow_rank_miss=True)
+    oc, orep = oracle.tt_utv(a, dims, eps=0.0, sweep="R2L", variant="URV", q=1, seed=3, max_rank=6,
+                             inner="deflation")
+    assert rep["ranks"] == orep["ranks"] == [1, 6, 6, 1]
+    assert not rep["rank_rule_met"]
+    _compare(cores, oc, "R2L")
