@@ -15,13 +15,13 @@ pytestmark = pytest.mark.gpu
 T = pytest.importorskip("paper_2501_07904_amd")
 
 
-def _case(dims, ranks, eps, sweep, variant, seed):
+def _case(dims, ranks, eps, sweep, variant, seed, inner="sketch", q=1):
     a, _ = ttgen.gaussian_tt_tensor(dims, ranks if ranks else [6] * (len(dims) - 1), 1e-6, seed)
     A = torch.from_numpy(a).cuda()
-    print(f"noalloc case dims={dims} ranks={ranks} eps={eps} {sweep}/{variant}", flush=True)
-    kw = dict(ranks=ranks, eps=eps, sweep=sweep, variant=variant, q=1, oversample=8, seed=seed)
+    print(f"noalloc case dims={dims} ranks={ranks} eps={eps} {sweep}/{variant} {inner}", flush=True)
+    kw = dict(ranks=ranks, eps=eps, sweep=sweep, variant=variant, q=q, oversample=8, seed=seed, inner=inner)
     flats = T.core_buffers_for(dims, ranks=ranks, eps=eps)
-    need = T.tt_utv_workspace(dims, ranks=ranks, eps=eps, sweep=sweep, variant=variant)
+    need = T.tt_utv_workspace(dims, ranks=ranks, eps=eps, sweep=sweep, variant=variant, inner=inner)
     assert need <= T.TT_NOALLOC_SCRATCH_BYTES
     nc, nrep = T.tt_utv_decompose_noalloc(A, dims, flats, **kw)
     rc, rrep = T.tt_utv_decompose(A, dims, **kw)
@@ -42,6 +42,14 @@ def test_noalloc_matches_workspace_entry_two_calls():
     second = _case([16, 16, 16, 16], None, 1e-6, "L2R", "ULV", 12)
     third = _case([12, 10, 14, 9], [5, 7, 6], None, "R2L", "ULV", 13)
     assert first > second > third
+
+
+def test_noalloc_deflation_inner_kernel_two_calls():
+    """The deflation inner kernel through the same entry point: its streaming
+    passes, their partials and the search state all live in the static scratch."""
+    first = _case([40, 12, 9, 10], [12, 20, 8], None, "L2R", "ULV", 14, inner="deflation", q=2)
+    second = _case([10, 12, 9, 40], None, 1e-4, "R2L", "URV", 15, inner="deflation")
+    assert first > 0 and second > 0
 
 
 def test_noalloc_rejects_beyond_its_scratch():
