@@ -6,12 +6,14 @@
 // such pass (HBM-bound: 4 m n flops on m n elements).
 //
 // Each workgroup owns a contiguous band of rows and holds its share of z in
-// registers: thread t keeps the columns t + 256 u (u < NC), so z needs no
-// reduction inside the band.  A band is read in chunks of RC rows (RC NC = 16
-// elements per thread, one row at least); the chunk's row products y = A x and A w need a sum
-// over the workgroup, done for all 2 RC values together by a halving butterfly
-// (each exchange step halves the values a lane holds) and four wave partials
-// added in a fixed order, so every thread applies the same y.
+// registers: a thread keeps every 256th (four-wave form) or 64th (one-wave
+// form) column, so z needs no reduction inside the band.  A band is read in
+// chunks of RC rows (RC NC = 16 elements per thread, one row at least); the
+// chunk's row products y = A x and A w need a sum over the workgroup, done for
+// all 2 RC values together by a halving butterfly (each exchange step halves
+// the values a lane holds), then, in the four-wave form, the four wave
+// partials added in a fixed order, so every thread applies the same y.  The
+// per-workgroup partials are summed in a fixed order by the reduction kernels.
 #include "tt_internal.h"
 
 namespace ttutv {
