@@ -113,7 +113,9 @@ typedef struct {
  * min(n, m, max_rank or TT_MAX_ELL) vectors.  The vectors are orthonormal, so
  * delta_k^2 = ||C||^2 - ||carry||^2 as with the sketch.  Steps with n <= 64
  * form A^T A in one pass and search on it in one workgroup; wider steps read A
- * once per power step (class "defl_pass", n <= 4096).  FP64 form only; not
+ * once per power step (class "defl_pass", n <= 4096; with a prescribed
+ * accuracy the check applies to the largest n a step can reach, the rank cap
+ * times I_k, so wide modes need max_rank, else TT_EUNSUPPORTED).  FP64 form only; not
  * with Alg. 4 (TT_ULV + TT_R2L) or TT_SVD (TT_EINVAL); report.ell holds the
  * number of vectors kept and report.sweeps 0. */
 typedef enum { TT_INNER_SKETCH = 0, TT_INNER_DEFLATION = 1 } tt_inner;
