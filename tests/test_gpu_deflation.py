@@ -201,3 +201,21 @@ def test_zero_tolerance_runs_to_the_cap():
     assert rep["ranks"] == orep["ranks"] == [1, 6, 6, 1]
     assert not rep["rank_rule_met"]
     _compare(cores, oc, "R2L")
+
+
+@pytest.mark.parametrize("dims,ranks,sweep", [
+    ([1, 7, 1, 9], [1, 1, 1], "L2R"),      # unit extents: one-vector steps on a 1-wide core side
+    ([13, 70], [9], "R2L"),                # d = 2, one column-major streaming step (n = 70)
+    ([70, 13], [9], "L2R"),                # d = 2, one row-major streaming step (n = 70)
+    ([13, 40], [9], "L2R"),                # d = 2, one Gram-mode step (n = 13)
+])
+def test_small_and_degenerate_shapes(dims, ranks, sweep):
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-3, 31)
+    variant = "ULV" if sweep == "L2R" else "URV"
+    print(f"deflation: dims {dims} ranks {ranks} {sweep}", flush=True)
+    cores, rep = _run(a, dims, sweep, variant, q=2, ranks=ranks)
+    oc, orep = oracle.tt_utv(a, dims, ranks=ranks, sweep=sweep, variant=variant, q=2, seed=3, inner="deflation")
+    assert rep["ranks"] == orep["ranks"]
+    _compare(cores, oc, sweep)
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    np.testing.assert_allclose(rec, oracle.tt_reconstruct(oc), rtol=0, atol=TOL * np.max(np.abs(a)))
