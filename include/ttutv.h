@@ -179,6 +179,9 @@ typedef struct {
   tt_kstat kstat[TT_NKCLASS];   /* classes selected by opts.profile */
   int32_t sweeps[TT_MAX_D];     /* Jacobi sweeps of the Rayleigh-Ritz step of unfolding k */
   double rho[TT_MAX_D];         /* mixed forms: ||carry - fl32(carry)||_F of unfolding k */
+  int32_t err_bound_measured;   /* 1: every delta was measured directly (opts.exact_delta)
+                                   and err_bound is a bound; 0: the deltas are the estimates
+                                   sqrt(||C||^2 - ||carry||^2), and so is err_bound */
 } tt_report;
 
 /* Name of kernel class c (0 <= c < TT_NKCLASS), or NULL. */

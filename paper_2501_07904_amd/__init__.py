@@ -60,7 +60,7 @@ class tt_report(ctypes.Structure):
                 ("norm_A", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("rank_rule_met", ctypes.c_int32), ("d", ctypes.c_int32),
                 ("kstat", tt_kstat * TT_NKCLASS), ("sweeps", ctypes.c_int32 * TT_MAX_D),
-                ("rho", ctypes.c_double * TT_MAX_D)]
+                ("rho", ctypes.c_double * TT_MAX_D), ("err_bound_measured", ctypes.c_int32)]
 
 
 _lib = None
@@ -267,6 +267,7 @@ def _report_dict(lib, rep, d, rc, profile):
         "rank_rule_met": bool(rep.rank_rule_met), "status": rc,
         "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
         "rho": [float(rep.rho[k]) for k in range(d - 1)],
+        "err_bound_measured": bool(rep.err_bound_measured),
     }
     if profile:
         report["kstat"] = {lib.tt_kernel_class_name(c).decode(): {
@@ -675,7 +676,8 @@ class Decomposer:
                "normC": [float(rep.normC[k]) for k in range(d - 1)], "norm_A": float(rep.norm_A),
                "err_bound": float(rep.err_bound), "rank_rule_met": bool(rep.rank_rule_met),
                "sweeps": [int(rep.sweeps[k]) for k in range(d - 1)],
-               "rho": [float(rep.rho[k]) for k in range(d - 1)]}
+               "rho": [float(rep.rho[k]) for k in range(d - 1)],
+               "err_bound_measured": bool(rep.err_bound_measured)}
         if self.profile:
             out["kstat"] = {self.lib.tt_kernel_class_name(c).decode(): {
                 "launches": int(rep.kstat[c].launches), "ms": float(rep.kstat[c].ms),

@@ -975,6 +975,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     // factorises by rho_k; the later steps are norm-non-increasing, so the
     // perturbations add to the bound of the exact sweep
     rep->err_bound = (P.alg4 ? sum1 : sqrt(sum2)) + rho_sum;
+    rep->err_bound_measured = P.o.exact_delta ? 1 : 0;
     rep->rank_rule_met = P.fixed ? 1 : (all_sat ? 1 : 0);
   }
   if (!isfinite(nA2)) return fail(TT_ENONFINITE, "input holds non-finite values (||A||^2 = %g)", nA2);

@@ -160,6 +160,10 @@ def test_c1_order4_16(sweep, variant):
     assert rep["err_bound"] == pytest.approx(orep["err_bound"], rel=1e-6)
     # equality for the Pythagorean sweeps; the error itself is formed by cancellation
     assert np.linalg.norm(rec - a) <= rep["err_bound"] * (1 + 1e-6)
+    # measured step errors make the reported bound a bound; the default run says it is an estimate
+    assert rep["err_bound_measured"]
+    _, rep0 = T.tt_utv_decompose(_dev(a), dims, ranks=[4, 6, 4], sweep=sweep, variant=variant, q=1)
+    assert not rep0["err_bound_measured"]
 
 
 @pytest.mark.parametrize("sweep,variant", ALL)
