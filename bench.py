@@ -584,9 +584,31 @@ def main():
                 "note": "pass figures from one extra call with HIP events on every launch"}
         log(f"bench: 32^5 deflation inner kernel: {ms_d:.4f} ms/step, RSE {rse_d:.3e}, {kd['launches']} passes at "
             f"{defl['defl_pass_avg_us']:.1f} us = {defl['defl_pass_GB/s']:.0f} GB/s")
+        # the same tensor and ranks with TT-ULV left to right and with TT-SVD (the configuration's
+        # "TT-SVD vs TT-URV vs TT-ULV", plain FP64 path)
+        others = {}
+        for key, kw in (("ttulv_l2r", dict(decomposer_kw(W2), sweep="L2R", variant="ULV")),
+                        ("ttsvd_r2l", dict(decomposer_kw(W2), variant="SVD"))):
+            do = T.Decomposer(W2["dims"], A2.dtype, **kw)
+            for _ in range(3):
+                do(A2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.c2_steps):
+                do(A2)
+            torch.cuda.synchronize()
+            ms_o = (time.perf_counter() - t0) * 1e3 / args.c2_steps
+            others[key] = {"ms_per_step": round(ms_o, 5), "rse": relative_error(T, do.cores(), A2),
+                           "ranks": do.report()["ranks"]}
+            del do
+        log(f"bench: 32^5 TT-ULV L2R {others['ttulv_l2r']['ms_per_step']:.4f} ms/step (RSE "
+            f"{others['ttulv_l2r']['rse']:.3e}), TT-SVD {others['ttsvd_r2l']['ms_per_step']:.4f} ms/step (RSE "
+            f"{others['ttsvd_r2l']['rse']:.3e})")
         c2 = {"workload": W2["desc"], "value": round(v2, 2), "unit": "GB/s", "ms_per_step": round(tm2["ms"], 5),
               "steps": args.c2_steps, "ranks": c2_ranks, "rse": rse2, "roofline": roof2,
-              "ms_per_step_orth_cholqr": round(ms_q, 5), "deflation": defl}
+              "ms_per_step_orth_cholqr": round(ms_q, 5), "deflation": defl, **others,
+              "ttsvd_note": "TT-SVD: the exact step (ell = n) where the core side is at most 64, else subspace "
+                            "iteration on the leading 64 directions with 30 power steps"}
         log(f"bench: 32^5 FP64 fixed rank: {tm2['ms']:.4f} ms/step, {v2:.1f} GB/s swept, RSE {rse2:.3e}, "
             f"{roof2['kernel']} {roof2['frac']:.1%} of peak, whole step {roof2['step_frac']:.1%}")
         del A2

@@ -54,7 +54,11 @@ typedef enum { TT_L2R = 0, TT_R2L = 1 } tt_sweep;
  * TT_URV + TT_R2L: Alg. 3 and its prescribed-accuracy form (Sec. 3.2).
  * TT_URV + TT_L2R: the index-reversal form (remark after Thm. 3.2).
  * TT_ULV + TT_R2L: Alg. 4 (appendix), carry U^ L11 without the U2 L21 term.
- * TT_SVD: exact truncated SVD of every unfolding (TT-SVD), the ell = n case. */
+ * TT_SVD: truncated SVD of every unfolding (TT-SVD): the exact ell = n case
+ * where the core side n is at most 64; wider core sides take subspace
+ * iteration on the leading 64 directions (30 power steps, then Rayleigh-Ritz:
+ * the leading singular subspace to rounding when s_65 <= 0.54 s_r), ranks up
+ * to 64. */
 typedef enum { TT_ULV = 0, TT_URV = 1, TT_SVD = 2 } tt_variant;
 typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
 

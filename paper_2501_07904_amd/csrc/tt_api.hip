@@ -266,13 +266,22 @@ int step_ell(const Problem& P, const Step& s, int ell_hint) {
   // the deflation search: the fixed rank, or at most TT_MAX_ELL vectors (s.r is
   // the cap in eps mode)
   if (P.defl) return (int)std::min<int64_t>(std::min<int64_t>(s.r, lim), TT_MAX_ELL);
-  if (P.variant == TT_SVD) ell = lim;
+  // TT-SVD: the exact step (ell = n, G = I) up to n = 64; wider core sides take
+  // subspace iteration on the leading 64 directions (kSvdPowerSteps power steps)
+  if (P.variant == TT_SVD) ell = std::min<int64_t>(lim, TT_MAX_ELL);
   else if (P.fixed) ell = std::min<int64_t>((int64_t)s.r + P.o.oversample, lim);
   else ell = std::min<int64_t>(ell_hint, lim);
   return (int)ell;
 }
 
 bool step_gram(const Problem& P, const Step& s) { return !P.alg4 && s.n <= kGramMax; }
+
+// Power steps of a TT-SVD step whose core side exceeds 64: subspace iteration
+// with ell = 64 columns converges to the leading singular subspace by a factor
+// (s_65 / s_r)^2 per step, so 30 steps fix it to rounding when s_65 <= 0.54 s_r.
+constexpr int kSvdPowerSteps = 30;
+
+int power_steps(const Problem& P) { return P.variant == TT_SVD ? kSvdPowerSteps : P.o.q; }
 
 // ---- workspace layout ------------------------------------------------------
 struct Work {
@@ -385,6 +394,8 @@ size_t layout_work(const Sizes& z, int d, char* base, Work* w) {
 
 int check_limits(const Problem& P, const std::vector<Step>& S) {
   for (const Step& s : S) {
+    if (P.variant == TT_SVD && P.fixed && s.r > TT_MAX_ELL)
+      return fail(TT_EUNSUPPORTED, "TT-SVD step for core %d asks for rank %d > %d", s.core, s.r, TT_MAX_ELL);
     if (P.defl) {
       if (P.fixed && s.r > TT_MAX_ELL)
         return fail(TT_EUNSUPPORTED, "step for core %d asks for rank %d > %d", s.core, s.r, TT_MAX_ELL);
@@ -487,7 +498,8 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
     const double mc = (double)m * c;
     const bool have_y = sketch_ready && !retry;
     if (!have_y) LAUNCH(PF, KC_SMALL, 0, 0, launch_gen_sketch(W.X, a, st));
-    for (int it = 0; it <= P.o.q; ++it) {
+    const int qp = power_steps(P);
+    for (int it = 0; it <= qp; ++it) {
       if (P.mixed) {
         // mixed precision: power products on FP32 (or BF16) operands with FP32
         // accumulation, FP32 iterate
@@ -526,7 +538,7 @@ int run_step(const Problem& P, const Step& s, int ell, int si, bool first, const
           LAUNCH(PF, KC_REDUCE, (double)(nch + 1) * n * c * 8, (double)nch * n * c,
                  launch_reduce(W.part, nch, (int64_t)n * c, W.M, nullptr, st));
       }
-      LAUNCH(PF, KC_SMALL, 0, 0, orth_iterate(P, it < P.o.q, W.M, W.X, n, c, W, st));
+      LAUNCH(PF, KC_SMALL, 0, 0, orth_iterate(P, it < qp, W.M, W.X, n, c, W, st));
     }
     // Rayleigh-Ritz: Y = A X, K = Y^T Y
     // the Rayleigh-Ritz pass keeps Y in FP64 (its Gram decides the rank); in the

@@ -318,3 +318,14 @@ def test_deflation_option_on_host(lib):
     assert "inner" in lib.tt_last_error().decode()
     assert lib.tt_kernel_class_name(8).decode() == "defl_pass"
     assert lib.tt_kernel_class_name(T.TT_NKCLASS) is None
+
+
+def test_ttsvd_core_side_beyond_64_on_host(lib):
+    """TT-SVD on core sides above 64 (subspace iteration on the leading 64
+    directions): accepted up to rank 64, refused above (TT_EUNSUPPORTED)."""
+    rc, nb = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=1, variant=2)
+    assert rc == T.TT_OK and nb > 0
+    rc, _ = _ws(lib, [32] * 5, [1, 16, 16, 16, 16, 1], sweep=0, variant=2)
+    assert rc == T.TT_OK
+    rc, _ = _ws(lib, [32] * 5, [1, 70, 70, 70, 70, 1], sweep=1, variant=2)
+    assert rc == T.TT_EUNSUPPORTED and "rank" in lib.tt_last_error().decode()
