@@ -183,6 +183,8 @@ EXAMPLE_FORMS = (("R2L", "URV"), ("L2R", "ULV"))
 # steps per vector; with a prescribed accuracy the rank cap 24 keeps every core side within the 4096 its
 # streaming pass takes (24 x 160)
 DEFL_KW = dict(sweep="L2R", variant="ULV", inner="deflation", q=2)
+# TT-SVD, the paper's baseline, left to right (core sides above 64 by subspace iteration on 64 directions)
+SVD_KW = dict(sweep="L2R", variant="SVD")
 DEFL_EPS_MAX_RANK = 24
 
 
@@ -229,6 +231,7 @@ def paper_examples(T, reps):
             row[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[20] * 3, sweep=sweep, variant=variant, q=1,
                                                           oversample=8, seed=1))
         row["ULV_L2R_deflation"] = run(A, dims, dict(ranks=[20] * 3, seed=1, **DEFL_KW))
+        row["SVD_L2R"] = run(A, dims, dict(ranks=[20] * 3, seed=1, **SVD_KW))
         log(f"bench: example 1 SNR {snr:2d} dB, ranks 20: " + ", ".join(
             f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in row.items() if isinstance(v, dict)))
         ex1["snr_sweep"].append(row)
@@ -239,6 +242,7 @@ def paper_examples(T, reps):
                     rrow[f"{variant}_{sweep}"] = run(A, dims, dict(ranks=[r] * 3, sweep=sweep, variant=variant,
                                                                    q=1, oversample=8, seed=1))
                 rrow["ULV_L2R_deflation"] = run(A, dims, dict(ranks=[r] * 3, seed=1, **DEFL_KW))
+                rrow["SVD_L2R"] = run(A, dims, dict(ranks=[r] * 3, seed=1, **SVD_KW))
                 log(f"bench: example 1 SNR 30 dB, ranks {r:2d}: " + ", ".join(
                     f"{k} {v['ms']:.2f} ms RSE {v['rse']:.4e}" for k, v in rrow.items() if isinstance(v, dict)))
                 ex1["rank_sweep"].append(rrow)
@@ -256,6 +260,7 @@ def paper_examples(T, reps):
             row[f"{variant}_{sweep}"] = run(B, dims, dict(eps=eps, sweep=sweep, variant=variant, q=1, oversample=8,
                                                           seed=2))
         row["ULV_L2R_deflation"] = run(B, dims, dict(eps=eps, seed=2, max_rank=DEFL_EPS_MAX_RANK, **DEFL_KW))
+        row["SVD_L2R"] = run(B, dims, dict(eps=eps, seed=2, **SVD_KW))
         log(f"bench: example 2 eps {eps:g}: TT-SVD (paper) {svd_ranks}, " + ", ".join(
             f"{k} ranks {v['ranks']} {v['ms']:.2f} ms RSE {v['rse']:.3e}" for k, v in row.items()
             if isinstance(v, dict)))

@@ -76,6 +76,24 @@ def test_example2_table_beps_ranks(tensor_b, sweep, variant):
         assert err <= rep["err_bound"] * (1 + 1e-6)
 
 
+def test_example2_table_beps_ttsvd_and_deflation_on_device(tensor_b):
+    """Table "Beps" again, for the device TT-SVD (core side 160 > 64: subspace
+    iteration on 64 directions) and for TT-ULV with the deflation inner kernel
+    (q = 2, rank cap 24): both return exactly the TT-SVD ranks the table prints,
+    with the error below eps.  (The table's USV-plus column has (6,7,6) at
+    1e-5; the kept-energy reading of its stopping rule gives TT-SVD's (7,7,6).)"""
+    dims = [160] * 4
+    norm_b = float(torch.linalg.vector_norm(tensor_b))
+    for eps, svd_ranks in _table_rows():
+        for kw in (dict(variant="SVD"), dict(variant="ULV", inner="deflation", q=2, max_rank=24)):
+            cores, rep = T.tt_utv_decompose(tensor_b, dims, eps=eps, sweep="L2R", **kw)
+            assert rep["ranks"] == [1] + svd_ranks + [1], (eps, kw, rep["ranks"])
+            rec = T.tt_reconstruct(cores)
+            err = float(torch.linalg.vector_norm(rec - tensor_b))
+            del rec
+            assert err <= eps * norm_b, (eps, kw)
+
+
 @pytest.mark.parametrize("snr_db", [0, 10, 20, 30])
 def test_example1_fixed_ranks_noise_floor(snr_db):
     """Example 1: 160^4 from Gaussian TT cores of ranks (20, 20, 20) plus noise
