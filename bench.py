@@ -81,7 +81,8 @@ def stated_bound(T, dims, A, kw, dec):
 
 def contractions(T, cores, reps=10):
     """The train contractions on the device: reconstruction of the decomposed
-    32^5 train (268 MB of FP64 written, an HBM-write-bound pass), and sampling
+    32^5 train (268 MB of FP64 written, an HBM-write-bound pass), its backward
+    for a dense upstream gradient (268 MB read twice), and sampling
     and its backward on a (16,16,16,16,16,10) train of ranks 16 and 10 at the
     3,145,728 entries of a 30% mask (the MRI-volume completion shape), each
     timed with events over `reps` calls after one untimed call.  Returns the
@@ -112,6 +113,18 @@ def contractions(T, cores, reps=10):
                           "ms": round(ms, 4), "GB/s written": round(gbs, 1),
                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     log(f"bench: reconstruct 32^5 FP64: {ms:.4f} ms, {gbs:.1f} GB/s written ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+
+    # the backward of the reconstruction: a dense FP64 upstream gradient of the
+    # same 32^5 shape, read twice (one pass against each half of the train),
+    # then the chain rule through the small partial products
+    gdense = torch.randn(total, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(13))
+    ms = timed(lambda: T.tt_reconstruct_backward(cores, gdense))
+    gbs = 2 * total * 8 / (ms * 1e-3) / 1e9
+    out["reconstruct_backward"] = {"workload": "32^5 train, ranks 16, dense FP64 upstream gradient (268 MB, read twice)",
+                                   "ms": round(ms, 4), "GB/s read": round(gbs, 1),
+                                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"bench: reconstruct backward 32^5 FP64: {ms:.4f} ms, {gbs:.1f} GB/s read ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    del gdense
 
     dims = [16, 16, 16, 16, 16, 10]
     ranks = [1, 16, 16, 16, 16, 10, 1]

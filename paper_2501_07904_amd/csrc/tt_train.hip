@@ -659,9 +659,14 @@ hipError_t launch_gemm_smallk(const double* A, const double* B, void* C, int c_f
 }
 
 int gemm_any_splits(int64_t M, int64_t N, int64_t K) {
+  // a workgroup's k loop is a chain of dependent load / barrier / FMA rounds
+  // (kGaKT of k each), so on the narrow outputs of a train's chain rule
+  // (M or N a rank) its length, not the arithmetic, sets the time: one round
+  // per workgroup where the partials (s M N doubles, summed afterwards) stay
+  // within 2^21 doubles and the workgroups within 4096
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  int64_t s = (K + 255) / 256;                 // at least 256 of k per workgroup
-  const int64_t cap = std::max<int64_t>(1, 1024 / tiles);
+  int64_t s = (K + kGaKT - 1) / kGaKT;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(4096 / tiles, ((int64_t)1 << 21) / (M * N)));
   if (s > cap) s = cap;
   if (s > 4096) s = 4096;
   return (int)std::max<int64_t>(s, 1);
