@@ -3,9 +3,11 @@ reading of the paper's fastest TT-ULV variant, Sec. 3.3 / Sec. 4) through the
 C ABI against the FP64 oracle: fixed ranks at 1e-10 on cores, reconstruction
 and step errors, in Gram mode (core side n <= 64: A^T A in one pass, the search
 in one workgroup) and in the streaming mode (one pass over A per power step)
-for every register width of its pass kernel (n up to 256, 512, 1024, 2048,
-4096), both storage orders, FP32 input, q = 1..3; prescribed accuracy with the
-oracle's ranks; the 32^5 workload in full."""
+for every form of its pass kernel (one wave per workgroup up to n = 128
+column-major and 512 row-major, then four waves with 1, 2, 4, 8 or 16
+register columns up to n = 4096), each at its width limits, both storage
+orders, FP32 input, q = 1..3; prescribed accuracy with the oracle's ranks; the
+32^5 workload in full."""
 import numpy as np
 import pytest
 import torch
@@ -78,6 +80,15 @@ CASES = [
     ([12, 120, 30], [10, 30], [10, 30], "R2L"),          # n = 3600: sixteen register columns
     ([30, 120, 12], [25, 10], [25, 10], "L2R"),          # n = 3000 row-major
     ([11, 13, 9, 5], [4, 7, 3], [4, 7, 3], "L2R"),       # every step in Gram mode
+    # the pass kernel's forms at their width limits: column-major one-wave up to n = 128, then four-wave
+    # with 1 (n <= 256), 2, 4, 8 (n <= 2048) register columns; row-major one-wave up to 512, then four-wave
+    ([40, 8, 16], [12, 16], [12, 16], "R2L"),            # n = 128: the widest column-major one-wave pass
+    ([40, 43, 9], [10, 3], [10, 3], "R2L"),              # n = 129: column-major four-wave, one register column
+    ([40, 16, 20], [12, 16], [12, 16], "R2L"),           # n = 256: the same at its width limit
+    ([30, 55, 20], [12, 20], [12, 20], "R2L"),           # n = 1100: eight register columns
+    ([40, 32, 30], [16, 12], [16, 12], "L2R"),           # n = 512: the widest row-major one-wave pass
+    ([30, 27, 25], [19, 10], [19, 10], "L2R"),           # n = 513: row-major four-wave, four register columns
+    ([50, 55, 24], [20, 12], [20, 12], "L2R"),           # n = 1100 row-major: eight register columns
 ]
 
 
