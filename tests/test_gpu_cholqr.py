@@ -4,7 +4,8 @@ both orthonormalise the same span, and the Rayleigh-Ritz step that fixes the
 cores does not depend on the basis, so the cores agree to FP64 parity (1e-10
 relative, with the bond sign gauge aligned).  Shapes: the 16^4 workload with
 q = 2 (two intermediate iterates), iterates too tall for one workgroup's
-Householder QR (1,280 x 40 on the 40^3 x 32 sweep), the fused-mixed form,
+Householder QR (1,280 x 40 on the 40^3 x 32 sweep), the 32^5 workload
+(512 x 24 iterates), the fused-mixed form,
 Alg. 4, prescribed accuracy, and an exact-rank input whose sketch is
 rank-deficient (the shift keeps the first Cholesky factor positive definite)."""
 import numpy as np
@@ -51,6 +52,16 @@ def test_cholqr_tall_iterate(sweep, variant):
     oc, orep = oracle.tt_utv(a, dims, ranks=ranks, sweep=sweep, variant=variant, q=1, p=8, seed=0)
     assert r1["ranks"] == orep["ranks"]
     _compare(c1, oc, sweep)
+
+
+def test_cholqr_c2_shape():
+    """The 32^5 workload (ranks 16, q = 2): 512 x 24 intermediate iterates."""
+    dims, ranks = [32] * 5, [16] * 4
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, 0)
+    c1, r1, _, _ = _both(a, dims, "R2L", "URV", ranks=ranks, q=2, oversample=8)
+    oc, orep = oracle.tt_utv(a, dims, ranks=ranks, sweep="R2L", variant="URV", q=2, p=8, seed=0)
+    assert r1["ranks"] == orep["ranks"]
+    _compare(c1, oc, "R2L")
 
 
 def test_cholqr_prescribed_accuracy_and_mixed():
