@@ -1,7 +1,8 @@
 """TT-SVD through the C ABI against the oracle's TT-SVD (LAPACK SVD of every
 unfolding) on core sides above 64, where the library runs subspace iteration on
 the leading 64 directions (30 power steps): the 32^5 FP64 workload at fixed rank
-16 in both sweep directions, ragged shapes and a prescribed accuracy.  Cores at
+16 in both sweep directions, ragged shapes, a prescribed accuracy, and the
+steps on either side of the switch (core sides 64 and 65).  Cores at
 1e-10 where the singular values are well separated, the reconstruction and the
 step errors always."""
 import numpy as np
@@ -83,3 +84,21 @@ def test_ragged_and_prescribed_accuracy(sweep):
     rec = T.tt_reconstruct(cores).cpu().numpy()
     np.testing.assert_allclose(rec, oracle.tt_reconstruct(oc), rtol=0, atol=TOL * np.max(np.abs(a)))
     assert np.linalg.norm(rec - a) <= 1e-3 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("sweep", ["L2R", "R2L"])
+def test_exact_and_subspace_steps_at_the_boundary(sweep):
+    """Consecutive steps on either side of the switch: core side 64 (the exact
+    step, l = n with G = I, in Gram mode) and 65 (subspace iteration on 64
+    directions, m = 100 rows on the long side)."""
+    dims, ranks = [8, 8, 13, 100], [8, 5, 10]
+    if sweep == "R2L":
+        dims, ranks = dims[::-1], ranks[::-1]
+    print(f"tt-svd boundary {dims} {ranks} {sweep}", flush=True)
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-4, 9)
+    cores, rep = T.tt_utv_decompose(_dev(a), dims, ranks=ranks, sweep=sweep, variant="SVD")
+    torch.cuda.synchronize()
+    oc, orep = oracle.tt_svd(a, dims, ranks=ranks, sweep=sweep)
+    _check(a, dims, cores, rep, oc, orep, sweep)
+    # the sketch widths per bond: n on the exact steps (8 and 64), 64 on the wide one
+    assert rep["ell"] == ([8, 64, 64] if sweep == "L2R" else [64, 64, 8])
