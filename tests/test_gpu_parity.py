@@ -167,6 +167,26 @@ def test_c1_order4_16(sweep, variant):
 
 
 @pytest.mark.parametrize("sweep,variant", ALL)
+def test_gram_and_sketched_steps_at_the_switch(sweep, variant):
+    """Consecutive steps with core sides 64 (the largest Gram-mode step: A^T A
+    in one pass and the solve in one workgroup) and 65 (the smallest sketched
+    step, l = 18)."""
+    dims, ranks = [8, 8, 13, 100], [8, 5, 10]
+    if sweep == "R2L":
+        dims, ranks = dims[::-1], ranks[::-1]
+    print(f"gram/sketch switch {dims} {ranks} {sweep}/{variant}", flush=True)
+    a, _ = ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, 110)
+    cores, rep, oc, orep = _run(a, dims, sweep, variant, ranks=ranks, q=1, exact_delta=True)
+    assert rep["ranks"] == orep["ranks"]
+    assert rep["ell"] == [int(x) for x in orep["ell"]]
+    _compare(cores, oc, sweep)
+    rec = T.tt_reconstruct(cores).cpu().numpy()
+    np.testing.assert_allclose(rec, oracle.tt_reconstruct(oc), rtol=0, atol=TOL * np.max(np.abs(a)))
+    # the step whose rank equals its core side (8) truncates nothing: its error is rounding on both sides
+    np.testing.assert_allclose(rep["delta"], orep["delta"], rtol=1e-6, atol=TOL * orep["norm_A"])
+
+
+@pytest.mark.parametrize("sweep,variant", ALL)
 def test_ragged_shapes(sweep, variant):
     """Extents and ranks that are not multiples of any tile; a step with n > 64
     (the sketched path) and one with m < n."""
