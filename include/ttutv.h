@@ -221,9 +221,11 @@ int tt_utv_core_capacity(int d, const int64_t* dims, const int64_t* ranks, doubl
  *             doubles (see tt_utv_core_capacity), layout above.
  *  rep        host, filled on TT_OK and TT_ERANK (may be NULL).
  *  stream     hipStream_t or NULL.
- * With fixed ranks the call only enqueues work and synchronises the stream
- * once at the end to fill the report; with eps it synchronises after every
- * step to size the next one. */
+ * With fixed ranks the call synchronises the stream twice: after the first
+ * pass over A (a non-finite input stops the sweep there with TT_ENONFINITE)
+ * and at the end, to fill the report; with eps it also synchronises after
+ * every step to size the next one (and, with the deflation inner kernel,
+ * after every vector of a streaming step). */
 int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
                      const int64_t* ranks, double eps, tt_sweep sweep, tt_variant variant,
                      const tt_opts* opts, void* work, size_t work_bytes,
@@ -239,7 +241,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
  * holds until the process ends; a problem whose tt_utv_workspace exceeds it
  * returns TT_ENOSPC before any work is enqueued.  opts.profile must be 0 (it
  * would create HIP events).  Otherwise arguments, results, report and
- * synchronisation are those of tt_utv_decompose, whose kernels it runs;
+ * synchronisation are those of tt_utv_decompose, whose kernels it runs (so
+ * the call itself waits on the stream and cannot be recorded into a graph);
  * nothing in the scratch needs to start cleared.  All calls on one device
  * share its scratch: calls that overlap in time on one device (other host
  * threads, or other streams before this call's work has finished) race and
