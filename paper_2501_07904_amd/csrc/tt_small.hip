@@ -1173,18 +1173,36 @@ __global__ __launch_bounds__(kThreads) void k_defl_gram(const double* __restrict
 }
 
 // ---- tall mode: V (n x cap) and x in global memory, n <= 4096 -------------
-// z <- z - V (V^T z) over the first j columns (z in LDS), two rounds.
+// z <- z - V (V^T z) over the first j columns (z in LDS), two rounds: the
+// coefficient of column l is one wave's sum, then thread i updates rows i,
+// i + kThreads, ...  Up to n = 1024 a lane's loads go four at a time.  Wider
+// vectors issue every load of a batch before the first use (16 rows of a
+// column per lane, 16 columns of a row per thread; indices past n or j
+// clamped and their values masked), so that the dependent memory round trips
+// per round fall from about n/256 + 4 ceil(j/4) to n/1024 + 4 ceil(j/16).
 __device__ __forceinline__ void defl_project_global(double* z, const double* V, int n, int j, double* cbuf) {
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const bool wide = n > kThreads;
   for (int round = 0; round < 2 && j > 0; ++round) {
     for (int l = wv; l < j; l += kThreads / 64) {
       const double* v = V + (int64_t)l * n;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i0 = lane; i0 < n; i0 += 256) {
+      if (wide) {
+        for (int i0 = lane; i0 < n; i0 += 64 * 16) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 64 * u;
-          if (i < n) acc[u] = fma(v[i], z[i], acc[u]);
+          for (int u = 0; u < 16; ++u) {
+            const int i = i0 + 64 * u;
+            const int ic = i < n ? i : n - 1;
+            acc[u & 3] = fma(v[ic], i < n ? z[ic] : 0.0, acc[u & 3]);
+          }
+        }
+      } else {
+        for (int i0 = lane; i0 < n; i0 += 256) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < n) acc[u] = fma(v[i], z[i], acc[u]);
+          }
         }
       }
       const double c = group_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), 64);
@@ -1193,12 +1211,23 @@ __device__ __forceinline__ void defl_project_global(double* z, const double* V, 
     __syncthreads();
     for (int i = t; i < n; i += kThreads) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      int l = 0;
-      for (; l + 4 <= j; l += 4) {
+      if (wide) {
+        for (int l0 = 0; l0 < j; l0 += 16) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = fma(V[i + (int64_t)(l + u) * n], cbuf[l + u], acc[u]);
+          for (int u = 0; u < 16; ++u) {
+            const int l = l0 + u;
+            const int lc = l < j ? l : j - 1;
+            acc[u & 3] = fma(V[i + (int64_t)lc * n], l < j ? cbuf[lc] : 0.0, acc[u & 3]);
+          }
+        }
+      } else {
+        int l = 0;
+        for (; l + 4 <= j; l += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] = fma(V[i + (int64_t)(l + u) * n], cbuf[l + u], acc[u]);
+        }
+        for (; l < j; ++l) acc[0] = fma(V[i + (int64_t)l * n], cbuf[l], acc[0]);
       }
-      for (; l < j; ++l) acc[0] = fma(V[i + (int64_t)l * n], cbuf[l], acc[0]);
       z[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
     __syncthreads();
