@@ -225,7 +225,10 @@ int tt_utv_core_capacity(int d, const int64_t* dims, const int64_t* ranks, doubl
  * pass over A (a non-finite input stops the sweep there with TT_ENONFINITE)
  * and at the end, to fill the report; with eps it also synchronises after
  * every step to size the next one (and, with the deflation inner kernel,
- * after every vector of a streaming step). */
+ * after every vector of a streaming step).  With fixed ranks, rep == NULL and
+ * opts.profile = 0 it only enqueues kernels on the stream and never waits on
+ * it, so the call can be recorded into a HIP graph; a non-finite input is
+ * then not reported and leaves non-finite cores. */
 int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
                      const int64_t* ranks, double eps, tt_sweep sweep, tt_variant variant,
                      const tt_opts* opts, void* work, size_t work_bytes,
@@ -242,7 +245,8 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims,
  * returns TT_ENOSPC before any work is enqueued.  opts.profile must be 0 (it
  * would create HIP events).  Otherwise arguments, results, report and
  * synchronisation are those of tt_utv_decompose, whose kernels it runs (so
- * the call itself waits on the stream and cannot be recorded into a graph);
+ * only a fixed-rank call with rep == NULL can be recorded into a graph, after
+ * a first call on the device has looked up the scratch);
  * nothing in the scratch needs to start cleared.  All calls on one device
  * share its scratch: calls that overlap in time on one device (other host
  * threads, or other streams before this call's work has finished) race and

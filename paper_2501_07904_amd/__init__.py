@@ -321,13 +321,19 @@ def tt_utv_decompose(A, dims, ranks=None, eps=None, sweep="L2R", variant="ULV", 
 def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L2R", variant="ULV", q=1,
                              oversample=8, seed=0, max_rank=0, exact_delta=False, weights=None, stream=None,
                              allow_rank_miss=False, prec="fp64", fuse_ata=False, orth="householder",
-                             separate_sketch=False, inner="sketch"):
+                             separate_sketch=False, inner="sketch", report=True):
     """tt_utv_decompose on the library's static device scratch (no workspace
     argument): for problems whose workspace fits TT_NOALLOC_SCRATCH_BYTES.
     core_flats: caller-allocated flat float64 device buffers, one per core, at
     least tt_utv_core_capacity long (core_buffers_for); the call allocates no
-    device memory.  Returns (cores, report) with cores viewing core_flats."""
+    device memory.  Returns (cores, report) with cores viewing core_flats.
+    report=False (fixed ranks only) passes no report: the call then only
+    enqueues kernels and never waits on the stream, so it can be recorded into
+    a graph (after a first call on the device), and returns (cores, None), the
+    ranks taken from the host-side capacity query."""
     lib = load_library()
+    if not report and ranks is None:
+        raise ValueError("report=False needs fixed ranks (a prescribed accuracy reads each step's rank back)")
     dims, o, _keep, rk, epsv = _decompose_args(A, dims, ranks, eps, q, oversample, seed, max_rank, exact_delta,
                                                weights, False, prec, fuse_ata, orth, separate_sketch, inner)
     d = len(dims)
@@ -338,14 +344,20 @@ def tt_utv_decompose_noalloc(A, dims, core_flats, ranks=None, eps=None, sweep="L
     for k, f in enumerate(core_flats):
         if not (f.is_cuda and f.dtype == torch.float64 and f.is_contiguous()) or f.numel() < int(cap[k]):
             raise ValueError(f"core buffer {k} must be a contiguous float64 device tensor of >= {int(cap[k])} entries")
-    rep = tt_report()
+    rep = tt_report() if report else None
     rc = lib.tt_utv_decompose_noalloc(ctypes.c_void_p(A.data_ptr()), DTYPES[A.dtype], d, _i64(dims), rk, epsv,
                                       SWEEPS[sweep], VARIANTS[variant], ctypes.byref(o), _ptrs(core_flats),
-                                      ctypes.byref(rep), _stream(stream))
+                                      ctypes.byref(rep) if report else None, _stream(stream))
     _check(rc, allow=(TT_ERANK,) if allow_rank_miss else ())
-    r = [int(rep.ranks[k]) for k in range(d + 1)]
+    if report:
+        r = [int(rep.ranks[k]) for k in range(d + 1)]
+    else:
+        # with fixed ranks the capacity of core k is exactly r_{k-1} I_k r_k
+        r = [1]
+        for k in range(d):
+            r.append(int(cap[k]) // (r[k] * dims[k]))
     cores = [_core_view(core_flats[k], r[k], dims[k], r[k + 1]) for k in range(d)]
-    return cores, _report_dict(lib, rep, d, rc, False)
+    return cores, (_report_dict(lib, rep, d, rc, False) if report else None)
 
 
 def _core_buffers(cores):

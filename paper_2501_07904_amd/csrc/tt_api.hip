@@ -822,6 +822,10 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
   PF.on = P.o.profile != 0;
   PF.mask = P.o.profile;
   PF.st = st;
+  // fixed ranks and no report: the call only enqueues kernels and never waits
+  // on the stream (so it can be recorded into a graph); a non-finite input is
+  // then not caught after the first pass and leaves non-finite cores
+  const bool enqueue_only = P.fixed && !rep && !PF.on;
 
   const int nsteps = d - 1;
   int64_t r_run[TT_MAX_D + 1];
@@ -859,7 +863,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
       if (rc) return rc;
       // ||A||^2 is known after the first pass over A: a non-finite input stops
       // the sweep here instead of running every step on NaNs
-      if (first && !retry) {
+      if (first && !retry && !enqueue_only) {
         double nA2_first = 0.0;
         HIP_OK(hipMemcpyAsync(&nA2_first, W.normA2, sizeof(double), hipMemcpyDeviceToHost, st));
         if (!P.fixed) HIP_OK(hipMemcpyAsync(&host[si], W.recs + si, sizeof(StepRec), hipMemcpyDeviceToHost, st));
@@ -928,6 +932,7 @@ int tt_utv_decompose(const void* A, tt_dtype dtype, int d, const int64_t* dims, 
     curA = io.out;
     a_f32 = io.out_f32;
   }
+  if (enqueue_only) return TT_OK;
   HIP_OK(hipMemcpyAsync(host.data(), W.recs, sizeof(StepRec) * nsteps, hipMemcpyDeviceToHost, st));
   double nA2 = 0.0;
   HIP_OK(hipMemcpyAsync(&nA2, W.normA2, sizeof(double), hipMemcpyDeviceToHost, st));

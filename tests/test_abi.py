@@ -329,3 +329,10 @@ def test_ttsvd_core_side_beyond_64_on_host(lib):
     assert rc == T.TT_OK
     rc, _ = _ws(lib, [32] * 5, [1, 70, 70, 70, 70, 1], sweep=1, variant=2)
     assert rc == T.TT_EUNSUPPORTED and "rank" in lib.tt_last_error().decode()
+
+
+def test_noalloc_without_report_needs_fixed_ranks():
+    """The enqueue-only form (no report) exists for fixed ranks alone: a
+    prescribed accuracy reads every step's rank back to the host."""
+    with pytest.raises(ValueError, match="report=False needs fixed ranks"):
+        T.tt_utv_decompose_noalloc(None, [2, 2], [], eps=0.1, report=False)

@@ -3,7 +3,8 @@ workspace in the library's static device scratch) against tt_utv_decompose
 with a caller workspace: the same kernels on the same input, so cores and
 report must agree exactly.  Two calls in a row, the second on a smaller
 problem with a different scratch layout, so a stale scratch from the first
-call would show."""
+call would show.  With fixed ranks and no report the call only enqueues
+kernels, and is recorded into a HIP graph and replayed."""
 import numpy as np
 import pytest
 import torch
@@ -58,3 +59,42 @@ def test_noalloc_rejects_beyond_its_scratch():
     flats = T.core_buffers_for(dims, ranks=[16] * 4)
     with pytest.raises(T.TTError, match="static scratch"):
         T.tt_utv_decompose_noalloc(A, dims, flats, ranks=[16] * 4, sweep="R2L", variant="URV")
+
+
+@pytest.mark.parametrize("sweep,variant,inner,q", [("R2L", "URV", "sketch", 1), ("L2R", "ULV", "sketch", 2),
+                                                   ("L2R", "ULV", "deflation", 2)])
+def test_noalloc_fixed_rank_call_recorded_in_a_graph(sweep, variant, inner, q):
+    """A graph recorded from one call with fixed ranks and no report, replayed
+    on new contents of the same input buffer (eager copies and
+    synchronisations between the replays), gives every time exactly the cores
+    an eager call gives on that input."""
+    dims, ranks = [16, 12, 14, 10], [4, 6, 5]
+    kw = dict(ranks=ranks, sweep=sweep, variant=variant, q=q, oversample=8, seed=21, inner=inner)
+    print(f"graph capture {dims} {ranks} {sweep}/{variant} {inner} q={q}", flush=True)
+    inputs = [torch.from_numpy(ttgen.gaussian_tt_tensor(dims, ranks, 1e-6, s)[0]).cuda() for s in (21, 22)]
+    ref_flats = T.core_buffers_for(dims, ranks=ranks)
+    want = []
+    for x in inputs:   # eager, with a report (the first call also looks up the scratch on this device)
+        cores, rep = T.tt_utv_decompose_noalloc(x, dims, ref_flats, **kw)
+        assert rep["ranks"] == [1] + ranks + [1]
+        want.append([c.clone() for c in cores])
+    A = inputs[0].clone()
+    flats = T.core_buffers_for(dims, ranks=ranks)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cores, rep = T.tt_utv_decompose_noalloc(A, dims, flats, report=False, **kw)
+    assert rep is None
+    assert [tuple(c.shape) for c in cores] == [tuple(c.shape) for c in want[0]]
+    for i in (1, 0, 1, 0):
+        A.copy_(inputs[i])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (x, y) in enumerate(zip(cores, want[i])):
+            assert torch.equal(x, y), f"replay on input {i}: core {k + 1} differs"
+    # an eager call with a report on the same scratch after the replays
+    cores, rep = T.tt_utv_decompose_noalloc(inputs[1], dims, ref_flats, **kw)
+    torch.cuda.synchronize()
+    for x, y in zip(cores, want[1]):
+        assert torch.equal(x, y)
