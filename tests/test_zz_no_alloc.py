@@ -62,7 +62,7 @@ def test_noalloc_rejects_beyond_its_scratch():
 
 
 @pytest.mark.parametrize("sweep,variant,inner,q", [("R2L", "URV", "sketch", 1), ("L2R", "ULV", "sketch", 2),
-                                                   ("L2R", "ULV", "deflation", 2)])
+                                                   ("L2R", "ULV", "deflation", 2), ("R2L", "SVD", "sketch", 1)])
 def test_noalloc_fixed_rank_call_recorded_in_a_graph(sweep, variant, inner, q):
     """A graph recorded from one call with fixed ranks and no report, replayed
     on new contents of the same input buffer (eager copies and
